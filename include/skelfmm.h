@@ -1,0 +1,165 @@
+/*
+ * skelfmm -- fast summation u = A q, A_ij = G(x_i, x_j) (i != j), A_ii = 0,
+ * by the neighbor-list skeletonization FMM of Yesypenko, Chen & Martinsson
+ * (arXiv 2310.16668).  Plain C boundary: no C++ type and no torch type crosses it.
+ *
+ * Operations and where the paper defines them:
+ *   skelfmm_build          the precomputation: adaptive tree with 2:1 balance
+ *                          (section 3, "Adaptive tree data structure") and strong
+ *                          recursive skeletonization with proxy-surface interpolative
+ *                          decompositions (section 2.1, equation (5); section 3,
+ *                          "Build stage", Algorithm "Strong recursive skeletonization").
+ *                          Host code, float64.
+ *   skelfmm_apply          u = Atilde q, the FMM apply (section 3, "FMM apply",
+ *                          equations (15)-(20) and Algorithm "FMM apply"): upward pass,
+ *                          ifo / ifs / tfo translations, top-level direct sum, downward
+ *                          pass.  Runs on the GPU.
+ *   skelfmm_apply_adjoint  w = Atilde^H v, the transposed sweep (not in the paper):
+ *                          transposed downward pass first, conjugated translations,
+ *                          transposed upward pass last.  Runs on the GPU.
+ *
+ * Conventions shared by every call:
+ *   - Status codes: SKELFMM_OK on success; a negative code otherwise, with a
+ *     message from skelfmm_last_error() (thread-local, valid until the next failing
+ *     call on the same thread).  Argument errors return before any GPU work and leave
+ *     outputs untouched.  Device errors surface as SKELFMM_EDEVICE from the failing
+ *     call or the next one.  No C++ exception crosses this boundary.
+ *   - Vectors q, u, v, w are caller-owned DEVICE buffers in the caller's point
+ *     order, n x nrhs row-major (the nrhs values of one point contiguous); complex
+ *     values are interleaved (re, im).  Outputs are overwritten, never accumulated.
+ *   - An operator may run on one HIP stream at a time: its workspace lives inside it.
+ *     All GPU work of apply / apply_adjoint is enqueued asynchronously on `hip_stream`
+ *     (NULL = the default stream); they neither allocate nor synchronize once
+ *     skelfmm_prepare has sized the workspace for that nrhs and dtype.
+ */
+#ifndef SKELFMM_H
+#define SKELFMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct skelfmm_op skelfmm_op;        /* opaque; owned by the library */
+typedef struct skelfmm_batch skelfmm_batch;  /* opaque; owned by the library */
+
+typedef enum {
+    SKELFMM_OK = 0,
+    SKELFMM_EINVAL = -1,     /* invalid argument */
+    SKELFMM_ENOMEM = -2,     /* host or device allocation failed */
+    SKELFMM_EDEVICE = -3,    /* HIP runtime error (no device, launch failure, ...) */
+    SKELFMM_ENOTSUP = -4,    /* valid request this build does not support */
+    SKELFMM_EINTERNAL = -5
+} skelfmm_status;
+
+typedef enum { SKELFMM_LAPLACE = 0, SKELFMM_HELMHOLTZ = 1 } skelfmm_kind;
+
+/* Arithmetic of an apply.  Laplace takes F64 or F32, Helmholtz C128 or C64. */
+typedef enum { SKELFMM_F64 = 0, SKELFMM_F32 = 1, SKELFMM_C128 = 2, SKELFMM_C64 = 3 } skelfmm_dtype;
+
+/* Kernel G (section 2):
+ *   2D Laplace    -log(r) / (2 pi)         (dim = 2)
+ *   3D Laplace    1 / (4 pi r)             (dim = 3)
+ *   3D Helmholtz  exp(i kappa r) / (4 pi r) (dim = 3, kappa >= 0)           */
+typedef struct {
+    int32_t kind;            /* skelfmm_kind */
+    int32_t dim;             /* 2 or 3 */
+    double kappa;            /* Helmholtz wavenumber; ignored for Laplace */
+} skelfmm_kernel;
+
+/* Build and apply options; a zero-initialised struct (or NULL) means defaults. */
+typedef struct {
+    int32_t proxy_shape;     /* 0 default (2D circle, 3D Chebyshev box), 1 box, 2 circle (2D only) */
+    int32_t proxy_points;    /* per side (box) or total (circle); 0 = default (3D 12/side, 2D 128) */
+    double proxy_scale;      /* proxy box side / box side; 0 = default 2.95 (circle radius = scale/2 * side) */
+    int32_t no_compression;  /* test mode: every box keeps all its points (k = n) */
+    int32_t num_threads;     /* host threads for the build; 0 = all cores */
+    int32_t keep_transparent;/* 1: also evaluate pairs of two uncompressed boxes, whose
+                                ifo terms cancel exactly (default 0: they are skipped) */
+    int32_t f64_leaf;        /* C64/F32 applies: evaluate and accumulate the near field in float64 */
+    int32_t reserved[8];
+} skelfmm_options;
+
+/* Build-time and layout statistics (section 5 / table "Notation for reported results"). */
+typedef struct {
+    int64_t n_points;
+    int32_t n_boxes, n_leaves, max_level, top_level, k_max, proxy_count;
+    double t_tree, t_skel;           /* seconds */
+    int64_t m_proj_elems;            /* sum over boxes of k (n - k): entries of all T */
+    int64_t n_entries;               /* index-set entries over all levels */
+    int64_t pairs_near;              /* kernel evaluations per apply (near field, all levels) */
+    int64_t pairs_skel;              /* extra skeleton-pair FMAs per apply (uhat part) */
+    int64_t n_tasks;                 /* near-field work items */
+    int32_t tile_targets;            /* targets per near-field work item */
+    int32_t reserved[7];
+} skelfmm_stats;
+
+/* Read-only host view of the skeleton operators, valid while the operator lives.
+ * Boxes are numbered level by level.  Per box b:
+ *   idx[idx_ptr[b] .. idx_ptr[b+1])  original point indices in natural order (a leaf:
+ *                                    its points; a tree box: its children's skeleton
+ *                                    points, children in order, each in skeleton order)
+ *   pos[same range]                  positions within that order: the k skeleton
+ *                                    positions first, then the n - k redundant ones
+ *   rank[b]                          k, or -1 for boxes at or above the top level
+ *   T[T_ptr[b] .. T_ptr[b+1])        interpolation matrix, column-major k x (n - k)
+ *   coll / coarse / fine             CSR neighbor relations (colleagues incl. self;
+ *                                    coarse = touching leaves one level up;
+ *                                    fine = inverse of coarse, on leaves)            */
+typedef struct {
+    int32_t dim, kind;
+    double kappa;
+    int64_t n_points;
+    const double* points;            /* n_points x dim, caller order */
+    int32_t n_boxes, max_level, top_level, pad0;
+    const int32_t *level, *parent, *is_leaf, *child_ptr, *child_idx, *coord;
+    const int64_t *idx_ptr, *idx, *pos;
+    const int32_t* rank;
+    const int64_t* T_ptr;
+    const double* T;
+    const int32_t *coll_ptr, *coll_idx, *coarse_ptr, *coarse_idx, *fine_ptr, *fine_idx;
+    double root_lo[3];
+    double root_side;
+} skelfmm_plan_view;
+
+/* Build the operator for n points (host buffer, n x dim row-major, copied) with
+ * interpolative-decomposition tolerance tol in (0, 1) and leaf size >= 1.
+ * Host-only and synchronous; touches no GPU.  On success *out owns the operator. */
+skelfmm_status skelfmm_build(const double* points, int64_t n, skelfmm_kernel kernel, double tol,
+                             int32_t leaf_size, const skelfmm_options* opt, skelfmm_op** out);
+
+/* Upload the operator to the current HIP device and size its workspace for up to
+ * nrhs_max right-hand sides of `dtype`.  Synchronous; may allocate.  Calling apply
+ * with a larger nrhs (or a new dtype) prepares implicitly, which then allocates. */
+skelfmm_status skelfmm_prepare(skelfmm_op* op, int64_t nrhs_max, skelfmm_dtype dtype);
+
+/* u = Atilde q on the GPU.  q, u: device buffers, n x nrhs (x2 for complex). */
+skelfmm_status skelfmm_apply(skelfmm_op* op, const void* q, void* u, int64_t nrhs,
+                             skelfmm_dtype dtype, void* hip_stream);
+
+/* w = Atilde^H v on the GPU (the transposed sweep).  Same layout as skelfmm_apply. */
+skelfmm_status skelfmm_apply_adjoint(skelfmm_op* op, const void* v, void* w, int64_t nrhs,
+                                     skelfmm_dtype dtype, void* hip_stream);
+
+skelfmm_status skelfmm_stats_get(const skelfmm_op* op, skelfmm_stats* out);
+skelfmm_status skelfmm_export(const skelfmm_op* op, skelfmm_plan_view* out);
+
+/* Several operators applied as one sweep: every pass of the sweep runs over the
+ * union of the operators' work, so small geometries share launches with large
+ * ones.  Operators must share kind and dim and outlive the batch.  q[i], u[i]:
+ * device buffers of operator i.  adjoint = 1 applies the transposed sweep. */
+skelfmm_status skelfmm_batch_create(skelfmm_op* const* ops, int32_t nops, skelfmm_batch** out);
+skelfmm_status skelfmm_batch_apply(skelfmm_batch* b, const void* const* q, void* const* u,
+                                   int64_t nrhs, skelfmm_dtype dtype, int32_t adjoint,
+                                   void* hip_stream);
+void skelfmm_batch_destroy(skelfmm_batch* b);   /* NULL-safe */
+
+void skelfmm_destroy(skelfmm_op* op);           /* NULL-safe; frees host and device state */
+const char* skelfmm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SKELFMM_H */

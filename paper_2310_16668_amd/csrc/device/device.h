@@ -1,0 +1,75 @@
+// Interface between the C ABI and the GPU executor.
+#pragma once
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../../include/skelfmm.h"
+#include "../host/plan.h"
+
+namespace skelfmm {
+
+struct DeviceError : std::runtime_error { using std::runtime_error::runtime_error; };
+struct NotSupported : std::runtime_error { using std::runtime_error::runtime_error; };
+struct OutOfMemory : std::runtime_error { using std::runtime_error::runtime_error; };
+
+// Near-field segment modes (what a source box contributes to a target box).
+enum SegMode : int32_t {
+    SEG_DIRECT = 0,   // u += G q over all source entries (top level)
+    SEG_IFO = 1,      // colleague: u += G q ; uhat -= G qhat over the source skeleton
+    SEG_IFS = 2,      // coarse leaf: u += G q ; uhat -= G q
+    SEG_TFO = 3       // fine box of a leaf: u += G q - G qhat (skeleton part)
+};
+
+struct Task {
+    int32_t box;      // target box
+    int32_t t0;       // first target entry (relative to the box)
+};
+
+// Host copy of everything the GPU sweep reads.  Built without touching a GPU.
+struct Layout {
+    int dim = 3, kind = 0;
+    double kappa = 0.0;
+    int64_t n_points = 0;
+    int n_boxes = 0, top = 0, max_level = 0;
+    double center[3] = {0, 0, 0};
+    std::vector<int32_t> level_ptr;
+    // per box
+    std::vector<int64_t> voff, hoff, toff;
+    std::vector<int32_t> nb, kb, level, parent, is_leaf;
+    // entries: index-set members of every box at or below the top level, per box
+    // in [skeleton | redundant] order
+    int64_t n_entries = 0, n_hentries = 0;
+    std::vector<double> X;          // n_entries x 4 (x, y, z, 0), root-centred
+    std::vector<int32_t> perm;      // user index of leaf entries, -1 elsewhere
+    std::vector<int32_t> pmap;      // skeleton entry -> entry in the parent's vector
+    std::vector<int32_t> gather_e, gather_p;     // leaf entries and their user indices
+    std::vector<int32_t> topleaf_e, topleaf_p;   // entries of top-level leaves
+    std::vector<double> T;          // interpolation matrices, column-major per box
+    // near field
+    std::vector<int32_t> seg_ptr;   // per target box
+    std::vector<int32_t> seg_src, seg_mode;
+    std::vector<Task> tasks;
+    int tile = 128;
+    int64_t pairs_near = 0, pairs_skel = 0;
+};
+
+Layout make_layout(const Plan& p, bool keep_transparent, int tile);
+
+struct DeviceOp;
+struct DeviceBatch;
+
+DeviceOp* device_create(const Plan& p, bool keep_transparent, bool f64_leaf);
+void device_prepare(DeviceOp* d, int64_t nrhs_max, int dtype);
+void device_apply(DeviceOp* d, const void* q, void* u, int64_t nrhs, int dtype, void* stream, bool adjoint);
+void device_fill_stats(const DeviceOp* d, skelfmm_stats* out);
+void device_destroy(DeviceOp* d);
+
+DeviceBatch* batch_create(const std::vector<DeviceOp*>& ops);
+void batch_apply(DeviceBatch* b, const void* const* q, void* const* u, int64_t nrhs, int dtype,
+                 void* stream, bool adjoint);
+void batch_destroy(DeviceBatch* b);
+
+}  // namespace skelfmm

@@ -1,0 +1,175 @@
+// Packs a built plan into the flat, level-sorted arrays the GPU sweep reads.
+//
+// Entries.  Every box at or below the top level owns a contiguous run of
+// "entries", one per member of its index set, ordered [skeleton | redundant]
+// (the skeleton positions first, as the build's pivot order gives them).  With
+// that order the outgoing skeleton charges are qhat = q[0:k] + T q[k:n] and the
+// downward pass adds uhat to u[0:k] and T^T uhat to u[k:n].  Boxes above the top
+// level own no entries.  Boxes of one level are contiguous, so one launch per
+// level covers its boxes.
+//
+// pmap sends skeleton entry i of a box to the entry of its parent that holds
+// the same point, so the upward pass writes qhat straight into the parent's
+// vector and the downward pass reads the parent's potential back from it.
+//
+// Near-field work.  For each target box, the list of source boxes ("segments")
+// with their translation type; the work list splits every target box into
+// tiles of `tile` entries, sorted by estimated cost (largest first) so one
+// launch over all levels balances across compute units.
+//
+// A box that keeps all its points (k = n) is transparent: qhat = q and
+// E = F = I.  An ifo pair of two transparent boxes adds A q to u and subtracts
+// the same A q from uhat, which the downward pass then adds back to u, so the
+// pair is skipped unless requested; likewise an ifs pair with a transparent
+// target and a tfo pair with a transparent source.
+#include <algorithm>
+#include <numeric>
+#include <stdexcept>
+
+#include "device.h"
+
+namespace skelfmm {
+
+Layout make_layout(const Plan& p, bool keep_transparent, int tile) {
+    Layout L;
+    L.dim = p.dim;
+    L.kind = p.kind;
+    L.kappa = p.kappa;
+    L.n_points = p.n;
+    L.n_boxes = p.n_boxes;
+    L.top = p.top_level;
+    L.max_level = p.max_level;
+    L.level_ptr = p.level_ptr;
+    L.tile = tile;
+    const int nb = p.n_boxes;
+    for (int d = 0; d < p.dim; ++d) L.center[d] = p.root_lo[d] + 0.5 * p.root_side;
+
+    L.voff.assign(nb, 0);
+    L.hoff.assign(nb, 0);
+    L.toff.assign(nb, 0);
+    L.nb.assign(nb, 0);
+    L.kb.assign(nb, 0);
+    L.level = p.level;
+    L.parent = p.parent;
+    L.is_leaf = p.is_leaf;
+    int64_t e = 0, h = 0;
+    for (int b = 0; b < nb; ++b) {
+        const int64_t n = p.idx_ptr[b + 1] - p.idx_ptr[b];
+        if (n >= (int64_t(1) << 31)) throw std::runtime_error("box too large");
+        L.voff[b] = e;
+        L.nb[b] = static_cast<int32_t>(n);
+        L.kb[b] = p.level[b] > p.top_level ? p.rank[b] : 0;
+        L.hoff[b] = h;
+        L.toff[b] = p.T_ptr[b];
+        e += n;
+        h += L.kb[b];
+    }
+    L.n_entries = e;
+    L.n_hentries = h;
+    if (e >= (int64_t(1) << 31)) throw std::runtime_error("too many entries for 32-bit maps");
+
+    // entry coordinates and leaf permutation
+    L.X.assign(static_cast<size_t>(e) * 4, 0.0);
+    L.perm.assign(e, -1);
+    for (int b = 0; b < nb; ++b) {
+        const int64_t n = L.nb[b];
+        const int64_t* ix = &p.idx[p.idx_ptr[b]];
+        const int64_t* ps = &p.pos[p.idx_ptr[b]];
+        for (int64_t i = 0; i < n; ++i) {
+            const int64_t pt = ix[ps[i]];
+            double* x = &L.X[static_cast<size_t>(L.voff[b] + i) * 4];
+            for (int d = 0; d < p.dim; ++d) x[d] = p.pts[pt * p.dim + d] - L.center[d];
+            if (p.is_leaf[b]) L.perm[L.voff[b] + i] = static_cast<int32_t>(pt);
+        }
+        if (p.is_leaf[b]) {
+            for (int64_t i = 0; i < n; ++i) {
+                L.gather_e.push_back(static_cast<int32_t>(L.voff[b] + i));
+                L.gather_p.push_back(static_cast<int32_t>(ix[ps[i]]));
+                if (p.level[b] == p.top_level) {
+                    L.topleaf_e.push_back(static_cast<int32_t>(L.voff[b] + i));
+                    L.topleaf_p.push_back(static_cast<int32_t>(ix[ps[i]]));
+                }
+            }
+        }
+    }
+    if (static_cast<int64_t>(L.gather_e.size()) != p.n) throw std::runtime_error("leaves do not partition the points");
+
+    // parent slots of skeleton entries
+    L.pmap.assign(h, 0);
+    for (int b = 0; b < nb; ++b) {
+        if (p.level[b] <= p.top_level) continue;
+        const int par = p.parent[b];
+        // offset of b's block in the parent's natural order
+        int64_t off = 0;
+        for (int c = p.child_ptr[par]; c < p.child_ptr[par + 1]; ++c) {
+            if (p.child_idx[c] == b) break;
+            off += p.rank[p.child_idx[c]];
+        }
+        // inverse of the parent's [sk | rd] order
+        const int64_t np = L.nb[par];
+        const int64_t* pp = &p.pos[p.idx_ptr[par]];
+        std::vector<int32_t> inv(np);
+        for (int64_t i = 0; i < np; ++i) inv[pp[i]] = static_cast<int32_t>(i);
+        for (int i = 0; i < L.kb[b]; ++i)
+            L.pmap[L.hoff[b] + i] = static_cast<int32_t>(L.voff[par] + inv[off + i]);
+    }
+    L.T = p.T;
+
+    // near-field segments per target box
+    auto transparent = [&](int b) { return L.kb[b] == L.nb[b]; };
+    L.seg_ptr.assign(nb + 1, 0);
+    std::vector<int32_t> top_boxes;
+    for (int b = p.level_ptr[p.top_level]; b < p.level_ptr[p.top_level + 1]; ++b) top_boxes.push_back(b);
+    for (int b = 0; b < nb; ++b) {
+        const int lb = p.level[b];
+        if (lb >= p.top_level) {
+            if (lb == p.top_level) {
+                for (int c : top_boxes) { L.seg_src.push_back(c); L.seg_mode.push_back(SEG_DIRECT); }
+            } else {
+                for (int x = p.coll_ptr[b]; x < p.coll_ptr[b + 1]; ++x) {
+                    const int c = p.coll_idx[x];
+                    if (!keep_transparent && transparent(b) && transparent(c)) continue;
+                    L.seg_src.push_back(c); L.seg_mode.push_back(SEG_IFO);
+                }
+                for (int x = p.coarse_ptr[b]; x < p.coarse_ptr[b + 1]; ++x) {
+                    const int c = p.coarse_idx[x];
+                    if (!keep_transparent && transparent(b)) continue;
+                    L.seg_src.push_back(c); L.seg_mode.push_back(SEG_IFS);
+                }
+            }
+            if (p.is_leaf[b])
+                for (int x = p.fine_ptr[b]; x < p.fine_ptr[b + 1]; ++x) {
+                    const int c = p.fine_idx[x];
+                    if (!keep_transparent && transparent(c)) continue;
+                    L.seg_src.push_back(c); L.seg_mode.push_back(SEG_TFO);
+                }
+        }
+        L.seg_ptr[b + 1] = static_cast<int32_t>(L.seg_src.size());
+    }
+
+    // work list: tiles of every target box, largest estimated cost first
+    std::vector<std::pair<int64_t, Task>> work;
+    for (int b = 0; b < nb; ++b) {
+        if (p.level[b] < p.top_level || L.nb[b] == 0) continue;
+        int64_t src = 0, skel_src = 0;
+        for (int x = L.seg_ptr[b]; x < L.seg_ptr[b + 1]; ++x) {
+            const int c = L.seg_src[x];
+            src += L.nb[c];
+            if (L.seg_mode[x] == SEG_IFO) skel_src += L.kb[c];
+            if (L.seg_mode[x] == SEG_IFS) skel_src += L.nb[c];
+        }
+        for (int t0 = 0; t0 < L.nb[b]; t0 += tile) {
+            const int nt = std::min(tile, L.nb[b] - t0);
+            const int nh = std::max(0, std::min(L.kb[b] - t0, nt));
+            L.pairs_near += int64_t(nt) * src;
+            L.pairs_skel += int64_t(nh) * skel_src;
+            work.push_back({int64_t(tile) * src + 64, Task{b, t0}});
+        }
+    }
+    std::stable_sort(work.begin(), work.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
+    L.tasks.reserve(work.size());
+    for (auto& w : work) L.tasks.push_back(w.second);
+    return L;
+}
+
+}  // namespace skelfmm
