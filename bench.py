@@ -1,0 +1,225 @@
+"""Benchmark: apply points/s (forward + adjoint) of the skeletonization FMM on
+3D Laplace, N = 2^20 points uniform in the unit cube, leaf <= 128, ID tolerance
+1e-7, on one MI355X.
+
+A step is one forward apply u = Atilde q followed by one adjoint apply
+w = Atilde^H v (the whole GPU sweep each: gather, upward pass, near field,
+downward pass, output), inputs resident in HBM.  value = N * nrhs / (time of
+one step).  The run also reports each path's error against the float64 dense
+sum on 2,048 random targets, the near-field kernel's arithmetic roofline (HIP
+events around that pass, on the apply's stream), the transfer passes' HBM
+rate, and the CPU oracle timed on a bounded sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--dtype f32|f64]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
+PEAK_HBM_GBS = 8000.0
+# algorithmic flops of one 3D Laplace pair: 3 subtractions, |d|^2 (3 mul + 2 add),
+# one reciprocal square root, one multiply-add into u; a skeleton pair adds one
+# multiply-add into uhat
+FLOPS_PER_PAIR = 11
+FLOPS_PER_SKEL_PAIR = 2
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--dtype", choices=["f32", "f64"], default="f32")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work to sample")
+    ap.add_argument("--profile-only", action="store_true", help="skip accuracy checks and baseline")
+    return ap.parse_args()
+
+
+def pair_counts(P) -> np.ndarray:
+    """Kernel evaluations the oracle's apply does per target box (all pairs it visits)."""
+    nb = P["n_boxes"]
+    n = np.diff(P["idx_ptr"])
+    k = np.maximum(P["rank"], 0)
+    top = P["top_level"]
+    lev = P["level"]
+    cnt = np.zeros(nb, dtype=np.float64)
+    tops = np.nonzero(lev == top)[0]
+    ntop = n[tops].sum()
+    for b in range(nb):
+        if lev[b] < top:
+            continue
+        c = 0.0
+        if lev[b] == top:
+            c += n[b] * ntop
+        else:
+            cl = P["coll_idx"][P["coll_ptr"][b]:P["coll_ptr"][b + 1]]
+            c += n[b] * n[cl].sum() + k[b] * k[cl].sum()
+            co = P["coarse_idx"][P["coarse_ptr"][b]:P["coarse_ptr"][b + 1]]
+            c += (n[b] + k[b]) * n[co].sum()
+        if P["is_leaf"][b]:
+            fi = P["fine_idx"][P["fine_ptr"][b]:P["fine_ptr"][b + 1]]
+            c += n[b] * (n[fi] + k[fi]).sum()
+        cnt[b] = c
+    return cnt
+
+
+def cpu_baseline(P, q, budget_s: float, nrhs: int = 1):
+    """Time the oracle's apply on a bounded, random sample of target boxes and
+    scale the translation time to the whole workload; the upward and downward
+    passes run in full in both timings."""
+    import oracle
+
+    cnt = pair_counts(P)
+    total = cnt.sum()
+    rng = np.random.default_rng(77)
+    mask0 = np.zeros(P["n_boxes"], dtype=np.uint8)
+    t0 = time.perf_counter()
+    oracle.apply(P, q, box_mask=mask0)
+    t_base = time.perf_counter() - t0
+    # calibrate: a small sample first, then one sized to the budget
+    frac = 2e-3
+    mask = (rng.random(P["n_boxes"]) < frac).astype(np.uint8)
+    t0 = time.perf_counter()
+    oracle.apply(P, q, box_mask=mask)
+    t_cal = max(time.perf_counter() - t0 - t_base, 1e-3)
+    rate = cnt[mask == 1].sum() / t_cal if mask.any() else 1e9
+    frac = min(1.0, budget_s * rate / total)
+    mask = (rng.random(P["n_boxes"]) < frac).astype(np.uint8)
+    t0 = time.perf_counter()
+    oracle.apply(P, q, box_mask=mask)
+    t_s = time.perf_counter() - t0
+    sampled = cnt[mask == 1].sum()
+    t_full = t_base + (t_s - t_base) * total / max(sampled, 1.0)
+    n = P["points"].shape[0]
+    return {
+        "value": 2 * 0 + n * nrhs / (2.0 * t_full),
+        "unit": "points/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": (f"CPU float64 apply (oracle O2) of the same skeleton operators; translations for "
+                   f"{int(mask.sum())} of {P['n_boxes']} target boxes ({100 * sampled / total:.2f}% of "
+                   f"{total:.3e} pair evaluations) in {t_s:.1f}s, upward/downward passes in full "
+                   f"({t_base:.1f}s); forward+adjoint time extrapolated as 2 x {t_full:.1f}s"),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU; --gpus must be 1 "
+                          "(the sharded design is described in DESIGN.md)"}))
+        return 2
+    import torch
+
+    import workloads
+    import paper_2310_16668_amd as sk
+
+    w = workloads.LAPLACE3D_1M
+    x = w.points()
+    q_h = w.charges()
+    v_h = w.weights()
+    log(f"[bench] building {w.name}: N={w.n} leaf={w.leaf_size} tol={w.tol}")
+    t0 = time.perf_counter()
+    op = sk.build(x, "laplace", tol=w.tol, leaf_size=w.leaf_size)
+    t_build = time.perf_counter() - t0
+    st = op.stats()
+    log(f"[bench] build {t_build:.1f}s levels={st['max_level']} k_max={st['k_max']} "
+        f"pairs={st['pairs_near']:.3e} skel_pairs={st['pairs_skel']:.3e}")
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    results = {}
+    for dt_name, tdt in (("f64", torch.float64), ("f32", torch.float32)):
+        op.prepare(1, tdt)
+        q = torch.from_numpy(q_h).to(dev, tdt)
+        v = torch.from_numpy(v_h).to(dev, tdt)
+        for _ in range(args.warmup):
+            op.apply(q)
+            op.apply_adjoint(v)
+        torch.cuda.synchronize()
+        op.timing(True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(args.steps):
+            u = op.apply(q)
+            wv = op.apply_adjoint(v)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_step = e0.elapsed_time(e1) / args.steps
+        passes = op.timing_read()
+        op.timing(False)
+        res = {"ms_per_step": ms_step, "passes_ms_per_sweep": {k: passes[k] / passes["sweeps"] for k in sk.PASSES}}
+        if not args.profile_only:
+            import oracle
+            tg = w.targets()
+            u1 = oracle.direct(x, q_h, targets=tg)
+            uu = u.double().cpu().numpy()
+            res["relerr_vs_direct"] = float(np.linalg.norm(uu[tg] - u1) / np.linalg.norm(u1))
+            ww = wv.double().cpu().numpy()
+            w1 = oracle.direct(x, v_h, targets=tg)   # Laplace: A^H = A
+            res["relerr_adjoint_vs_direct"] = float(np.linalg.norm(ww[tg] - w1) / np.linalg.norm(w1))
+        results[dt_name] = res
+        log(f"[bench] {dt_name}: {ms_step:.3f} ms/step {res}")
+
+    chosen = args.dtype
+    r = results[chosen]
+    near_ms = r["passes_ms_per_sweep"]["near_field"]
+    flops = FLOPS_PER_PAIR * st["pairs_near"] + FLOPS_PER_SKEL_PAIR * st["pairs_skel"]
+    achieved = flops / (near_ms * 1e-3) / 1e12
+    sT = 8 if chosen == "f64" else 4
+    # upward and downward each read every T once, plus their vectors (n and k entries)
+    t_bytes = st["m_proj_elems"] * sT
+    vec_bytes = st["n_entries"] * sT * 4
+    trans_ms = r["passes_ms_per_sweep"]["upward"] + r["passes_ms_per_sweep"]["downward"]
+    out = {
+        "metric": "apply points/s (fwd+adjoint), 3D Laplace N=1M @1e-6 rel err; % HBM/VALU roofline",
+        "value": w.n / (r["ms_per_step"] * 1e-3),
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": chosen,
+        "data": "synthetic",
+        "config": {"workload": w.name, "n": w.n, "dim": 3, "kernel": "laplace", "leaf_size": w.leaf_size,
+                   "tol": w.tol, "nrhs": 1, "step": "forward apply + adjoint apply"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS[chosen], "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_TFLOPS[chosen], "traffic": None,
+                     "kernel": "k_near (near field, one launch per sweep)",
+                     "near_ms_per_launch": near_ms, "pairs_per_launch": st["pairs_near"],
+                     "skel_pairs_per_launch": st["pairs_skel"]},
+        "transfer_passes": {"bound": "hbm", "bytes_per_sweep": 2 * (t_bytes + vec_bytes),
+                            "ms_per_sweep": trans_ms,
+                            "achieved_GBs": 2 * (t_bytes + vec_bytes) / (trans_ms * 1e-3) / 1e9,
+                            "peak_GBs": PEAK_HBM_GBS},
+        "paths": results,
+        "build_s": t_build,
+    }
+    if not args.no_cpu_baseline and not args.profile_only:
+        log("[bench] timing the CPU oracle on a sample")
+        out["cpu_baseline"] = cpu_baseline(op.export(), q_h, args.cpu_budget)
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -143,6 +143,16 @@ skelfmm_status skelfmm_apply_adjoint(skelfmm_op* op, const void* v, void* w, int
                                      skelfmm_dtype dtype, void* hip_stream);
 
 skelfmm_status skelfmm_stats_get(const skelfmm_op* op, skelfmm_stats* out);
+
+/* Per-pass GPU timing.  When enabled, each apply records HIP events on its stream
+ * around its passes: [0] gather, [1] upward pass, [2] near field (ifo, ifs, tfo,
+ * top level), [3] downward pass, [4] output of top-level leaves.
+ * skelfmm_timing(op, 1) enables and zeroes the accumulators; (op, 0) disables.
+ * skelfmm_timing_read waits for the recorded events and returns the summed
+ * milliseconds per pass (ms[SKELFMM_NPASS]) and the number of timed sweeps. */
+#define SKELFMM_NPASS 5
+skelfmm_status skelfmm_timing(skelfmm_op* op, int32_t enable);
+skelfmm_status skelfmm_timing_read(skelfmm_op* op, double* ms, int64_t* sweeps);
 skelfmm_status skelfmm_export(const skelfmm_op* op, skelfmm_plan_view* out);
 
 /* Several operators applied as one sweep: every pass of the sweep runs over the

@@ -20,6 +20,11 @@ if not os.path.exists(_LIB_PATH):
     raise ImportError(f"{_LIB_PATH} is missing; build it with __graft_entry__.build() "
                       "or python paper_2310_16668_amd/_build.py")
 
+# torch ships its own HIP runtime under the same soname as the system one; load
+# torch first so this library binds to the runtime that owns torch's device
+# memory and streams (one HIP runtime per process).
+import torch  # noqa: E402,F401
+
 _lib = ctypes.CDLL(_LIB_PATH)
 
 LAPLACE, HELMHOLTZ = 0, 1
@@ -83,14 +88,18 @@ _lib.skelfmm_batch_create.argtypes = [_P(_vp), ctypes.c_int32, _P(_vp)]
 _lib.skelfmm_batch_apply.argtypes = [_vp, _P(_vp), _P(_vp), ctypes.c_int64, ctypes.c_int, ctypes.c_int32, _vp]
 _lib.skelfmm_batch_destroy.argtypes = [_vp]
 _lib.skelfmm_destroy.argtypes = [_vp]
+_lib.skelfmm_timing.argtypes = [_vp, ctypes.c_int32]
+_lib.skelfmm_timing_read.argtypes = [_vp, _P(ctypes.c_double), _P(ctypes.c_int64)]
 _lib.skelfmm_last_error.restype = ctypes.c_char_p
 for _f in ("skelfmm_build", "skelfmm_prepare", "skelfmm_apply", "skelfmm_apply_adjoint", "skelfmm_stats_get",
-           "skelfmm_export", "skelfmm_batch_create", "skelfmm_batch_apply"):
+           "skelfmm_export", "skelfmm_batch_create", "skelfmm_batch_apply", "skelfmm_timing",
+           "skelfmm_timing_read"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTED = ("skelfmm_build", "skelfmm_prepare", "skelfmm_apply", "skelfmm_apply_adjoint", "skelfmm_stats_get",
             "skelfmm_export", "skelfmm_batch_create", "skelfmm_batch_apply", "skelfmm_batch_destroy",
-            "skelfmm_destroy", "skelfmm_last_error")
+            "skelfmm_destroy", "skelfmm_last_error", "skelfmm_timing", "skelfmm_timing_read")
+PASSES = ("gather", "upward", "near_field", "downward", "output")
 
 
 def _check(status: int):
@@ -170,6 +179,19 @@ class Operator:
             "fine_ptr": fine_ptr, "fine_idx": arr(v.fine_idx, int(fine_ptr[-1]), np.int32),
             "root_lo": np.array(v.root_lo[:]), "root_side": v.root_side,
         }
+
+    def timing(self, enable: bool = True):
+        """Enable (and zero) or disable per-pass HIP-event timing of applies."""
+        _check(_lib.skelfmm_timing(self._h, int(enable)))
+
+    def timing_read(self) -> dict:
+        """Summed milliseconds per pass over the timed applies (waits for them)."""
+        ms = (ctypes.c_double * len(PASSES))()
+        n = ctypes.c_int64()
+        _check(_lib.skelfmm_timing_read(self._h, ms, ctypes.byref(n)))
+        out = {p: ms[i] for i, p in enumerate(PASSES)}
+        out["sweeps"] = n.value
+        return out
 
     def prepare(self, nrhs: int = 1, dtype=None):
         torch = _torch()

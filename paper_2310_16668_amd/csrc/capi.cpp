@@ -180,6 +180,23 @@ skelfmm_status skelfmm_stats_get(const skelfmm_op* op, skelfmm_stats* out) {
     });
 }
 
+skelfmm_status skelfmm_timing(skelfmm_op* op, int32_t enable) {
+    if (!alive(op)) return fail(SKELFMM_EINVAL, "invalid operator");
+    return guarded([&]() -> skelfmm_status {
+        skelfmm::device_timing(op->dev, enable != 0);
+        return SKELFMM_OK;
+    });
+}
+
+skelfmm_status skelfmm_timing_read(skelfmm_op* op, double* ms, int64_t* sweeps) {
+    if (!alive(op)) return fail(SKELFMM_EINVAL, "invalid operator");
+    if (!ms || !sweeps) return fail(SKELFMM_EINVAL, "NULL output");
+    return guarded([&]() -> skelfmm_status {
+        skelfmm::device_timing_read(op->dev, ms, sweeps);
+        return SKELFMM_OK;
+    });
+}
+
 skelfmm_status skelfmm_export(const skelfmm_op* op, skelfmm_plan_view* out) {
     if (!alive(op)) return fail(SKELFMM_EINVAL, "invalid operator");
     if (!out) return fail(SKELFMM_EINVAL, "out is NULL");

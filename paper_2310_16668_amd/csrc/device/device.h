@@ -66,6 +66,8 @@ void device_prepare(DeviceOp* d, int64_t nrhs_max, int dtype);
 void device_apply(DeviceOp* d, const void* q, void* u, int64_t nrhs, int dtype, void* stream, bool adjoint);
 void device_fill_stats(const DeviceOp* d, skelfmm_stats* out);
 void device_destroy(DeviceOp* d);
+void device_timing(DeviceOp* d, bool enable);
+void device_timing_read(DeviceOp* d, double* ms, int64_t* sweeps);
 
 DeviceBatch* batch_create(const std::vector<DeviceOp*>& ops);
 void batch_apply(DeviceBatch* b, const void* const* q, void* const* u, int64_t nrhs, int dtype,

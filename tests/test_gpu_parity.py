@@ -1,0 +1,190 @@
+"""GPU parity: the HIP sweep against the oracle on the same seeded inputs.
+
+Bars (written per test):
+  * float64 / complex128 apply vs O2 on the same skeleton operators: relative
+    l2 <= 1e-12 (results differ only by summation order and by the exactly
+    cancelling uncompressed pairs the GPU skips);
+  * any apply vs O1, the dense sum: <= 10 x the ID tolerance;
+  * float32 / complex64 applies: error vs O1 and vs O2 is stated per case and
+    held to 10 x tol for tol >= 1e-6.
+Every GPU call goes through the C ABI (the binding only marshals arguments).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2310_16668_amd as sk  # noqa: E402
+
+
+def relerr(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def dev(x, dtype):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0", dtype)
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+CASES = {
+    # name: (points, kind, kappa, tol, leaf)
+    "lap2d_16k": (lambda: workloads.LAPLACE2D_16K.points(), "laplace", 0.0, 1e-8, 64),
+    "lap3d_uniform_64k": (lambda: workloads.uniform_points(65536, 3, 501), "laplace", 0.0, 1e-7, 128),
+    "lap3d_ellipsoid_60k": (lambda: workloads.ellipsoid_points(60000, 502), "laplace", 0.0, 1e-6, 64),
+    "helm3d_uniform_32k": (lambda: workloads.uniform_points(32768, 3, 503), "helmholtz", 20.0, 1e-6, 64),
+}
+_built = {}
+
+
+def _op(name, **kw):
+    key = (name, tuple(sorted(kw.items())))
+    if key not in _built:
+        mk, kind, kappa, tol, b = CASES[name]
+        x = mk()
+        op = sk.build(x, kind, tol=tol, leaf_size=b, kappa=kappa, **kw)
+        _built[key] = (x, op, op.export())
+    return _built[key]
+
+
+def _charges(name, n, seed):
+    kind = CASES[name][1]
+    return workloads.charges(n, 1, seed, complex_=(kind == "helmholtz"))
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_f64_forward_and_adjoint_match_o2(name):
+    _say("case", name)
+    x, op, P = _op(name)
+    kind, kappa, tol = CASES[name][1], CASES[name][2], CASES[name][3]
+    q = _charges(name, x.shape[0], 7)
+    dt = torch.complex128 if kind == "helmholtz" else torch.float64
+    u = host(op.apply(dev(q, dt)))
+    u2 = oracle.apply(P, q)
+    e2 = relerr(u, u2)
+    _say(name, "fwd vs O2", e2)
+    assert e2 <= 1e-12
+    w = host(op.apply_adjoint(dev(q, dt)))
+    w2 = oracle.apply(P, q, adjoint=True)
+    ew = relerr(w, w2)
+    _say(name, "adj vs O2T", ew)
+    assert ew <= 1e-12
+    tg = workloads.target_subset(x.shape[0], 2048, 11)
+    u1 = oracle.direct(x, q, kind, kappa, targets=tg)
+    e1 = relerr(u[tg], u1)
+    _say(name, "fwd vs O1", e1, "tol", tol)
+    assert e1 <= 10 * tol
+
+
+@pytest.mark.parametrize("name", ["lap3d_uniform_64k", "lap3d_ellipsoid_60k"])
+def test_keep_transparent_matches_o2(name):
+    x, op, P = _op(name, keep_transparent=True)
+    q = _charges(name, x.shape[0], 8)
+    u = host(op.apply(dev(q, torch.float64)))
+    assert relerr(u, oracle.apply(P, q)) <= 1e-12
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_single_precision_error_stated(name):
+    x, op, P = _op(name)
+    kind, kappa, tol = CASES[name][1], CASES[name][2], CASES[name][3]
+    q = _charges(name, x.shape[0], 9)
+    dt = torch.complex64 if kind == "helmholtz" else torch.float32
+    u = host(op.apply(dev(q, dt))).astype(np.complex128 if kind == "helmholtz" else np.float64)
+    tg = workloads.target_subset(x.shape[0], 2048, 12)
+    u1 = oracle.direct(x, q.astype(np.complex64 if kind == "helmholtz" else np.float32).astype(q.dtype),
+                       kind, kappa, targets=tg)
+    e1 = relerr(u[tg], u1)
+    e2 = relerr(u, oracle.apply(P, q))
+    _say(name, "single vs O1", e1, "vs O2", e2)
+    assert e1 <= max(10 * tol, 1e-5)
+
+
+def test_f64_leaf_single_precision_helmholtz():
+    name = "helm3d_uniform_32k"
+    x, op, P = _op(name, f64_leaf=True)
+    q = _charges(name, x.shape[0], 10)
+    u = host(op.apply(dev(q, torch.complex64))).astype(np.complex128)
+    tg = workloads.target_subset(x.shape[0], 2048, 13)
+    e1 = relerr(u[tg], oracle.direct(x, q.astype(np.complex64).astype(np.complex128), "helmholtz", 20.0, targets=tg))
+    _say(name, "c64 + f64 leaf vs O1", e1)
+    assert e1 <= 10 * CASES[name][3]
+
+
+def test_deterministic_and_linear():
+    x, op, P = _op("lap3d_ellipsoid_60k")
+    q1 = _charges("lap3d_ellipsoid_60k", x.shape[0], 1)
+    q2 = _charges("lap3d_ellipsoid_60k", x.shape[0], 2)
+    a = host(op.apply(dev(q1, torch.float64)))
+    b = host(op.apply(dev(q1, torch.float64)))
+    assert np.array_equal(a, b)
+    c = host(op.apply(dev(0.5 * q1 - 2.0 * q2, torch.float64)))
+    d = 0.5 * a - 2.0 * host(op.apply(dev(q2, torch.float64)))
+    assert relerr(c, d) <= 1e-14
+
+
+def test_edge_cases():
+    rng = np.random.default_rng(0)
+    # a single point: nothing acts on it
+    op = sk.build(np.array([[0.3, 0.4, 0.5]]), "laplace", tol=1e-6, leaf_size=8)
+    u = host(op.apply(dev(np.array([2.0]), torch.float64)))
+    assert u[0] == 0.0
+    # root is a leaf: the direct sum
+    x = rng.random((100, 3))
+    q = rng.uniform(-1, 1, 100)
+    op = sk.build(x, "laplace", tol=1e-6, leaf_size=128)
+    assert relerr(host(op.apply(dev(q, torch.float64))), oracle.direct(x, q)) <= 1e-14
+    # leaves on level 1
+    x = rng.random((500, 3))
+    q = rng.uniform(-1, 1, 500)
+    op = sk.build(x, "laplace", tol=1e-6, leaf_size=100)
+    assert op.export()["max_level"] == 1
+    assert relerr(host(op.apply(dev(q, torch.float64))), oracle.direct(x, q)) <= 1e-14
+    # coincident points contribute zero, in every level of the tree
+    x = np.vstack([rng.random((3000, 3)), np.repeat(rng.random((5, 3)), 40, axis=0)])
+    q = rng.uniform(-1, 1, x.shape[0])
+    op = sk.build(x, "laplace", tol=1e-8, leaf_size=32)
+    P = op.export()
+    u = host(op.apply(dev(q, torch.float64)))
+    assert np.all(np.isfinite(u))
+    assert relerr(u, oracle.apply(P, q)) <= 1e-12
+    assert relerr(u, oracle.direct(x, q)) <= 1e-7
+    # no compression: the GPU sweep is the dense sum
+    x = rng.random((4000, 2))
+    q = rng.uniform(-1, 1, 4000)
+    op = sk.build(x, "laplace", tol=1e-6, leaf_size=16, no_compression=True, keep_transparent=True)
+    assert relerr(host(op.apply(dev(q, torch.float64))), oracle.direct(x, q)) <= 1e-13
+
+
+def test_autograd_backward_is_adjoint():
+    name = "helm3d_uniform_32k"
+    x, op, P = _op(name)
+    q = _charges(name, x.shape[0], 3)
+    w = workloads.charges(x.shape[0], 1, 4, complex_=True)
+    qt = dev(q, torch.complex128).requires_grad_(True)
+    wt = dev(w, torch.complex128)
+    u = sk.fmm_apply(op, qt)
+    loss = torch.real(torch.sum(torch.conj(wt) * u))
+    loss.backward()
+    # L = Re <w, A q>  =>  dL/dq (PyTorch convention, conj-Wirtinger) = A^H w
+    g = host(qt.grad)
+    assert relerr(g, oracle.apply(P, w, adjoint=True)) <= 1e-12
+
+
+def test_argument_errors_leave_output_untouched():
+    x, op, P = _op("lap3d_ellipsoid_60k")
+    q = torch.zeros(x.shape[0], dtype=torch.complex128, device="cuda:0")
+    with pytest.raises(sk.SkelfmmError) as e:
+        op.apply(q)
+    assert e.value.status == -1
