@@ -89,16 +89,19 @@ _lib.skelfmm_batch_apply.argtypes = [_vp, _P(_vp), _P(_vp), ctypes.c_int64, ctyp
 _lib.skelfmm_batch_destroy.argtypes = [_vp]
 _lib.skelfmm_destroy.argtypes = [_vp]
 _lib.skelfmm_timing.argtypes = [_vp, ctypes.c_int32]
+_lib.skelfmm_autotune.argtypes = [_vp, ctypes.c_int, _vp, _P(ctypes.c_int32), _P(ctypes.c_float)]
+_lib.skelfmm_set_targets_per_lane.argtypes = [_vp, ctypes.c_int32]
 _lib.skelfmm_timing_read.argtypes = [_vp, _P(ctypes.c_double), _P(ctypes.c_int64)]
 _lib.skelfmm_last_error.restype = ctypes.c_char_p
 for _f in ("skelfmm_build", "skelfmm_prepare", "skelfmm_apply", "skelfmm_apply_adjoint", "skelfmm_stats_get",
            "skelfmm_export", "skelfmm_batch_create", "skelfmm_batch_apply", "skelfmm_timing",
-           "skelfmm_timing_read"):
+           "skelfmm_timing_read", "skelfmm_autotune", "skelfmm_set_targets_per_lane"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTED = ("skelfmm_build", "skelfmm_prepare", "skelfmm_apply", "skelfmm_apply_adjoint", "skelfmm_stats_get",
             "skelfmm_export", "skelfmm_batch_create", "skelfmm_batch_apply", "skelfmm_batch_destroy",
-            "skelfmm_destroy", "skelfmm_last_error", "skelfmm_timing", "skelfmm_timing_read")
+            "skelfmm_destroy", "skelfmm_last_error", "skelfmm_timing", "skelfmm_timing_read",
+            "skelfmm_autotune", "skelfmm_set_targets_per_lane")
 PASSES = ("gather", "upward", "near_field", "downward", "output")
 
 
@@ -179,6 +182,21 @@ class Operator:
             "fine_ptr": fine_ptr, "fine_idx": arr(v.fine_idx, int(fine_ptr[-1]), np.int32),
             "root_lo": np.array(v.root_lo[:]), "root_side": v.root_side,
         }
+
+    def autotune(self, dtype=None) -> dict:
+        """Time the near-field launch with 1, 2 and 4 targets per lane; keep the fastest."""
+        torch = _torch()
+        if dtype is None:
+            dtype = torch.complex128 if self.kind == HELMHOLTZ else torch.float64
+        code = _dtype_code(torch.empty(0, dtype=dtype))
+        chosen = ctypes.c_int32()
+        ms = (ctypes.c_float * 3)()
+        stream = torch.cuda.current_stream().cuda_stream
+        _check(_lib.skelfmm_autotune(self._h, code, stream, ctypes.byref(chosen), ms))
+        return {"targets_per_lane": chosen.value, "ms": {1: ms[0], 2: ms[1], 4: ms[2]}}
+
+    def set_targets_per_lane(self, tpl: int):
+        _check(_lib.skelfmm_set_targets_per_lane(self._h, tpl))
 
     def timing(self, enable: bool = True):
         """Enable (and zero) or disable per-pass HIP-event timing of applies."""

@@ -33,6 +33,7 @@ struct skelfmm_op {
 struct skelfmm_batch {
     uint64_t magic = kMagic;
     skelfmm::DeviceBatch* dev = nullptr;
+    int kind = 0;
 };
 
 namespace {
@@ -180,6 +181,27 @@ skelfmm_status skelfmm_stats_get(const skelfmm_op* op, skelfmm_stats* out) {
     });
 }
 
+skelfmm_status skelfmm_autotune(skelfmm_op* op, skelfmm_dtype dtype, void* hip_stream, int32_t* chosen, float* ms) {
+    if (!alive(op)) return fail(SKELFMM_EINVAL, "invalid operator");
+    if (!chosen) return fail(SKELFMM_EINVAL, "chosen is NULL");
+    if (skelfmm_status s = check_dtype(op, dtype)) return s;
+    return guarded([&]() -> skelfmm_status {
+        float t[3] = {0, 0, 0};
+        *chosen = skelfmm::device_autotune(op->dev, static_cast<int>(dtype), hip_stream, t);
+        if (ms) for (int i = 0; i < 3; ++i) ms[i] = t[i];
+        return SKELFMM_OK;
+    });
+}
+
+skelfmm_status skelfmm_set_targets_per_lane(skelfmm_op* op, int32_t tpl) {
+    if (!alive(op)) return fail(SKELFMM_EINVAL, "invalid operator");
+    if (tpl != 1 && tpl != 2 && tpl != 4) return fail(SKELFMM_EINVAL, "targets per lane must be 1, 2 or 4");
+    return guarded([&]() -> skelfmm_status {
+        skelfmm::device_set_tpl(op->dev, tpl);
+        return SKELFMM_OK;
+    });
+}
+
 skelfmm_status skelfmm_timing(skelfmm_op* op, int32_t enable) {
     if (!alive(op)) return fail(SKELFMM_EINVAL, "invalid operator");
     return guarded([&]() -> skelfmm_status {
@@ -246,6 +268,7 @@ skelfmm_status skelfmm_batch_create(skelfmm_op* const* ops, int32_t nops, skelfm
         std::vector<skelfmm::DeviceOp*> devs;
         for (int i = 0; i < nops; ++i) devs.push_back(ops[i]->dev);
         auto* b = new skelfmm_batch();
+        b->kind = ops[0]->plan.kind;
         try {
             b->dev = skelfmm::batch_create(devs);
         } catch (...) {
@@ -262,6 +285,12 @@ skelfmm_status skelfmm_batch_apply(skelfmm_batch* b, const void* const* q, void*
     if (!b || b->magic != kMagic) return fail(SKELFMM_EINVAL, "invalid batch");
     if (!q || !u) return fail(SKELFMM_EINVAL, "NULL vector list");
     if (nrhs < 1) return fail(SKELFMM_EINVAL, "nrhs must be >= 1");
+    {
+        const bool cplx = dtype == SKELFMM_C128 || dtype == SKELFMM_C64;
+        if (dtype != SKELFMM_F64 && dtype != SKELFMM_F32 && !cplx) return fail(SKELFMM_EINVAL, "unknown dtype");
+        if ((b->kind == SKELFMM_HELMHOLTZ) != cplx)
+            return fail(SKELFMM_EINVAL, cplx ? "Laplace needs a real dtype" : "Helmholtz needs a complex dtype");
+    }
     return guarded([&]() -> skelfmm_status {
         skelfmm::batch_apply(b->dev, q, u, nrhs, static_cast<int>(dtype), hip_stream, adjoint != 0);
         return SKELFMM_OK;

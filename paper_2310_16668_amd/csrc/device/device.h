@@ -20,7 +20,9 @@ enum SegMode : int32_t {
     SEG_DIRECT = 0,   // u += G q over all source entries (top level)
     SEG_IFO = 1,      // colleague: u += G q ; uhat -= G qhat over the source skeleton
     SEG_IFS = 2,      // coarse leaf: u += G q ; uhat -= G q
-    SEG_TFO = 3       // fine box of a leaf: u += G q - G qhat (skeleton part)
+    SEG_TFO = 3,      // fine box of a leaf: u += G q - G qhat (skeleton part)
+    SEG_MODE_MASK = 7,
+    SEG_SELF = 8      // flag: the source box is the target box
 };
 
 struct Task {
@@ -43,6 +45,8 @@ struct Layout {
     // in [skeleton | redundant] order
     int64_t n_entries = 0, n_hentries = 0;
     std::vector<double> X;          // n_entries x 4 (x, y, z, 0), root-centred
+    std::vector<float> Xrel;        // n_entries x 4, offsets from the owning box's centre
+    std::vector<double> ctr;        // n_boxes x 4, box centres (root-centred)
     std::vector<int32_t> perm;      // user index of leaf entries, -1 elsewhere
     std::vector<int32_t> pmap;      // skeleton entry -> entry in the parent's vector
     std::vector<int32_t> gather_e, gather_p;     // leaf entries and their user indices
@@ -51,12 +55,18 @@ struct Layout {
     // near field
     std::vector<int32_t> seg_ptr;   // per target box
     std::vector<int32_t> seg_src, seg_mode;
-    std::vector<Task> tasks;
+    std::vector<Task> tasks;        // built for `tile` targets per work item
     int tile = 128;
     int64_t pairs_near = 0, pairs_skel = 0;
 };
 
 Layout make_layout(const Plan& p, bool keep_transparent, int tile);
+// Work list for another tile size (same segments), largest estimated cost first.
+std::vector<Task> make_tasks(const Layout& L, int tile);
+// One layout for several operators: boxes renumbered by (level, operator), entry,
+// skeleton-entry and T offsets shifted, one cost-sorted work list over all of
+// them.  entry_base / hentry_base receive each operator's first entry / skeleton entry.
+Layout merge_layouts(const std::vector<const Layout*>& ls, std::vector<int64_t>& entry_base);
 
 struct DeviceOp;
 struct DeviceBatch;
@@ -67,6 +77,8 @@ void device_apply(DeviceOp* d, const void* q, void* u, int64_t nrhs, int dtype, 
 void device_fill_stats(const DeviceOp* d, skelfmm_stats* out);
 void device_destroy(DeviceOp* d);
 void device_timing(DeviceOp* d, bool enable);
+int device_autotune(DeviceOp* d, int dtype, void* stream, float* ms_out);
+void device_set_tpl(DeviceOp* d, int tpl);
 void device_timing_read(DeviceOp* d, double* ms, int64_t* sweeps);
 
 DeviceBatch* batch_create(const std::vector<DeviceOp*>& ops);

@@ -1,5 +1,14 @@
 // GPU executor: uploads a layout, owns the workspace, enqueues one sweep.
 //
+// A sweep is: gather the caller's charges into the leaf entries; upward pass,
+// one launch per level (deepest first); one near-field launch over every
+// level; downward pass, one launch per level (coarsest first); scatter the
+// leaf entries' potentials to the caller's output.  One right-hand side uses
+// the single-RHS kernels; several use the kernels with lanes (transfers) or
+// registers (near field) over right-hand-side columns.  A batch runs the same
+// sweep over one merged layout of several operators, with one gather and one
+// scatter per operator.
+//
 // The adjoint apply is the transposed sweep.  Transposing each forward step in
 // reverse order gives: the output scatter becomes a gather of v into the leaf
 // entries; the downward pass (uhat += u_parent[slot]; u += [I; T^*] uhat)
@@ -25,13 +34,13 @@
 
 namespace skelfmm {
 
-#define SKF_HIP(x)                                                                          \
-    do {                                                                                    \
-        hipError_t e_ = (x);                                                                \
-        if (e_ != hipSuccess) {                                                             \
+#define SKF_HIP(x)                                                                                 \
+    do {                                                                                           \
+        hipError_t e_ = (x);                                                                       \
+        if (e_ != hipSuccess) {                                                                    \
             if (e_ == hipErrorOutOfMemory) throw OutOfMemory(std::string(#x) + ": out of memory"); \
-            throw DeviceError(std::string(#x) + ": " + hipGetErrorString(e_));             \
-        }                                                                                   \
+            throw DeviceError(std::string(#x) + ": " + hipGetErrorString(e_));                    \
+        }                                                                                          \
     } while (0)
 
 namespace {
@@ -48,10 +57,10 @@ struct DevMem {
         p = nullptr;
         bytes = 0;
     }
+    // 256 spare bytes keep merged wave-uniform loads at the end of an array in bounds
     void alloc(size_t b) {
         release();
-        if (b == 0) b = 16;
-        SKF_HIP(hipMalloc(&p, b));
+        SKF_HIP(hipMalloc(&p, b + 256));
         bytes = b;
     }
     template <class T>
@@ -66,8 +75,20 @@ struct DevMem {
 int dtype_is_complex(int dt) { return dt == SKELFMM_C128 || dt == SKELFMM_C64; }
 int dtype_is_single(int dt) { return dt == SKELFMM_F32 || dt == SKELFMM_C64; }
 
-constexpr int kTPL = 2;              // targets per lane in the near-field kernel
-constexpr int kTile = 64 * kTPL;     // targets per near-field work item
+constexpr int kDefaultTPL = 2;   // targets per lane in the single-RHS near-field kernel (1, 2 or 4)
+constexpr int kChunkReals = 8;   // right-hand-side reals per multi-RHS near-field work item
+
+int tpl_slot(int tpl) { return tpl == 1 ? 0 : (tpl == 2 ? 1 : 2); }
+
+// Values per entry inside the workspace: nv for one RHS; several RHS are padded
+// to a multiple of the near-field chunk.
+int64_t padded_width(int64_t nrhs, int dtype) {
+    const int64_t w = nrhs * (dtype_is_complex(dtype) ? 2 : 1);
+    if (nrhs == 1) return w;
+    return (w + kChunkReals - 1) / kChunkReals * kChunkReals;
+}
+
+inline unsigned blocks_for(int64_t n, int bs) { return static_cast<unsigned>((n + bs - 1) / bs); }
 
 }  // namespace
 
@@ -77,13 +98,13 @@ struct DeviceOp {
     int device = -1;
     bool uploaded = false;
     // static arrays
-    DevMem voff, hoff, toff, nb, kb, is_leaf, level, pmap, perm;
-    DevMem gather_e, gather_p, topleaf_e, topleaf_p;
-    DevMem X64, X32, T64, T32;
-    DevMem seg_ptr, segs, tasks, boxrec;
+    DevMem voff, hoff, toff, nb, kb, pmap, gather_e, gather_p;
+    DevMem X64, X32, ctr, T64, T32, Tt64, Tt32;   // Tt: per-box transposes (multi-RHS downward)
+    DevMem seg_ptr, segs, boxrec;
+    int tpl = kDefaultTPL;
+    DevMem tasks[3];                              // work lists for 1, 2, 4 targets per lane
+    int ntasks[3] = {0, 0, 0};
     // workspace
-    int64_t ws_nrhs = 0;
-    int ws_dtype = -1;
     DevMem Q, Qh, U, Uh;
     // per-pass timing
     bool timing = false;
@@ -98,15 +119,21 @@ struct DeviceOp {
 
 struct DeviceBatch {
     std::vector<DeviceOp*> ops;
+    std::unique_ptr<DeviceOp> merged;
+    std::vector<int64_t> gbase;                   // first gather-list index of each operator
 };
+
+static void check_ranks(const Layout& L) {
+    int kmax = 0;
+    for (int k : L.kb) kmax = std::max(kmax, k);
+    if (kmax > 8192) throw NotSupported("skeleton rank above 8192 is not supported by the downward kernel");
+}
 
 DeviceOp* device_create(const Plan& p, bool keep_transparent, bool f64_leaf) {
     auto d = std::make_unique<DeviceOp>();
-    d->L = make_layout(p, keep_transparent, kTile);
+    d->L = make_layout(p, keep_transparent, 64 * kDefaultTPL);
     d->f64_leaf = f64_leaf;
-    int kmax = 0;
-    for (int k : d->L.kb) kmax = std::max(kmax, k);
-    if (kmax > 8192) throw NotSupported("skeleton rank above 8192 is not supported by the downward kernel");
+    check_ranks(d->L);
     return d.release();
 }
 
@@ -119,79 +146,118 @@ static void upload(DeviceOp* d, int dtype) {
         d->toff.upload(L.toff);
         d->nb.upload(L.nb);
         d->kb.upload(L.kb);
-        d->is_leaf.upload(L.is_leaf);
-        d->level.upload(L.level);
         d->pmap.upload(L.pmap);
-        d->perm.upload(L.perm);
         d->gather_e.upload(L.gather_e);
         d->gather_p.upload(L.gather_p);
-        d->topleaf_e.upload(L.topleaf_e);
-        d->topleaf_p.upload(L.topleaf_p);
         d->seg_ptr.upload(L.seg_ptr);
         std::vector<int2> sg(L.seg_src.size());
         for (size_t i = 0; i < sg.size(); ++i) sg[i] = make_int2(L.seg_src[i], L.seg_mode[i]);
         d->segs.upload(sg);
-        d->tasks.upload(L.tasks);
+        for (int t : {1, 2, 4}) {
+            const std::vector<Task> tl = (64 * t == L.tile) ? L.tasks : make_tasks(L, 64 * t);
+            d->tasks[tpl_slot(t)].upload(tl);
+            d->ntasks[tpl_slot(t)] = static_cast<int>(tl.size());
+        }
+        d->ctr.upload(L.ctr);
         std::vector<kern::BoxRec> br(L.n_boxes);
         for (int b = 0; b < L.n_boxes; ++b)
             br[b] = kern::BoxRec{L.voff[b], L.hoff[b], L.nb[b], L.kb[b], L.level[b], L.is_leaf[b]};
         d->boxrec.upload(br);
+        // float64 coordinates serve float64 applies, f64_leaf applies and the
+        // targets of the float32 relative-coordinate policy
+        d->X64.upload(L.X);
         d->uploaded = true;
     }
     const bool single = dtype_is_single(dtype);
-    const bool need64 = !single || d->f64_leaf;
-    if (need64 && !d->X64.p) d->X64.upload(L.X);
-    if (!need64 && !d->X32.p) {
-        std::vector<float> x32(L.X.begin(), L.X.end());
-        d->X32.upload(x32);
-    }
+    if (single && !d->f64_leaf && !d->X32.p) d->X32.upload(L.Xrel);
     if (!single && !d->T64.p) d->T64.upload(L.T);
-    if (single && !d->T32.p) {
-        std::vector<float> t32(L.T.begin(), L.T.end());
-        d->T32.upload(t32);
+    if (single && !d->T32.p) d->T32.upload(std::vector<float>(L.T.begin(), L.T.end()));
+}
+
+static void upload_transposes(DeviceOp* d, bool single) {
+    const Layout& L = d->L;
+    if ((single && d->Tt32.p) || (!single && d->Tt64.p)) return;
+    std::vector<double> tt(L.T.size());
+    for (int b = 0; b < L.n_boxes; ++b) {
+        const int64_t k = L.kb[b], m = L.nb[b] - L.kb[b];
+        if (k <= 0 || m <= 0) continue;
+        const double* src = L.T.data() + L.toff[b];
+        double* dst = tt.data() + L.toff[b];
+        for (int64_t j = 0; j < m; ++j)
+            for (int64_t i = 0; i < k; ++i) dst[j + i * m] = src[i + j * k];
     }
+    if (single) d->Tt32.upload(std::vector<float>(tt.begin(), tt.end()));
+    else d->Tt64.upload(tt);
 }
 
 void device_prepare(DeviceOp* d, int64_t nrhs, int dtype) {
     upload(d, dtype);
-    const size_t vb = (dtype_is_single(dtype) ? 4 : 8) * (dtype_is_complex(dtype) ? 2 : 1);
-    const size_t need_e = static_cast<size_t>(d->L.n_entries) * nrhs * vb;
-    const size_t need_h = static_cast<size_t>(d->L.n_hentries) * nrhs * vb;
+    if (nrhs > 1) upload_transposes(d, dtype_is_single(dtype));
+    const size_t vb = dtype_is_single(dtype) ? 4 : 8;
+    const size_t wp = static_cast<size_t>(padded_width(nrhs, dtype));
+    const size_t need_e = static_cast<size_t>(d->L.n_entries) * wp * vb;
+    const size_t need_h = static_cast<size_t>(d->L.n_hentries) * wp * vb;
     if (d->Q.bytes < need_e) { d->Q.alloc(need_e); d->U.alloc(need_e); }
     if (d->Qh.bytes < need_h) { d->Qh.alloc(need_h); d->Uh.alloc(need_h); }
-    d->ws_nrhs = std::max(d->ws_nrhs, nrhs);
 }
 
 namespace {
 
 kern::BoxArgs box_args(const DeviceOp* d) {
-    kern::BoxArgs a;
+    kern::BoxArgs a{};
     a.voff = d->voff.as<int64_t>();
     a.hoff = d->hoff.as<int64_t>();
     a.toff = d->toff.as<int64_t>();
     a.nb = d->nb.as<int32_t>();
     a.kb = d->kb.as<int32_t>();
-    a.is_leaf = d->is_leaf.as<int32_t>();
-    a.level = d->level.as<int32_t>();
     a.pmap = d->pmap.as<int32_t>();
-    a.perm = d->perm.as<int32_t>();
     return a;
 }
 
-inline unsigned blocks_for(int64_t n, int bs) { return static_cast<unsigned>((n + bs - 1) / bs); }
+// The caller's buffers of one operator and its range of leaf entries.
+struct IO {
+    const void* q;
+    void* u;
+    int64_t g0;     // first index into the gather lists
+    int64_t cnt;    // number of points
+};
+
+template <class P, int TPL, bool CONJ>
+void launch_near_t(const DeviceOp* d, hipStream_t s, const void* X, void* Q, void* Qh, void* U, void* Uh) {
+    const int ntasks = d->ntasks[tpl_slot(TPL)];
+    if (ntasks == 0) return;
+    using R = typename P::Rt;
+    using V = typename P::Vt;
+    hipLaunchKernelGGL((kern::k_near<P, TPL, CONJ>), dim3(blocks_for(ntasks, 4)), dim3(256), 0, s,
+                       d->tasks[tpl_slot(TPL)].as<Task>(), ntasks, d->seg_ptr.as<int32_t>(), d->segs.as<int2>(),
+                       d->boxrec.as<kern::BoxRec>(), static_cast<const kern::Rec4<R>*>(X),
+                       d->X64.as<kern::Rec4<double>>(), d->ctr.as<double4>(), static_cast<const V*>(Q),
+                       static_cast<const V*>(Qh), static_cast<V*>(U), static_cast<V*>(Uh),
+                       static_cast<R>(d->L.kappa), kern::kInv4Pi);
+    SKF_HIP(hipGetLastError());
+}
 
 template <class P, bool CONJ>
 void launch_near(const DeviceOp* d, hipStream_t s, const void* X, void* Q, void* Qh, void* U, void* Uh) {
-    const Layout& L = d->L;
-    if (L.tasks.empty()) return;
+    if (d->tpl == 1) launch_near_t<P, 1, CONJ>(d, s, X, Q, Qh, U, Uh);
+    else if (d->tpl == 4) launch_near_t<P, 4, CONJ>(d, s, X, Q, Qh, U, Uh);
+    else launch_near_t<P, 2, CONJ>(d, s, X, Q, Qh, U, Uh);
+}
+
+template <class P, bool CONJ, typename Am>
+void launch_near_mr(const DeviceOp* d, hipStream_t s, int Wp, const void* X, void* Q, void* Qh, void* U, void* Uh) {
+    const int ntasks = d->ntasks[tpl_slot(1)];
+    if (ntasks == 0) return;
     using R = typename P::Rt;
     using V = typename P::Vt;
-    const int ntasks = static_cast<int>(L.tasks.size());
-    hipLaunchKernelGGL((kern::k_near<P, kTPL, CONJ>), dim3(blocks_for(ntasks, 4)), dim3(256), 0, s,
-                       d->tasks.as<Task>(), ntasks, L.top, d->seg_ptr.as<int32_t>(), d->segs.as<int2>(),
-                       d->boxrec.as<kern::BoxRec>(), static_cast<const kern::Rec4<R>*>(X),
-                       static_cast<const V*>(Q), static_cast<const V*>(Qh), static_cast<V*>(U),
-                       static_cast<V*>(Uh), static_cast<R>(L.kappa), kern::kInv4Pi);
+    constexpr int NR = kChunkReals / P::nv;
+    const int nchunks = Wp / kChunkReals;
+    hipLaunchKernelGGL((kern::k_near_mr<P, NR, CONJ, Am>), dim3(blocks_for(int64_t(ntasks) * nchunks, 4)),
+                       dim3(256), 0, s, d->tasks[tpl_slot(1)].as<Task>(), ntasks, nchunks, Wp,
+                       d->seg_ptr.as<int32_t>(), d->segs.as<int2>(), d->boxrec.as<kern::BoxRec>(),
+                       static_cast<const kern::Rec4<R>*>(X), d->X64.as<kern::Rec4<double>>(), d->ctr.as<double4>(),
+                       static_cast<const V*>(Q), static_cast<const V*>(Qh), static_cast<V*>(U), static_cast<V*>(Uh),
+                       static_cast<R>(d->L.kappa), kern::kInv4Pi);
     SKF_HIP(hipGetLastError());
 }
 
@@ -212,50 +278,70 @@ struct PassMarks {
     }
 };
 
-// One sweep for nrhs == 1 with value type V (float or double), transfer-matrix
-// type TT, near-field policy P.
-template <typename V, typename TT, class P>
-void sweep(DeviceOp* d, const V* q, V* u, hipStream_t s, bool adjoint, const TT* T, const void* X) {
+// One sweep.  V: stored values; TT: transfer matrices; P: near-field policy;
+// Am: accumulator of one source box's partial sums in the multi-RHS near field.
+template <typename V, typename TT, class P, typename Am>
+void sweep(DeviceOp* d, const std::vector<IO>& io, int64_t nrhs, int dtype, hipStream_t s, bool adjoint,
+           const TT* T, const TT* Tt, const void* X) {
     const Layout& L = d->L;
-    constexpr int nv = P::nv;
-    const int W = nv;
+    const bool multi = nrhs > 1;
+    const int Win = static_cast<int>(nrhs * P::nv);
+    const int Wp = static_cast<int>(padded_width(nrhs, dtype));
     V* Q = d->Q.as<V>();
     V* Qh = d->Qh.as<V>();
     V* U = d->U.as<V>();
     V* Uh = d->Uh.as<V>();
     const kern::BoxArgs ba = box_args(d);
-    const int64_t N = L.n_points;
+    const kern::BoxRec* br = d->boxrec.as<kern::BoxRec>();
+    const int32_t* ge = d->gather_e.as<int32_t>();
+    const int32_t* gp = d->gather_p.as<int32_t>();
     PassMarks pm(d, s);
     pm.mark(0);
-    hipLaunchKernelGGL((kern::k_gather<V, V>), dim3(blocks_for(N * W, 256)), dim3(256), 0, s,
-                       d->gather_e.as<int32_t>(), d->gather_p.as<int32_t>(), N, W, q, Q);
-    SKF_HIP(hipGetLastError());
+    for (const IO& x : io) {
+        if (x.cnt <= 0) continue;
+        hipLaunchKernelGGL((kern::k_gather_pad<V, V>), dim3(blocks_for(x.cnt * Wp, 256)), dim3(256), 0, s,
+                           ge + x.g0, gp + x.g0, x.cnt, Win, Wp, static_cast<const V*>(x.q), Q);
+        SKF_HIP(hipGetLastError());
+    }
     pm.mark(1);
-    for (int l = L.max_level; l > L.top; --l) {
+    for (int l = L.max_level; l >= 2; --l) {
         const int b0 = L.level_ptr[l], nbx = L.level_ptr[l + 1] - b0;
         if (nbx <= 0) continue;
-        hipLaunchKernelGGL((kern::k_upward<V, TT>), dim3(nbx), dim3(256), 0, s, ba, b0, W, T, Q, Qh);
+        if (multi)
+            hipLaunchKernelGGL((kern::k_upward_mr<V, TT>), dim3(nbx), dim3(256), 0, s, br, ba.toff, ba.pmap, b0, Wp,
+                               T, Q, Qh);
+        else
+            hipLaunchKernelGGL((kern::k_upward<V, TT>), dim3(nbx), dim3(256), 0, s, ba, b0, Wp, T, Q, Qh);
         SKF_HIP(hipGetLastError());
     }
     pm.mark(2);
-    if (adjoint && P::kind == 1) launch_near<P, true>(d, s, X, Q, Qh, U, Uh);
-    else launch_near<P, false>(d, s, X, Q, Qh, U, Uh);
+    if (multi) {
+        if (adjoint && P::kind == 1) launch_near_mr<P, true, Am>(d, s, Wp, X, Q, Qh, U, Uh);
+        else launch_near_mr<P, false, Am>(d, s, Wp, X, Q, Qh, U, Uh);
+    } else {
+        if (adjoint && P::kind == 1) launch_near<P, true>(d, s, X, Q, Qh, U, Uh);
+        else launch_near<P, false>(d, s, X, Q, Qh, U, Uh);
+    }
     pm.mark(3);
-    int kmax = 0;
-    for (int l = L.top + 1; l <= L.max_level; ++l) {
+    for (int l = 2; l <= L.max_level; ++l) {
         const int b0 = L.level_ptr[l], nbx = L.level_ptr[l + 1] - b0;
         if (nbx <= 0) continue;
-        kmax = 0;
-        for (int b = b0; b < b0 + nbx; ++b) kmax = std::max(kmax, L.kb[b]);
-        const size_t lds = std::max<size_t>(8, static_cast<size_t>(kmax) * sizeof(double));
-        hipLaunchKernelGGL((kern::k_downward<V, TT, V>), dim3(nbx), dim3(256), lds, s, ba, b0, W, T, Uh, U, u);
+        if (multi) {
+            hipLaunchKernelGGL((kern::k_downward_mr<V, TT>), dim3(nbx), dim3(256), 0, s, br, ba.toff, ba.pmap, b0, Wp,
+                               Tt, Uh, U);
+        } else {
+            int kmax = 0;
+            for (int b = b0; b < b0 + nbx; ++b) kmax = std::max(kmax, L.kb[b]);
+            const size_t lds = std::max<size_t>(8, static_cast<size_t>(kmax) * sizeof(double));
+            hipLaunchKernelGGL((kern::k_downward<V, TT>), dim3(nbx), dim3(256), lds, s, ba, b0, Wp, T, Uh, U);
+        }
         SKF_HIP(hipGetLastError());
     }
     pm.mark(4);
-    const int64_t ntl = static_cast<int64_t>(L.topleaf_e.size());
-    if (ntl > 0) {
-        hipLaunchKernelGGL((kern::k_scatter<V, V>), dim3(blocks_for(ntl * W, 256)), dim3(256), 0, s,
-                           d->topleaf_e.as<int32_t>(), d->topleaf_p.as<int32_t>(), ntl, W, U, u);
+    for (const IO& x : io) {
+        if (x.cnt <= 0) continue;
+        hipLaunchKernelGGL((kern::k_scatter_pad<V, V>), dim3(blocks_for(x.cnt * Win, 256)), dim3(256), 0, s,
+                           ge + x.g0, gp + x.g0, x.cnt, Win, Wp, U, static_cast<V*>(x.u));
         SKF_HIP(hipGetLastError());
     }
     pm.mark(5);
@@ -263,43 +349,100 @@ void sweep(DeviceOp* d, const V* q, V* u, hipStream_t s, bool adjoint, const TT*
 }
 
 template <int DIM, int KIND>
-void dispatch(DeviceOp* d, const void* q, void* u, int dtype, hipStream_t s, bool adjoint) {
+void dispatch(DeviceOp* d, const std::vector<IO>& io, int64_t nrhs, int dtype, hipStream_t s, bool adjoint) {
     if (dtype == SKELFMM_F64 || dtype == SKELFMM_C128) {
         using P = kern::Pol<double, double, double, DIM, KIND>;
-        sweep<double, double, P>(d, static_cast<const double*>(q), static_cast<double*>(u), s, adjoint,
-                                 d->T64.as<double>(), d->X64.p);
+        sweep<double, double, P, double>(d, io, nrhs, dtype, s, adjoint, d->T64.as<double>(), d->Tt64.as<double>(),
+                                         d->X64.p);
     } else if (d->f64_leaf) {
         using P = kern::Pol<double, double, float, DIM, KIND>;
-        sweep<float, float, P>(d, static_cast<const float*>(q), static_cast<float*>(u), s, adjoint,
-                               d->T32.as<float>(), d->X64.p);
+        sweep<float, float, P, double>(d, io, nrhs, dtype, s, adjoint, d->T32.as<float>(), d->Tt32.as<float>(),
+                                       d->X64.p);
     } else {
-        using P = kern::Pol<float, double, float, DIM, KIND>;
-        sweep<float, float, P>(d, static_cast<const float*>(q), static_cast<float*>(u), s, adjoint,
-                               d->T32.as<float>(), d->X32.p);
+        using P = kern::Pol<float, double, float, DIM, KIND, true>;
+        sweep<float, float, P, float>(d, io, nrhs, dtype, s, adjoint, d->T32.as<float>(), d->Tt32.as<float>(),
+                                      d->X32.p);
     }
 }
 
-}  // namespace
-
-void device_apply(DeviceOp* d, const void* q, void* u, int64_t nrhs, int dtype, void* stream, bool adjoint) {
-    if (nrhs != 1) throw NotSupported("this build applies one right-hand side per call");
+void run(DeviceOp* d, const std::vector<IO>& io, int64_t nrhs, int dtype, void* stream, bool adjoint) {
+    if (nrhs > (int64_t(1) << 20)) throw std::invalid_argument("nrhs too large");
     int dev = -1;
     SKF_HIP(hipGetDevice(&dev));
     if (d->uploaded && dev != d->device) throw std::invalid_argument("operator was prepared on another device");
     device_prepare(d, nrhs, dtype);
     hipStream_t s = static_cast<hipStream_t>(stream);
     const Layout& L = d->L;
-    if (L.kind == 1) dispatch<3, 1>(d, q, u, dtype, s, adjoint);
-    else if (L.dim == 3) dispatch<3, 0>(d, q, u, dtype, s, adjoint);
-    else dispatch<2, 0>(d, q, u, dtype, s, adjoint);
+    if (L.kind == 1) dispatch<3, 1>(d, io, nrhs, dtype, s, adjoint);
+    else if (L.dim == 3) dispatch<3, 0>(d, io, nrhs, dtype, s, adjoint);
+    else dispatch<2, 0>(d, io, nrhs, dtype, s, adjoint);
+}
+
+}  // namespace
+
+void device_apply(DeviceOp* d, const void* q, void* u, int64_t nrhs, int dtype, void* stream, bool adjoint) {
+    run(d, {IO{q, u, 0, d->L.n_points}}, nrhs, dtype, stream, adjoint);
+}
+
+// Time the near-field launch for 1, 2 and 4 targets per lane on this operator
+// (workspace contents are whatever the last apply left; timing does not depend
+// on values) and keep the fastest.
+template <int DIM, int KIND>
+static void tune_near(DeviceOp* d, int dtype, hipStream_t s, float* ms_out) {
+    const bool single = dtype_is_single(dtype);
+    for (int t : {1, 2, 4}) {
+        d->tpl = t;
+        hipEvent_t a, b;
+        SKF_HIP(hipEventCreate(&a));
+        SKF_HIP(hipEventCreate(&b));
+        for (int rep = 0; rep < 4; ++rep) {
+            if (rep == 1) SKF_HIP(hipEventRecord(a, s));
+            if (!single) {
+                using P = kern::Pol<double, double, double, DIM, KIND>;
+                launch_near<P, false>(d, s, d->X64.p, d->Q.p, d->Qh.p, d->U.p, d->Uh.p);
+            } else if (d->f64_leaf) {
+                using P = kern::Pol<double, double, float, DIM, KIND>;
+                launch_near<P, false>(d, s, d->X64.p, d->Q.p, d->Qh.p, d->U.p, d->Uh.p);
+            } else {
+                using P = kern::Pol<float, double, float, DIM, KIND, true>;
+                launch_near<P, false>(d, s, d->X32.p, d->Q.p, d->Qh.p, d->U.p, d->Uh.p);
+            }
+        }
+        SKF_HIP(hipEventRecord(b, s));
+        SKF_HIP(hipEventSynchronize(b));
+        float ms = 0.f;
+        SKF_HIP(hipEventElapsedTime(&ms, a, b));
+        ms_out[tpl_slot(t)] = ms / 3.0f;
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+    }
+    int best = 1;
+    for (int t : {1, 2, 4})
+        if (ms_out[tpl_slot(t)] < ms_out[tpl_slot(best)]) best = t;
+    d->tpl = best;
+}
+
+int device_autotune(DeviceOp* d, int dtype, void* stream, float* ms_out) {
+    device_prepare(d, 1, dtype);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const Layout& L = d->L;
+    if (L.kind == 1) tune_near<3, 1>(d, dtype, s, ms_out);
+    else if (L.dim == 3) tune_near<3, 0>(d, dtype, s, ms_out);
+    else tune_near<2, 0>(d, dtype, s, ms_out);
+    return d->tpl;
+}
+
+void device_set_tpl(DeviceOp* d, int tpl) {
+    if (tpl != 1 && tpl != 2 && tpl != 4) throw std::invalid_argument("targets per lane must be 1, 2 or 4");
+    d->tpl = tpl;
 }
 
 void device_fill_stats(const DeviceOp* d, skelfmm_stats* out) {
     out->n_entries = d->L.n_entries;
     out->pairs_near = d->L.pairs_near;
     out->pairs_skel = d->L.pairs_skel;
-    out->n_tasks = static_cast<int64_t>(d->L.tasks.size());
-    out->tile_targets = d->L.tile;
+    out->n_tasks = d->uploaded ? d->ntasks[tpl_slot(d->tpl)] : static_cast<int64_t>(d->L.tasks.size());
+    out->tile_targets = 64 * d->tpl;
 }
 
 void device_destroy(DeviceOp* d) { delete d; }
@@ -330,14 +473,32 @@ void device_timing_read(DeviceOp* d, double* ms, int64_t* sweeps) {
 }
 
 DeviceBatch* batch_create(const std::vector<DeviceOp*>& ops) {
-    auto* b = new DeviceBatch();
+    auto b = std::make_unique<DeviceBatch>();
     b->ops = ops;
-    return b;
+    std::vector<const Layout*> ls;
+    for (auto* o : ops) {
+        ls.push_back(&o->L);
+        if (o->f64_leaf != ops[0]->f64_leaf) throw std::invalid_argument("batched operators must share f64_leaf");
+    }
+    std::vector<int64_t> ebase;
+    b->merged = std::make_unique<DeviceOp>();
+    b->merged->L = merge_layouts(ls, ebase);
+    b->merged->f64_leaf = ops[0]->f64_leaf;
+    check_ranks(b->merged->L);
+    b->gbase.assign(ops.size() + 1, 0);
+    for (size_t i = 0; i < ops.size(); ++i) b->gbase[i + 1] = b->gbase[i] + ops[i]->L.n_points;
+    return b.release();
 }
 
 void batch_apply(DeviceBatch* b, const void* const* q, void* const* u, int64_t nrhs, int dtype, void* stream,
                  bool adjoint) {
-    for (size_t i = 0; i < b->ops.size(); ++i) device_apply(b->ops[i], q[i], u[i], nrhs, dtype, stream, adjoint);
+    std::vector<IO> io;
+    for (size_t i = 0; i < b->ops.size(); ++i) {
+        if (!q[i] || !u[i]) throw std::invalid_argument("NULL vector in batch");
+        if (q[i] == u[i]) throw std::invalid_argument("input and output must not alias");
+        io.push_back(IO{q[i], u[i], b->gbase[i], b->gbase[i + 1] - b->gbase[i]});
+    }
+    run(b->merged.get(), io, nrhs, dtype, stream, adjoint);
 }
 
 void batch_destroy(DeviceBatch* b) { delete b; }

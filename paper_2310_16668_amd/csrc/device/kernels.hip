@@ -53,9 +53,14 @@ __device__ __forceinline__ double two_inv_r(double r2) {
     return fmax(y * e, 0.0);
 }
 __device__ __forceinline__ double inv_r(double r2) { return 0.5 * two_inv_r(r2); }
-__device__ __forceinline__ float inv_r(float r2) {
+// 1/r in float32.  A zero distance can only occur when a box is paired with
+// itself (points at one position fall in one box at every level), so only
+// those segments pay for the r = 0 test (MASK).
+template <bool MASK>
+__device__ __forceinline__ float inv_r_f(float r2) {
     const float y = __builtin_amdgcn_rsqf(r2);
-    return r2 > 0.0f ? y : 0.0f;
+    if constexpr (MASK) return r2 > 0.0f ? y : 0.0f;
+    return y;
 }
 
 // -log(r2) (= -2 log r); zero at r2 = 0
@@ -65,7 +70,7 @@ __device__ __forceinline__ float neg_log_r2(float r2) { return r2 > 0.0f ? -__lo
 __device__ __forceinline__ void sin_cos(double x, double* s, double* c) { sincos(x, s, c); }
 __device__ __forceinline__ void sin_cos(float x, float* s, float* c) { sincosf(x, s, c); }
 
-template <typename R, typename A, typename V, int DIM, int KIND>
+template <typename R, typename A, typename V, int DIM, int KIND, bool REL = false>
 struct Pol {
     using Rt = R;   // coordinates / kernel evaluation
     using At = A;   // accumulators
@@ -73,6 +78,9 @@ struct Pol {
     static constexpr int dim = DIM;
     static constexpr int kind = KIND;   // 0 Laplace, 1 Helmholtz
     static constexpr int nv = KIND == 1 ? 2 : 1;
+    // REL: source coordinates are float32 offsets from their own box centre and
+    // each lane re-expresses its targets relative to the source box per segment
+    static constexpr bool rel = REL;
     // 3D Laplace in float64 evaluates 2/r (see two_inv_r); the factor is undone in the scale
     static constexpr bool twice = DIM == 3 && KIND == 0 && sizeof(R) == 8;
     static constexpr double gscale = twice ? 0.5 : 1.0;
@@ -80,47 +88,27 @@ struct Pol {
 
 // G(x_t, x_s) (times 4 pi for 3D, times 4 pi / 2 for 2D: the common factor is
 // applied once at the end).  Real kernels return gr only.
-template <class P, bool CONJ>
+template <class P, bool CONJ, bool MASK>
 __device__ __forceinline__ void green(typename P::Rt dx, typename P::Rt dy, typename P::Rt dz,
                                       typename P::Rt kappa, typename P::Rt& gr, typename P::Rt& gi) {
     using R = typename P::Rt;
     R r2 = dx * dx;
     r2 = fma(dy, dy, r2);
     if constexpr (P::dim == 3) r2 = fma(dz, dz, r2);
+    R ir;
+    if constexpr (sizeof(R) == 8) ir = (P::twice) ? two_inv_r(r2) : inv_r(r2);
+    else ir = inv_r_f<MASK>(r2);
     if constexpr (P::kind == 0) {
-        if constexpr (P::twice) gr = two_inv_r(r2);
-        else if constexpr (P::dim == 3) gr = inv_r(r2);
-        else gr = neg_log_r2(r2);
+        if constexpr (P::dim == 3) gr = ir;
+        else gr = (sizeof(R) == 8 || MASK) ? neg_log_r2(r2) : -__logf(r2);
         gi = R(0);
     } else {
-        const R ir = inv_r(r2);
         const R r = r2 * ir;
         R s, c;
         sin_cos(kappa * r, &s, &c);
         gr = c * ir;
         gi = CONJ ? -s * ir : s * ir;
     }
-}
-
-// ---------------------------------------------------------------------------
-// gather / scatter of leaf entries
-// ---------------------------------------------------------------------------
-template <typename VI, typename VO>
-__global__ void k_gather(const int32_t* __restrict__ dst_e, const int32_t* __restrict__ src_p, int64_t cnt,
-                         int W, const VI* __restrict__ in, VO* __restrict__ out) {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= cnt * W) return;
-    const int64_t r = i / W, c = i - r * W;
-    out[static_cast<int64_t>(dst_e[r]) * W + c] = static_cast<VO>(in[static_cast<int64_t>(src_p[r]) * W + c]);
-}
-
-template <typename VI, typename VO>
-__global__ void k_scatter(const int32_t* __restrict__ src_e, const int32_t* __restrict__ dst_p, int64_t cnt,
-                          int W, const VI* __restrict__ in, VO* __restrict__ out) {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= cnt * W) return;
-    const int64_t r = i / W, c = i - r * W;
-    out[static_cast<int64_t>(dst_p[r]) * W + c] = static_cast<VO>(in[static_cast<int64_t>(src_e[r]) * W + c]);
 }
 
 // ---------------------------------------------------------------------------
@@ -134,10 +122,7 @@ struct BoxArgs {
     const int64_t* toff;
     const int32_t* nb;
     const int32_t* kb;
-    const int32_t* is_leaf;
-    const int32_t* level;
     const int32_t* pmap;
-    const int32_t* perm;
 };
 
 template <typename V, typename TT>
@@ -175,30 +160,25 @@ __global__ void __launch_bounds__(256) k_upward(BoxArgs a, int b0, int W, const 
 // ---------------------------------------------------------------------------
 // downward pass, one block per box of a level:
 //   uhat = Uh + U_parent[pmap]; u[i] += uhat[i] (i < k); u[k+j] += sum_i T[i + j k] uhat[i]
-// a leaf writes its final potential to the caller's output instead of U.
 // Columns of T are contiguous: a wave reads a column with consecutive lanes
 // and reduces across the wave.
 // ---------------------------------------------------------------------------
-template <typename V, typename TT, typename VO>
+template <typename V, typename TT>
 __global__ void __launch_bounds__(256) k_downward(BoxArgs a, int b0, int W, const TT* __restrict__ T,
-                                                 const V* __restrict__ Uh, V* __restrict__ U,
-                                                 VO* __restrict__ out) {
+                                                 const V* __restrict__ Uh, V* __restrict__ U) {
     extern __shared__ double uh_s[];
     const int b = b0 + blockIdx.x;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t voff = a.voff[b], hoff = a.hoff[b];
     const int n = a.nb[b], k = a.kb[b];
     const int m = n - k;
-    const bool leaf = a.is_leaf[b] != 0;
     const TT* Tb = T + a.toff[b];
     for (int c = 0; c < W; ++c) {
         for (int i = threadIdx.x; i < k; i += blockDim.x) {
             const double uh = static_cast<double>(Uh[(hoff + i) * W + c]) +
                               static_cast<double>(U[static_cast<int64_t>(a.pmap[hoff + i]) * W + c]);
             uh_s[i] = uh;
-            const double u = static_cast<double>(U[(voff + i) * W + c]) + uh;
-            if (leaf) out[static_cast<int64_t>(a.perm[voff + i]) * W + c] = static_cast<VO>(u);
-            else U[(voff + i) * W + c] = static_cast<V>(u);
+            U[(voff + i) * W + c] = static_cast<V>(static_cast<double>(U[(voff + i) * W + c]) + uh);
         }
         __syncthreads();
         for (int j = wave; j < m; j += 4) {
@@ -206,11 +186,8 @@ __global__ void __launch_bounds__(256) k_downward(BoxArgs a, int b0, int W, cons
             double acc = 0.0;
             for (int i = lane; i < k; i += 64) acc = fma(static_cast<double>(col[i]), uh_s[i], acc);
             for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-            if (lane == 0) {
-                const double u = static_cast<double>(U[(voff + k + j) * W + c]) + acc;
-                if (leaf) out[static_cast<int64_t>(a.perm[voff + k + j]) * W + c] = static_cast<VO>(u);
-                else U[(voff + k + j) * W + c] = static_cast<V>(u);
-            }
+            if (lane == 0)
+                U[(voff + k + j) * W + c] = static_cast<V>(static_cast<double>(U[(voff + k + j) * W + c]) + acc);
         }
         __syncthreads();
     }
@@ -230,7 +207,7 @@ struct alignas(32) BoxRec {
 };
 
 // MODE 0: u += G w ;  1: u += G w, uh -= G wh ;  2: u += G w, uh -= G w ;  3: u += G (w - wh)
-template <class P, int TPL, bool CONJ, int MODE>
+template <class P, int TPL, bool CONJ, int MODE, bool MASK>
 __device__ __forceinline__ void near_loop(const Rec4<typename P::Rt>* __restrict__ X,
                                           const typename P::Vt* __restrict__ Q,
                                           const typename P::Vt* __restrict__ Qh, int s0, int s1,
@@ -254,7 +231,7 @@ __device__ __forceinline__ void near_loop(const Rec4<typename P::Rt>* __restrict
 #pragma unroll
         for (int p = 0; p < TPL; ++p) {
             R gr, gi;
-            green<P, CONJ>(xt[p] - xs.x, yt[p] - xs.y, zt[p] - xs.z, kappa, gr, gi);
+            green<P, CONJ, MASK>(xt[p] - xs.x, yt[p] - xs.y, zt[p] - xs.z, kappa, gr, gi);
             const A g = static_cast<A>(gr);
             if constexpr (nv == 1) {
                 acc[p][0] = fma(g, w[0], acc[p][0]);
@@ -277,14 +254,44 @@ __device__ __forceinline__ void near_loop(const Rec4<typename P::Rt>* __restrict
     }
 }
 
+// All translation types of one source box into the lane's targets.
+template <class P, int TPL, bool CONJ, bool MASK>
+__device__ __forceinline__ void near_segment(int mode, bool has_h, const Rec4<typename P::Rt>* __restrict__ Xs,
+                                             const typename P::Vt* __restrict__ Qs,
+                                             const typename P::Vt* __restrict__ Qhs, int sn, int sk,
+                                             typename P::Rt kappa,
+                                             const typename P::Rt (&xt)[TPL], const typename P::Rt (&yt)[TPL],
+                                             const typename P::Rt (&zt)[TPL],
+                                             typename P::At (&acc)[TPL][P::nv], typename P::At (&acch)[TPL][P::nv]) {
+    if (mode == SEG_IFO) {
+        if (has_h) {
+            near_loop<P, TPL, CONJ, 1, MASK>(Xs, Qs, Qhs, 0, sk, kappa, xt, yt, zt, acc, acch);
+            near_loop<P, TPL, CONJ, 0, MASK>(Xs, Qs, Qhs, sk, sn, kappa, xt, yt, zt, acc, acch);
+        } else {
+            near_loop<P, TPL, CONJ, 0, MASK>(Xs, Qs, Qhs, 0, sn, kappa, xt, yt, zt, acc, acch);
+        }
+    } else if (mode == SEG_IFS) {
+        if (has_h) near_loop<P, TPL, CONJ, 2, MASK>(Xs, Qs, Qhs, 0, sn, kappa, xt, yt, zt, acc, acch);
+        else near_loop<P, TPL, CONJ, 0, MASK>(Xs, Qs, Qhs, 0, sn, kappa, xt, yt, zt, acc, acch);
+    } else if (mode == SEG_TFO) {
+        near_loop<P, TPL, CONJ, 3, MASK>(Xs, Qs, Qhs, 0, sk, kappa, xt, yt, zt, acc, acch);
+        near_loop<P, TPL, CONJ, 0, MASK>(Xs, Qs, Qhs, sk, sn, kappa, xt, yt, zt, acc, acch);
+    } else {
+        near_loop<P, TPL, CONJ, 0, MASK>(Xs, Qs, Qhs, 0, sn, kappa, xt, yt, zt, acc, acch);
+    }
+}
+
 // One wavefront per work item; every pointer is a separate restrict argument so
 // the compiler can prove the source data is never written by this kernel and
-// read it with scalar loads.
+// read it with scalar loads.  Segment modes carry SEG_SELF when the source box
+// is the target box.
 template <class P, int TPL, bool CONJ>
-__global__ void __launch_bounds__(256) k_near(const Task* __restrict__ tasks, int ntasks, int top,
+__global__ void __launch_bounds__(256) k_near(const Task* __restrict__ tasks, int ntasks,
                                               const int32_t* __restrict__ seg_ptr, const int2* __restrict__ segs,
                                               const BoxRec* __restrict__ box,
                                               const Rec4<typename P::Rt>* __restrict__ X,
+                                              const Rec4<double>* __restrict__ X64,
+                                              const double4* __restrict__ ctr,
                                               const typename P::Vt* __restrict__ Q,
                                               const typename P::Vt* __restrict__ Qh,
                                               typename P::Vt* __restrict__ U, typename P::Vt* __restrict__ Uh,
@@ -298,15 +305,22 @@ __global__ void __launch_bounds__(256) k_near(const Task* __restrict__ tasks, in
     if (tid >= ntasks) return;
     const Task tk = tasks[tid];
     const BoxRec tb = box[tk.box];
-    const bool has_h = tb.level > top && tk.t0 < tb.k;
+    // boxes at or above the top level carry k = 0: no skeleton part
+    const bool has_h = tk.t0 < tb.k;
 
     R xt[TPL], yt[TPL], zt[TPL];
+    double xd[TPL], yd[TPL], zd[TPL];
     A acc[TPL][nv], acch[TPL][nv];
 #pragma unroll
     for (int p = 0; p < TPL; ++p) {
         const int t = min(tk.t0 + lane + 64 * p, tb.n - 1);
-        const Rec4<R> x = X[tb.voff + t];
-        xt[p] = x.x; yt[p] = x.y; zt[p] = x.z;
+        if constexpr (P::rel) {
+            const Rec4<double> x = X64[tb.voff + t];
+            xd[p] = x.x; yd[p] = x.y; zd[p] = x.z;
+        } else {
+            const Rec4<R> x = X[tb.voff + t];
+            xt[p] = x.x; yt[p] = x.y; zt[p] = x.z;
+        }
 #pragma unroll
         for (int v = 0; v < nv; ++v) { acc[p][v] = A(0); acch[p][v] = A(0); }
     }
@@ -314,25 +328,23 @@ __global__ void __launch_bounds__(256) k_near(const Task* __restrict__ tasks, in
     for (int e = seg_ptr[tk.box]; e < e1; ++e) {
         const int2 sg = segs[e];
         const BoxRec sb = box[sg.x];
+        if constexpr (P::rel) {
+            const double4 c = ctr[sg.x];
+#pragma unroll
+            for (int p = 0; p < TPL; ++p) {
+                xt[p] = static_cast<R>(xd[p] - c.x);
+                yt[p] = static_cast<R>(yd[p] - c.y);
+                zt[p] = static_cast<R>(zd[p] - c.z);
+            }
+        }
         const Rec4<R>* Xs = X + sb.voff;
         const V* Qs = Q + sb.voff * nv;
         const V* Qhs = Qh + sb.hoff * nv;
-        if (sg.y == SEG_IFO) {
-            if (has_h) {
-                near_loop<P, TPL, CONJ, 1>(Xs, Qs, Qhs, 0, sb.k, kappa, xt, yt, zt, acc, acch);
-                near_loop<P, TPL, CONJ, 0>(Xs, Qs, Qhs, sb.k, sb.n, kappa, xt, yt, zt, acc, acch);
-            } else {
-                near_loop<P, TPL, CONJ, 0>(Xs, Qs, Qhs, 0, sb.n, kappa, xt, yt, zt, acc, acch);
-            }
-        } else if (sg.y == SEG_IFS) {
-            if (has_h) near_loop<P, TPL, CONJ, 2>(Xs, Qs, Qhs, 0, sb.n, kappa, xt, yt, zt, acc, acch);
-            else near_loop<P, TPL, CONJ, 0>(Xs, Qs, Qhs, 0, sb.n, kappa, xt, yt, zt, acc, acch);
-        } else if (sg.y == SEG_TFO) {
-            near_loop<P, TPL, CONJ, 3>(Xs, Qs, Qhs, 0, sb.k, kappa, xt, yt, zt, acc, acch);
-            near_loop<P, TPL, CONJ, 0>(Xs, Qs, Qhs, sb.k, sb.n, kappa, xt, yt, zt, acc, acch);
-        } else {
-            near_loop<P, TPL, CONJ, 0>(Xs, Qs, Qhs, 0, sb.n, kappa, xt, yt, zt, acc, acch);
-        }
+        const int mode = sg.y & SEG_MODE_MASK;
+        if (sg.y & SEG_SELF)
+            near_segment<P, TPL, CONJ, true>(mode, has_h, Xs, Qs, Qhs, sb.n, sb.k, kappa, xt, yt, zt, acc, acch);
+        else
+            near_segment<P, TPL, CONJ, false>(mode, has_h, Xs, Qs, Qhs, sb.n, sb.k, kappa, xt, yt, zt, acc, acch);
     }
     const A sc = static_cast<A>(scale * P::gscale);
 #pragma unroll
@@ -345,6 +357,273 @@ __global__ void __launch_bounds__(256) k_near(const Task* __restrict__ tasks, in
 #pragma unroll
                 for (int v = 0; v < nv; ++v) Uh[(tb.hoff + t) * nv + v] = static_cast<V>(acch[p][v] * sc);
             }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// many right-hand sides
+// ---------------------------------------------------------------------------
+// Gather / scatter between the caller's n x Win vectors and the leaf entries of
+// the n_entries x Wp workspace (Wp = Win for one RHS; for several, Wp is a
+// multiple of the RHS chunk, the gather zero-fills the padding and the scatter
+// writes only the caller's columns).
+template <typename VI, typename VO>
+__global__ void k_gather_pad(const int32_t* __restrict__ dst_e, const int32_t* __restrict__ src_p, int64_t cnt,
+                             int Win, int Wp, const VI* __restrict__ in, VO* __restrict__ out) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= cnt * Wp) return;
+    const int64_t r = i / Wp, c = i - r * Wp;
+    out[static_cast<int64_t>(dst_e[r]) * Wp + c] =
+        c < Win ? static_cast<VO>(in[static_cast<int64_t>(src_p[r]) * Win + c]) : VO(0);
+}
+
+template <typename VI, typename VO>
+__global__ void k_scatter_pad(const int32_t* __restrict__ src_e, const int32_t* __restrict__ dst_p, int64_t cnt,
+                              int Win, int Wp, const VI* __restrict__ in, VO* __restrict__ out) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= cnt * Win) return;
+    const int64_t r = i / Win, c = i - r * Win;
+    out[static_cast<int64_t>(dst_p[r]) * Win + c] = static_cast<VO>(in[static_cast<int64_t>(src_e[r]) * Wp + c]);
+}
+
+// Transfer with lanes over right-hand-side columns:
+//   acc[rr] = sum_j A[r0 + rr + j lda] x[j]   for the wave's RB rows
+// A is column-major (contiguous along rows), so the RB coefficients of one
+// column are one wave-uniform scalar load; x rows are coalesced vector loads.
+constexpr int kRB = 16;
+
+// upward: qhat = q[0:k] + T q[k:n]  (T column-major k x m)
+template <typename V, typename TT>
+__global__ void __launch_bounds__(256) k_upward_mr(const BoxRec* __restrict__ box, const int64_t* __restrict__ toff,
+                                                  const int32_t* __restrict__ pmap, int b0, int Wp,
+                                                  const TT* __restrict__ T, V* __restrict__ Q,
+                                                  V* __restrict__ Qh) {
+    const int b = b0 + blockIdx.x;
+    const BoxRec tb = box[b];
+    const int k = tb.k, m = tb.n - tb.k;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const TT* __restrict__ Tb = T + toff[b];
+    for (int c0 = 0; c0 < Wp; c0 += 64) {
+        const int c = c0 + lane;
+        const bool act = c < Wp;
+        for (int r0 = wave * kRB; r0 < k; r0 += 4 * kRB) {
+            double acc[kRB];
+#pragma unroll
+            for (int rr = 0; rr < kRB; ++rr) acc[rr] = 0.0;
+            const int nr = min(kRB, k - r0);
+            for (int j = 0; j < m; ++j) {
+                const double x = act ? static_cast<double>(Q[(tb.voff + k + j) * Wp + c]) : 0.0;
+                const TT* col = Tb + r0 + static_cast<int64_t>(j) * k;
+                if (nr == kRB) {
+#pragma unroll
+                    for (int rr = 0; rr < kRB; ++rr) acc[rr] = fma(static_cast<double>(col[rr]), x, acc[rr]);
+                } else {
+#pragma unroll
+                    for (int rr = 0; rr < kRB; ++rr)
+                        if (rr < nr) acc[rr] = fma(static_cast<double>(col[rr]), x, acc[rr]);
+                }
+            }
+            if (act) {
+#pragma unroll
+                for (int rr = 0; rr < kRB; ++rr) {
+                    const int r = r0 + rr;
+                    if (rr < nr) {
+                        const V v = static_cast<V>(static_cast<double>(Q[(tb.voff + r) * Wp + c]) + acc[rr]);
+                        Qh[(tb.hoff + r) * Wp + c] = v;
+                        Q[static_cast<int64_t>(pmap[tb.hoff + r]) * Wp + c] = v;
+                    }
+                }
+            }
+        }
+    }
+}
+
+// downward: uhat = Uh + U_parent[pmap]; u[0:k] += uhat; u[k:n] += T^T uhat.
+// Tt holds T transposed (column-major m x k) so the second step has the same
+// shape as the upward transfer.
+template <typename V, typename TT>
+__global__ void __launch_bounds__(256) k_downward_mr(const BoxRec* __restrict__ box, const int64_t* __restrict__ toff,
+                                                    const int32_t* __restrict__ pmap, int b0, int Wp,
+                                                    const TT* __restrict__ Tt, const V* __restrict__ Uh,
+                                                    V* __restrict__ U) {
+    const int b = b0 + blockIdx.x;
+    const BoxRec tb = box[b];
+    const int k = tb.k, m = tb.n - tb.k;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const TT* __restrict__ Tb = Tt + toff[b];
+    for (int c0 = 0; c0 < Wp; c0 += 64) {
+        const int c = c0 + lane;
+        const bool act = c < Wp;
+        // redundant rows (reads uhat inputs: this box's Uh and the parent's U,
+        // never this box's own skeleton entries, which the loop after updates)
+        for (int r0 = wave * kRB; r0 < m; r0 += 4 * kRB) {
+            double acc[kRB];
+#pragma unroll
+            for (int rr = 0; rr < kRB; ++rr) acc[rr] = 0.0;
+            const int nr = min(kRB, m - r0);
+            for (int i = 0; i < k; ++i) {
+                const double x = act ? static_cast<double>(Uh[(tb.hoff + i) * Wp + c]) +
+                                           static_cast<double>(U[static_cast<int64_t>(pmap[tb.hoff + i]) * Wp + c])
+                                     : 0.0;
+                const TT* col = Tb + r0 + static_cast<int64_t>(i) * m;
+                if (nr == kRB) {
+#pragma unroll
+                    for (int rr = 0; rr < kRB; ++rr) acc[rr] = fma(static_cast<double>(col[rr]), x, acc[rr]);
+                } else {
+#pragma unroll
+                    for (int rr = 0; rr < kRB; ++rr)
+                        if (rr < nr) acc[rr] = fma(static_cast<double>(col[rr]), x, acc[rr]);
+                }
+            }
+            if (act) {
+#pragma unroll
+                for (int rr = 0; rr < kRB; ++rr) {
+                    if (rr >= nr) continue;
+                    const int64_t e = tb.voff + k + r0 + rr;
+                    U[e * Wp + c] = static_cast<V>(static_cast<double>(U[e * Wp + c]) + acc[rr]);
+                }
+            }
+        }
+        // skeleton rows
+        for (int i = wave; i < k && act; i += 4) {
+            const double uh = static_cast<double>(Uh[(tb.hoff + i) * Wp + c]) +
+                              static_cast<double>(U[static_cast<int64_t>(pmap[tb.hoff + i]) * Wp + c]);
+            U[(tb.voff + i) * Wp + c] = static_cast<V>(static_cast<double>(U[(tb.voff + i) * Wp + c]) + uh);
+        }
+    }
+}
+
+// Near field for NR right-hand sides per work item (one chunk of Wp): the
+// kernel value of a pair is computed once and applied to NR columns.  Partial
+// sums of one source box accumulate in Am (float32 for the single-precision
+// policies) and are added to float64 totals at the end of the box.
+template <class P, int NR, bool CONJ, int MODE, bool MASK, typename Am>
+__device__ __forceinline__ void near_loop_mr(const Rec4<typename P::Rt>* __restrict__ X,
+                                             const typename P::Vt* __restrict__ Q,
+                                             const typename P::Vt* __restrict__ Qh, int Wp, int s0, int s1,
+                                             typename P::Rt kappa, typename P::Rt xt, typename P::Rt yt,
+                                             typename P::Rt zt, Am (&pu)[NR * P::nv], Am (&ph)[NR * P::nv]) {
+    using R = typename P::Rt;
+    constexpr int nv = P::nv;
+    for (int s = s0; s < s1; ++s) {
+        const Rec4<R> xs = X[s];
+        R gr, gi;
+        green<P, CONJ, MASK>(xt - xs.x, yt - xs.y, zt - xs.z, kappa, gr, gi);
+        const Am g = static_cast<Am>(gr);
+        const typename P::Vt* __restrict__ w = Q + static_cast<int64_t>(s) * Wp;
+        const typename P::Vt* __restrict__ wh = Qh + static_cast<int64_t>(s) * Wp;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            if constexpr (nv == 1) {
+                Am a = static_cast<Am>(w[r]);
+                if constexpr (MODE == 3) a -= static_cast<Am>(wh[r]);
+                pu[r] = fma(g, a, pu[r]);
+                if constexpr (MODE == 1) ph[r] = fma(-g, static_cast<Am>(wh[r]), ph[r]);
+                if constexpr (MODE == 2) ph[r] = fma(-g, a, ph[r]);
+            } else {
+                const Am h = static_cast<Am>(gi);
+                Am a0 = static_cast<Am>(w[2 * r]), a1 = static_cast<Am>(w[2 * r + 1]);
+                if constexpr (MODE == 3) { a0 -= static_cast<Am>(wh[2 * r]); a1 -= static_cast<Am>(wh[2 * r + 1]); }
+                pu[2 * r] = fma(g, a0, fma(-h, a1, pu[2 * r]));
+                pu[2 * r + 1] = fma(g, a1, fma(h, a0, pu[2 * r + 1]));
+                if constexpr (MODE == 1) {
+                    const Am b0 = static_cast<Am>(wh[2 * r]), b1 = static_cast<Am>(wh[2 * r + 1]);
+                    ph[2 * r] = fma(-g, b0, fma(h, b1, ph[2 * r]));
+                    ph[2 * r + 1] = fma(-g, b1, fma(-h, b0, ph[2 * r + 1]));
+                }
+                if constexpr (MODE == 2) {
+                    ph[2 * r] = fma(-g, a0, fma(h, a1, ph[2 * r]));
+                    ph[2 * r + 1] = fma(-g, a1, fma(-h, a0, ph[2 * r + 1]));
+                }
+            }
+        }
+    }
+}
+
+template <class P, int NR, bool CONJ, typename Am>
+__global__ void __launch_bounds__(256) k_near_mr(const Task* __restrict__ tasks, int ntasks, int nchunks,
+                                                 int Wp, const int32_t* __restrict__ seg_ptr,
+                                                 const int2* __restrict__ segs, const BoxRec* __restrict__ box,
+                                                 const Rec4<typename P::Rt>* __restrict__ X,
+                                                 const Rec4<double>* __restrict__ X64,
+                                                 const double4* __restrict__ ctr,
+                                                 const typename P::Vt* __restrict__ Q,
+                                                 const typename P::Vt* __restrict__ Qh,
+                                                 typename P::Vt* __restrict__ U, typename P::Vt* __restrict__ Uh,
+                                                 typename P::Rt kappa, double scale) {
+    using R = typename P::Rt;
+    using V = typename P::Vt;
+    constexpr int nv = P::nv;
+    constexpr int NW = NR * nv;
+    const int lane = threadIdx.x & 63;
+    const int wid = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (wid >= ntasks * nchunks) return;
+    const int chunk = wid % nchunks;
+    const Task tk = tasks[wid / nchunks];
+    const BoxRec tb = box[tk.box];
+    // boxes at or above the top level carry k = 0: no skeleton part
+    const bool has_h = tk.t0 < tb.k;
+    const int c0 = chunk * NW;
+    const int t = min(tk.t0 + lane, tb.n - 1);
+    R xt, yt, zt;
+    double xd = 0, yd = 0, zd = 0;
+    if constexpr (P::rel) {
+        const Rec4<double> x = X64[tb.voff + t];
+        xd = x.x; yd = x.y; zd = x.z;
+    } else {
+        const Rec4<R> x = X[tb.voff + t];
+        xt = x.x; yt = x.y; zt = x.z;
+    }
+    double au[NW], ah[NW];
+#pragma unroll
+    for (int v = 0; v < NW; ++v) { au[v] = 0.0; ah[v] = 0.0; }
+    const int e1 = seg_ptr[tk.box + 1];
+    for (int e = seg_ptr[tk.box]; e < e1; ++e) {
+        const int2 sg = segs[e];
+        const BoxRec sb = box[sg.x];
+        if constexpr (P::rel) {
+            const double4 cc = ctr[sg.x];
+            xt = static_cast<R>(xd - cc.x); yt = static_cast<R>(yd - cc.y); zt = static_cast<R>(zd - cc.z);
+        }
+        const Rec4<R>* Xs = X + sb.voff;
+        const V* Qs = Q + sb.voff * Wp + c0;
+        const V* Qhs = Qh + sb.hoff * Wp + c0;
+        const int mode = sg.y & SEG_MODE_MASK;
+        Am pu[NW], ph[NW];
+#pragma unroll
+        for (int v = 0; v < NW; ++v) { pu[v] = Am(0); ph[v] = Am(0); }
+        const bool self = (sg.y & SEG_SELF) != 0;
+#define SKF_MR(MD, A0, A1)                                                                                 \
+        do {                                                                                               \
+            if (self) near_loop_mr<P, NR, CONJ, MD, true, Am>(Xs, Qs, Qhs, Wp, A0, A1, kappa, xt, yt, zt, pu, ph); \
+            else near_loop_mr<P, NR, CONJ, MD, false, Am>(Xs, Qs, Qhs, Wp, A0, A1, kappa, xt, yt, zt, pu, ph);    \
+        } while (0)
+        if (mode == SEG_IFO) {
+            if (has_h) { SKF_MR(1, 0, sb.k); SKF_MR(0, sb.k, sb.n); }
+            else SKF_MR(0, 0, sb.n);
+        } else if (mode == SEG_IFS) {
+            if (has_h) SKF_MR(2, 0, sb.n);
+            else SKF_MR(0, 0, sb.n);
+        } else if (mode == SEG_TFO) {
+            SKF_MR(3, 0, sb.k); SKF_MR(0, sb.k, sb.n);
+        } else {
+            SKF_MR(0, 0, sb.n);
+        }
+#undef SKF_MR
+#pragma unroll
+        for (int v = 0; v < NW; ++v) { au[v] += static_cast<double>(pu[v]); ah[v] += static_cast<double>(ph[v]); }
+    }
+    const double sc = scale * P::gscale;
+    const int tt = tk.t0 + lane;
+    if (tt < tb.n) {
+#pragma unroll
+        for (int v = 0; v < NW; ++v) U[(tb.voff + tt) * Wp + c0 + v] = static_cast<V>(au[v] * sc);
+        if (has_h && tt < tb.k) {
+#pragma unroll
+            for (int v = 0; v < NW; ++v) Uh[(tb.hoff + tt) * Wp + c0 + v] = static_cast<V>(ah[v] * sc);
         }
     }
 }

@@ -23,6 +23,8 @@
 // pair is skipped unless requested; likewise an ifs pair with a transparent
 // target and a tfo pair with a transparent source.
 #include <algorithm>
+#include <cmath>
+#include <tuple>
 #include <numeric>
 #include <stdexcept>
 
@@ -68,8 +70,16 @@ Layout make_layout(const Plan& p, bool keep_transparent, int tile) {
     L.n_hentries = h;
     if (e >= (int64_t(1) << 31)) throw std::runtime_error("too many entries for 32-bit maps");
 
-    // entry coordinates and leaf permutation
+    // box centres (root-centred)
+    L.ctr.assign(static_cast<size_t>(nb) * 4, 0.0);
+    for (int b = 0; b < nb; ++b) {
+        const double a = std::ldexp(p.root_side, -p.level[b]);
+        for (int d = 0; d < p.dim; ++d)
+            L.ctr[4 * b + d] = p.root_lo[d] + (p.coord[3 * b + d] + 0.5) * a - L.center[d];
+    }
+    // entry coordinates (root-centred, and relative to the owning box) and leaf permutation
     L.X.assign(static_cast<size_t>(e) * 4, 0.0);
+    L.Xrel.assign(static_cast<size_t>(e) * 4, 0.0f);
     L.perm.assign(e, -1);
     for (int b = 0; b < nb; ++b) {
         const int64_t n = L.nb[b];
@@ -78,7 +88,11 @@ Layout make_layout(const Plan& p, bool keep_transparent, int tile) {
         for (int64_t i = 0; i < n; ++i) {
             const int64_t pt = ix[ps[i]];
             double* x = &L.X[static_cast<size_t>(L.voff[b] + i) * 4];
-            for (int d = 0; d < p.dim; ++d) x[d] = p.pts[pt * p.dim + d] - L.center[d];
+            float* xr = &L.Xrel[static_cast<size_t>(L.voff[b] + i) * 4];
+            for (int d = 0; d < p.dim; ++d) {
+                x[d] = p.pts[pt * p.dim + d] - L.center[d];
+                xr[d] = static_cast<float>(x[d] - L.ctr[4 * b + d]);
+            }
             if (p.is_leaf[b]) L.perm[L.voff[b] + i] = static_cast<int32_t>(pt);
         }
         if (p.is_leaf[b]) {
@@ -124,12 +138,16 @@ Layout make_layout(const Plan& p, bool keep_transparent, int tile) {
         const int lb = p.level[b];
         if (lb >= p.top_level) {
             if (lb == p.top_level) {
-                for (int c : top_boxes) { L.seg_src.push_back(c); L.seg_mode.push_back(SEG_DIRECT); }
+                for (int c : top_boxes) {
+                    L.seg_src.push_back(c);
+                    L.seg_mode.push_back(SEG_DIRECT | (c == b ? SEG_SELF : 0));
+                }
             } else {
                 for (int x = p.coll_ptr[b]; x < p.coll_ptr[b + 1]; ++x) {
                     const int c = p.coll_idx[x];
                     if (!keep_transparent && transparent(b) && transparent(c)) continue;
-                    L.seg_src.push_back(c); L.seg_mode.push_back(SEG_IFO);
+                    L.seg_src.push_back(c);
+                    L.seg_mode.push_back(SEG_IFO | (c == b ? SEG_SELF : 0));
                 }
                 for (int x = p.coarse_ptr[b]; x < p.coarse_ptr[b + 1]; ++x) {
                     const int c = p.coarse_idx[x];
@@ -147,29 +165,131 @@ Layout make_layout(const Plan& p, bool keep_transparent, int tile) {
         L.seg_ptr[b + 1] = static_cast<int32_t>(L.seg_src.size());
     }
 
-    // work list: tiles of every target box, largest estimated cost first
-    std::vector<std::pair<int64_t, Task>> work;
+    // work list and pair counts
+    L.tasks = make_tasks(L, tile);
     for (int b = 0; b < nb; ++b) {
-        if (p.level[b] < p.top_level || L.nb[b] == 0) continue;
+        if (L.level[b] < L.top || L.nb[b] == 0) continue;
         int64_t src = 0, skel_src = 0;
         for (int x = L.seg_ptr[b]; x < L.seg_ptr[b + 1]; ++x) {
             const int c = L.seg_src[x];
+            const int mode = L.seg_mode[x] & SEG_MODE_MASK;
             src += L.nb[c];
-            if (L.seg_mode[x] == SEG_IFO) skel_src += L.kb[c];
-            if (L.seg_mode[x] == SEG_IFS) skel_src += L.nb[c];
+            if (mode == SEG_IFO) skel_src += L.kb[c];
+            if (mode == SEG_IFS) skel_src += L.nb[c];
         }
-        for (int t0 = 0; t0 < L.nb[b]; t0 += tile) {
-            const int nt = std::min(tile, L.nb[b] - t0);
-            const int nh = std::max(0, std::min(L.kb[b] - t0, nt));
-            L.pairs_near += int64_t(nt) * src;
-            L.pairs_skel += int64_t(nh) * skel_src;
-            work.push_back({int64_t(tile) * src + 64, Task{b, t0}});
+        L.pairs_near += int64_t(L.nb[b]) * src;
+        L.pairs_skel += int64_t(std::min(L.kb[b], L.nb[b])) * skel_src;
+    }
+    return L;
+}
+
+Layout merge_layouts(const std::vector<const Layout*>& ls, std::vector<int64_t>& entry_base) {
+    Layout M;
+    const Layout& L0 = *ls[0];
+    M.dim = L0.dim;
+    M.kind = L0.kind;
+    M.kappa = L0.kappa;
+    M.tile = L0.tile;
+    M.top = L0.top;
+    const int nops = static_cast<int>(ls.size());
+    std::vector<int> box_base(nops + 1, 0);
+    std::vector<int64_t> hbase(nops + 1, 0), tbase(nops + 1, 0);
+    entry_base.assign(nops + 1, 0);
+    for (int i = 0; i < nops; ++i) {
+        const Layout& L = *ls[i];
+        if (L.dim != M.dim || L.kind != M.kind || L.kappa != M.kappa)
+            throw std::invalid_argument("batched operators must share kernel, dimension and wavenumber");
+        box_base[i + 1] = box_base[i] + L.n_boxes;
+        entry_base[i + 1] = entry_base[i] + L.n_entries;
+        hbase[i + 1] = hbase[i] + L.n_hentries;
+        tbase[i + 1] = tbase[i] + static_cast<int64_t>(L.T.size());
+        M.n_points += L.n_points;
+        M.max_level = std::max(M.max_level, L.max_level);
+        M.top = std::min(M.top, L.top);
+        M.pairs_near += L.pairs_near;
+        M.pairs_skel += L.pairs_skel;
+    }
+    M.n_boxes = box_base[nops];
+    M.n_entries = entry_base[nops];
+    M.n_hentries = hbase[nops];
+    if (M.n_entries >= (int64_t(1) << 31)) throw std::runtime_error("too many entries for 32-bit maps");
+    // merged numbering: by level, then operator, then the operator's own order
+    std::vector<std::pair<int, int>> owner(M.n_boxes);   // merged id -> (op, local id)
+    std::vector<std::vector<int>> newid(nops);
+    {
+        std::vector<std::tuple<int, int, int>> keys;
+        keys.reserve(M.n_boxes);
+        for (int i = 0; i < nops; ++i)
+            for (int b = 0; b < ls[i]->n_boxes; ++b) keys.emplace_back(ls[i]->level[b], i, b);
+        std::sort(keys.begin(), keys.end());
+        for (int i = 0; i < nops; ++i) newid[i].assign(ls[i]->n_boxes, -1);
+        M.level_ptr.assign(M.max_level + 2, 0);
+        for (int g = 0; g < M.n_boxes; ++g) {
+            const auto [lev, i, b] = keys[g];
+            owner[g] = {i, b};
+            newid[i][b] = g;
+            M.level_ptr[lev + 1]++;
+        }
+        for (int l = 0; l <= M.max_level; ++l) M.level_ptr[l + 1] += M.level_ptr[l];
+    }
+    M.voff.resize(M.n_boxes); M.hoff.resize(M.n_boxes); M.toff.resize(M.n_boxes);
+    M.nb.resize(M.n_boxes); M.kb.resize(M.n_boxes); M.level.resize(M.n_boxes);
+    M.parent.resize(M.n_boxes); M.is_leaf.resize(M.n_boxes);
+    M.ctr.resize(static_cast<size_t>(M.n_boxes) * 4);
+    M.seg_ptr.assign(M.n_boxes + 1, 0);
+    for (int g = 0; g < M.n_boxes; ++g) {
+        const auto [i, b] = owner[g];
+        const Layout& L = *ls[i];
+        M.voff[g] = L.voff[b] + entry_base[i];
+        M.hoff[g] = L.hoff[b] + hbase[i];
+        M.toff[g] = L.toff[b] + tbase[i];
+        M.nb[g] = L.nb[b];
+        M.kb[g] = L.kb[b];
+        M.level[g] = L.level[b];
+        M.parent[g] = L.parent[b] < 0 ? -1 : newid[i][L.parent[b]];
+        M.is_leaf[g] = L.is_leaf[b];
+        for (int d = 0; d < 4; ++d) M.ctr[4 * g + d] = L.ctr[4 * b + d];
+        for (int x = L.seg_ptr[b]; x < L.seg_ptr[b + 1]; ++x) {
+            M.seg_src.push_back(newid[i][L.seg_src[x]]);
+            M.seg_mode.push_back(L.seg_mode[x]);
+        }
+        M.seg_ptr[g + 1] = static_cast<int32_t>(M.seg_src.size());
+    }
+    // per-entry and per-skeleton-entry arrays, concatenated in operator order
+    M.X.reserve(static_cast<size_t>(M.n_entries) * 4);
+    M.Xrel.reserve(static_cast<size_t>(M.n_entries) * 4);
+    M.perm.reserve(M.n_entries);
+    M.pmap.reserve(M.n_hentries);
+    M.T.reserve(tbase[nops]);
+    for (int i = 0; i < nops; ++i) {
+        const Layout& L = *ls[i];
+        M.X.insert(M.X.end(), L.X.begin(), L.X.end());
+        M.Xrel.insert(M.Xrel.end(), L.Xrel.begin(), L.Xrel.end());
+        M.perm.insert(M.perm.end(), L.perm.begin(), L.perm.end());
+        for (int32_t v : L.pmap) M.pmap.push_back(static_cast<int32_t>(v + entry_base[i]));
+        M.T.insert(M.T.end(), L.T.begin(), L.T.end());
+        for (size_t j = 0; j < L.gather_e.size(); ++j) {
+            M.gather_e.push_back(static_cast<int32_t>(L.gather_e[j] + entry_base[i]));
+            M.gather_p.push_back(L.gather_p[j]);
         }
     }
+    M.tasks = make_tasks(M, M.tile);
+    return M;
+}
+
+std::vector<Task> make_tasks(const Layout& L, int tile) {
+    std::vector<std::pair<int64_t, Task>> work;
+    for (int b = 0; b < L.n_boxes; ++b) {
+        if (L.level[b] < L.top || L.nb[b] == 0) continue;
+        int64_t src = 0;
+        for (int x = L.seg_ptr[b]; x < L.seg_ptr[b + 1]; ++x) src += L.nb[L.seg_src[x]];
+        for (int t0 = 0; t0 < L.nb[b]; t0 += tile) work.push_back({int64_t(tile) * src + 64, Task{b, t0}});
+    }
     std::stable_sort(work.begin(), work.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
-    L.tasks.reserve(work.size());
-    for (auto& w : work) L.tasks.push_back(w.second);
-    return L;
+    std::vector<Task> tasks;
+    tasks.reserve(work.size());
+    for (auto& w : work) tasks.push_back(w.second);
+    return tasks;
 }
 
 }  // namespace skelfmm

@@ -188,3 +188,79 @@ def test_argument_errors_leave_output_untouched():
     with pytest.raises(sk.SkelfmmError) as e:
         op.apply(q)
     assert e.value.status == -1
+
+
+@pytest.mark.parametrize("name,nrhs", [("lap3d_ellipsoid_60k", 3), ("lap3d_uniform_64k", 8),
+                                       ("lap2d_16k", 17), ("helm3d_uniform_32k", 5)])
+def test_many_rhs_match_single_and_o2(name, nrhs):
+    x, op, P = _op(name)
+    kind = CASES[name][1]
+    n = x.shape[0]
+    Q = workloads.charges(n, nrhs, 20, complex_=(kind == "helmholtz"))
+    dt = torch.complex128 if kind == "helmholtz" else torch.float64
+    U = host(op.apply(dev(Q, dt)))
+    assert U.shape == (n, nrhs)
+    for c in (0, nrhs - 1):
+        assert relerr(U[:, c], host(op.apply(dev(np.ascontiguousarray(Q[:, c]), dt)))) <= 1e-13
+    assert relerr(U, oracle.apply(P, Q)) <= 1e-12
+    W = host(op.apply_adjoint(dev(Q, dt)))
+    assert relerr(W, oracle.apply(P, Q, adjoint=True)) <= 1e-12
+
+
+@pytest.mark.parametrize("name", ["lap3d_uniform_64k", "helm3d_uniform_32k"])
+def test_many_rhs_single_precision(name):
+    x, op, P = _op(name)
+    kind, kappa, tol = CASES[name][1], CASES[name][2], CASES[name][3]
+    n = x.shape[0]
+    Q = workloads.charges(n, 16, 21, complex_=(kind == "helmholtz"))
+    dt = torch.complex64 if kind == "helmholtz" else torch.float32
+    U = host(op.apply(dev(Q, dt))).astype(np.complex128 if kind == "helmholtz" else np.float64)
+    Qr = Q.astype(np.complex64 if kind == "helmholtz" else np.float32).astype(Q.dtype)
+    tg = workloads.target_subset(n, 512, 22)
+    e1 = relerr(U[tg], oracle.direct(x, Qr, kind, kappa, targets=tg))
+    _say(name, "16 rhs single vs O1", e1)
+    assert e1 <= max(10 * tol, 1e-5)
+
+
+def _batch_ops(f64_leaf=False):
+    geo = [workloads.uniform_points(20000, 3, 601), workloads.ellipsoid_points(30000, 602),
+           workloads.uniform_points(15000, 3, 603)]
+    return geo, [sk.build(x, "laplace", tol=1e-6, leaf_size=64, f64_leaf=f64_leaf) for x in geo]
+
+
+@pytest.mark.parametrize("nrhs", [1, 8])
+def test_batch_equals_separate_applies(nrhs):
+    geo, ops = _batch_ops()
+    batch = sk.Batch(ops)
+    qs = [dev(workloads.charges(x.shape[0], nrhs, 30 + i), torch.float64) for i, x in enumerate(geo)]
+    outs = batch.apply(qs)
+    adj = batch.apply(qs, adjoint=True)
+    for i, op in enumerate(ops):
+        ref = op.apply(qs[i])
+        assert torch.equal(outs[i].reshape(ref.shape), ref)
+        assert torch.equal(adj[i].reshape(ref.shape), op.apply_adjoint(qs[i]))
+    P = ops[1].export()
+    assert relerr(host(outs[1]), oracle.apply(P, host(qs[1]))) <= 1e-12
+
+
+def test_batch_graph_capture_replays():
+    geo, ops = _batch_ops()
+    batch = sk.Batch(ops)
+    qs = [dev(workloads.charges(x.shape[0], 4, 40 + i), torch.float32) for i, x in enumerate(geo)]
+    ref = [o.clone() for o in batch.apply(qs)]        # eager; also sizes the workspace
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        batch.apply(qs)
+    torch.cuda.current_stream().wait_stream(side)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        outs = batch.apply(qs)
+    for _ in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        for o, r in zip(outs, ref):
+            assert torch.equal(o, r)
+        batch.apply(qs, adjoint=True)      # eager work between replays
+        torch.cuda.synchronize()
