@@ -132,12 +132,13 @@ class Operator:
 
     def __init__(self, handle, n: int, dim: int, kind: int):
         self._h = handle
+        self._destroy = _lib.skelfmm_destroy   # kept: module globals may be gone at exit
         self.n, self.dim, self.kind = n, dim, kind
 
     def __del__(self):
         h = getattr(self, "_h", None)
         if h:
-            _lib.skelfmm_destroy(h)
+            self._destroy(h)
             self._h = None
 
     @property
@@ -269,23 +270,30 @@ class Batch:
         h = _vp()
         _check(_lib.skelfmm_batch_create(arr, len(self.ops), ctypes.byref(h)))
         self._h = h
+        self._destroy = _lib.skelfmm_batch_destroy
 
     def __del__(self):
         h = getattr(self, "_h", None)
         if h:
-            _lib.skelfmm_batch_destroy(h)
+            self._destroy(h)
             self._h = None
 
     def apply(self, qs, adjoint: bool = False):
+        """Outputs for every operator, each shaped like its input ([n] or [n, nrhs])."""
         torch = _torch()
+        shapes = [q.shape for q in qs]
         qs = [q.reshape(q.shape[0], -1).contiguous() for q in qs]
+        if len(qs) != len(self.ops) or any(q.shape[0] != o.n for q, o in zip(qs, self.ops)):
+            raise ValueError("one input of matching length per operator")
+        if len({q.shape[1] for q in qs}) != 1 or len({q.dtype for q in qs}) != 1:
+            raise ValueError("batched inputs must share nrhs and dtype")
         us = [torch.empty_like(q) for q in qs]
         nrhs = qs[0].shape[1]
         qa = (_vp * len(qs))(*[q.data_ptr() for q in qs])
         ua = (_vp * len(us))(*[u.data_ptr() for u in us])
         stream = torch.cuda.current_stream(qs[0].device).cuda_stream
         _check(_lib.skelfmm_batch_apply(self._h, qa, ua, nrhs, _dtype_code(qs[0]), int(adjoint), stream))
-        return us
+        return [u.reshape(sh) for u, sh in zip(us, shapes)]
 
 
 def _make_autograd():

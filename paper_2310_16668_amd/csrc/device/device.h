@@ -45,8 +45,6 @@ struct Layout {
     // in [skeleton | redundant] order
     int64_t n_entries = 0, n_hentries = 0;
     std::vector<double> X;          // n_entries x 4 (x, y, z, 0), root-centred
-    std::vector<float> Xrel;        // n_entries x 4, offsets from the owning box's centre
-    std::vector<double> ctr;        // n_boxes x 4, box centres (root-centred)
     std::vector<int32_t> perm;      // user index of leaf entries, -1 elsewhere
     std::vector<int32_t> pmap;      // skeleton entry -> entry in the parent's vector
     std::vector<int32_t> gather_e, gather_p;     // leaf entries and their user indices

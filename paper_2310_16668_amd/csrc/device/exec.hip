@@ -99,7 +99,7 @@ struct DeviceOp {
     bool uploaded = false;
     // static arrays
     DevMem voff, hoff, toff, nb, kb, pmap, gather_e, gather_p;
-    DevMem X64, X32, ctr, T64, T32, Tt64, Tt32;   // Tt: per-box transposes (multi-RHS downward)
+    DevMem X64, T64, T32, Tt64, Tt32;             // Tt: per-box transposes (multi-RHS downward)
     DevMem seg_ptr, segs, boxrec;
     int tpl = kDefaultTPL;
     DevMem tasks[3];                              // work lists for 1, 2, 4 targets per lane
@@ -158,18 +158,14 @@ static void upload(DeviceOp* d, int dtype) {
             d->tasks[tpl_slot(t)].upload(tl);
             d->ntasks[tpl_slot(t)] = static_cast<int>(tl.size());
         }
-        d->ctr.upload(L.ctr);
         std::vector<kern::BoxRec> br(L.n_boxes);
         for (int b = 0; b < L.n_boxes; ++b)
             br[b] = kern::BoxRec{L.voff[b], L.hoff[b], L.nb[b], L.kb[b], L.level[b], L.is_leaf[b]};
         d->boxrec.upload(br);
-        // float64 coordinates serve float64 applies, f64_leaf applies and the
-        // targets of the float32 relative-coordinate policy
-        d->X64.upload(L.X);
+        d->X64.upload(L.X);   // coordinates are float64 in every precision policy
         d->uploaded = true;
     }
     const bool single = dtype_is_single(dtype);
-    if (single && !d->f64_leaf && !d->X32.p) d->X32.upload(L.Xrel);
     if (!single && !d->T64.p) d->T64.upload(L.T);
     if (single && !d->T32.p) d->T32.upload(std::vector<float>(L.T.begin(), L.T.end()));
 }
@@ -223,29 +219,28 @@ struct IO {
 };
 
 template <class P, int TPL, bool CONJ>
-void launch_near_t(const DeviceOp* d, hipStream_t s, const void* X, void* Q, void* Qh, void* U, void* Uh) {
+void launch_near_t(const DeviceOp* d, hipStream_t s, void* Q, void* Qh, void* U, void* Uh) {
     const int ntasks = d->ntasks[tpl_slot(TPL)];
     if (ntasks == 0) return;
     using R = typename P::Rt;
     using V = typename P::Vt;
     hipLaunchKernelGGL((kern::k_near<P, TPL, CONJ>), dim3(blocks_for(ntasks, 4)), dim3(256), 0, s,
                        d->tasks[tpl_slot(TPL)].as<Task>(), ntasks, d->seg_ptr.as<int32_t>(), d->segs.as<int2>(),
-                       d->boxrec.as<kern::BoxRec>(), static_cast<const kern::Rec4<R>*>(X),
-                       d->X64.as<kern::Rec4<double>>(), d->ctr.as<double4>(), static_cast<const V*>(Q),
+                       d->boxrec.as<kern::BoxRec>(), d->X64.as<kern::Rec4<double>>(), static_cast<const V*>(Q),
                        static_cast<const V*>(Qh), static_cast<V*>(U), static_cast<V*>(Uh),
                        static_cast<R>(d->L.kappa), kern::kInv4Pi);
     SKF_HIP(hipGetLastError());
 }
 
 template <class P, bool CONJ>
-void launch_near(const DeviceOp* d, hipStream_t s, const void* X, void* Q, void* Qh, void* U, void* Uh) {
-    if (d->tpl == 1) launch_near_t<P, 1, CONJ>(d, s, X, Q, Qh, U, Uh);
-    else if (d->tpl == 4) launch_near_t<P, 4, CONJ>(d, s, X, Q, Qh, U, Uh);
-    else launch_near_t<P, 2, CONJ>(d, s, X, Q, Qh, U, Uh);
+void launch_near(const DeviceOp* d, hipStream_t s, void* Q, void* Qh, void* U, void* Uh) {
+    if (d->tpl == 1) launch_near_t<P, 1, CONJ>(d, s, Q, Qh, U, Uh);
+    else if (d->tpl == 4) launch_near_t<P, 4, CONJ>(d, s, Q, Qh, U, Uh);
+    else launch_near_t<P, 2, CONJ>(d, s, Q, Qh, U, Uh);
 }
 
 template <class P, bool CONJ, typename Am>
-void launch_near_mr(const DeviceOp* d, hipStream_t s, int Wp, const void* X, void* Q, void* Qh, void* U, void* Uh) {
+void launch_near_mr(const DeviceOp* d, hipStream_t s, int Wp, void* Q, void* Qh, void* U, void* Uh) {
     const int ntasks = d->ntasks[tpl_slot(1)];
     if (ntasks == 0) return;
     using R = typename P::Rt;
@@ -255,8 +250,7 @@ void launch_near_mr(const DeviceOp* d, hipStream_t s, int Wp, const void* X, voi
     hipLaunchKernelGGL((kern::k_near_mr<P, NR, CONJ, Am>), dim3(blocks_for(int64_t(ntasks) * nchunks, 4)),
                        dim3(256), 0, s, d->tasks[tpl_slot(1)].as<Task>(), ntasks, nchunks, Wp,
                        d->seg_ptr.as<int32_t>(), d->segs.as<int2>(), d->boxrec.as<kern::BoxRec>(),
-                       static_cast<const kern::Rec4<R>*>(X), d->X64.as<kern::Rec4<double>>(), d->ctr.as<double4>(),
-                       static_cast<const V*>(Q), static_cast<const V*>(Qh), static_cast<V*>(U), static_cast<V*>(Uh),
+                       d->X64.as<kern::Rec4<double>>(), static_cast<const V*>(Q), static_cast<const V*>(Qh), static_cast<V*>(U), static_cast<V*>(Uh),
                        static_cast<R>(d->L.kappa), kern::kInv4Pi);
     SKF_HIP(hipGetLastError());
 }
@@ -282,7 +276,7 @@ struct PassMarks {
 // Am: accumulator of one source box's partial sums in the multi-RHS near field.
 template <typename V, typename TT, class P, typename Am>
 void sweep(DeviceOp* d, const std::vector<IO>& io, int64_t nrhs, int dtype, hipStream_t s, bool adjoint,
-           const TT* T, const TT* Tt, const void* X) {
+           const TT* T, const TT* Tt) {
     const Layout& L = d->L;
     const bool multi = nrhs > 1;
     const int Win = static_cast<int>(nrhs * P::nv);
@@ -316,11 +310,11 @@ void sweep(DeviceOp* d, const std::vector<IO>& io, int64_t nrhs, int dtype, hipS
     }
     pm.mark(2);
     if (multi) {
-        if (adjoint && P::kind == 1) launch_near_mr<P, true, Am>(d, s, Wp, X, Q, Qh, U, Uh);
-        else launch_near_mr<P, false, Am>(d, s, Wp, X, Q, Qh, U, Uh);
+        if (adjoint && P::kind == 1) launch_near_mr<P, true, Am>(d, s, Wp, Q, Qh, U, Uh);
+        else launch_near_mr<P, false, Am>(d, s, Wp, Q, Qh, U, Uh);
     } else {
-        if (adjoint && P::kind == 1) launch_near<P, true>(d, s, X, Q, Qh, U, Uh);
-        else launch_near<P, false>(d, s, X, Q, Qh, U, Uh);
+        if (adjoint && P::kind == 1) launch_near<P, true>(d, s, Q, Qh, U, Uh);
+        else launch_near<P, false>(d, s, Q, Qh, U, Uh);
     }
     pm.mark(3);
     for (int l = 2; l <= L.max_level; ++l) {
@@ -352,16 +346,13 @@ template <int DIM, int KIND>
 void dispatch(DeviceOp* d, const std::vector<IO>& io, int64_t nrhs, int dtype, hipStream_t s, bool adjoint) {
     if (dtype == SKELFMM_F64 || dtype == SKELFMM_C128) {
         using P = kern::Pol<double, double, double, DIM, KIND>;
-        sweep<double, double, P, double>(d, io, nrhs, dtype, s, adjoint, d->T64.as<double>(), d->Tt64.as<double>(),
-                                         d->X64.p);
+        sweep<double, double, P, double>(d, io, nrhs, dtype, s, adjoint, d->T64.as<double>(), d->Tt64.as<double>());
     } else if (d->f64_leaf) {
         using P = kern::Pol<double, double, float, DIM, KIND>;
-        sweep<float, float, P, double>(d, io, nrhs, dtype, s, adjoint, d->T32.as<float>(), d->Tt32.as<float>(),
-                                       d->X64.p);
+        sweep<float, float, P, double>(d, io, nrhs, dtype, s, adjoint, d->T32.as<float>(), d->Tt32.as<float>());
     } else {
-        using P = kern::Pol<float, double, float, DIM, KIND, true>;
-        sweep<float, float, P, float>(d, io, nrhs, dtype, s, adjoint, d->T32.as<float>(), d->Tt32.as<float>(),
-                                      d->X32.p);
+        using P = kern::Pol<float, double, float, DIM, KIND>;
+        sweep<float, float, P, float>(d, io, nrhs, dtype, s, adjoint, d->T32.as<float>(), d->Tt32.as<float>());
     }
 }
 
@@ -399,13 +390,13 @@ static void tune_near(DeviceOp* d, int dtype, hipStream_t s, float* ms_out) {
             if (rep == 1) SKF_HIP(hipEventRecord(a, s));
             if (!single) {
                 using P = kern::Pol<double, double, double, DIM, KIND>;
-                launch_near<P, false>(d, s, d->X64.p, d->Q.p, d->Qh.p, d->U.p, d->Uh.p);
+                launch_near<P, false>(d, s, d->Q.p, d->Qh.p, d->U.p, d->Uh.p);
             } else if (d->f64_leaf) {
                 using P = kern::Pol<double, double, float, DIM, KIND>;
-                launch_near<P, false>(d, s, d->X64.p, d->Q.p, d->Qh.p, d->U.p, d->Uh.p);
+                launch_near<P, false>(d, s, d->Q.p, d->Qh.p, d->U.p, d->Uh.p);
             } else {
-                using P = kern::Pol<float, double, float, DIM, KIND, true>;
-                launch_near<P, false>(d, s, d->X32.p, d->Q.p, d->Qh.p, d->U.p, d->Uh.p);
+                using P = kern::Pol<float, double, float, DIM, KIND>;
+                launch_near<P, false>(d, s, d->Q.p, d->Qh.p, d->U.p, d->Uh.p);
             }
         }
         SKF_HIP(hipEventRecord(b, s));

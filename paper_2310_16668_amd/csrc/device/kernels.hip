@@ -5,8 +5,7 @@
 // through pmap, into its parent's entries) -> one near-field launch over every
 // level (ifo, ifs, tfo and the top-level direct sum) -> downward pass, one
 // launch per level (uhat += parent's u at the box's slots; u[0:k] += uhat;
-// u[k:n] += T^T uhat; leaves write the caller's output) -> output of the
-// top-level leaves.
+// u[k:n] += T^T uhat) -> scatter of the leaf entries to the caller's output.
 //
 // The near field is the hot loop.  A work item is one wavefront: `TPL` targets
 // per lane (64 TPL consecutive entries of one target box) against every source
@@ -17,11 +16,15 @@
 // update (one extra FMA per skeleton pair, the sub-block reuse of section 4)
 // runs over a prefix of the same loop.
 //
-// Precision policies:
-//   F64   coordinates, kernel and accumulators in float64;
-//   F32   coordinates and kernel in float32, accumulators in float64 (the
-//         float64 FMA issues at the float32 rate on CDNA4, so the wider
-//         accumulator costs one conversion per pair);
+// Precision.  Coordinates, their differences and |d|^2 are always float64:
+// float64 add / multiply-add issue at the float32 rate on CDNA4, and float32
+// differences of nearby points lose their relative precision whenever the
+// points sit far from the coordinate origin (a clustered surface).  Policies:
+//   F64   kernel value and accumulators in float64 (reciprocal square root
+//         refined by one Newton step);
+//   F32   |d|^2 rounded once to float32, kernel value (reciprocal square root,
+//         log, sincos) in float32, accumulators in float64, stored vectors and
+//         transfer matrices in float32;
 //   C128 / C64 the complex analogues; C64 with f64_leaf evaluates in float64.
 #include <hip/hip_runtime.h>
 
@@ -70,31 +73,30 @@ __device__ __forceinline__ float neg_log_r2(float r2) { return r2 > 0.0f ? -__lo
 __device__ __forceinline__ void sin_cos(double x, double* s, double* c) { sincos(x, s, c); }
 __device__ __forceinline__ void sin_cos(float x, float* s, float* c) { sincosf(x, s, c); }
 
-template <typename R, typename A, typename V, int DIM, int KIND, bool REL = false>
+template <typename R, typename A, typename V, int DIM, int KIND>
 struct Pol {
-    using Rt = R;   // coordinates / kernel evaluation
+    using Rt = R;   // kernel evaluation (coordinates are float64 in every policy)
     using At = A;   // accumulators
     using Vt = V;   // stored vectors
     static constexpr int dim = DIM;
     static constexpr int kind = KIND;   // 0 Laplace, 1 Helmholtz
     static constexpr int nv = KIND == 1 ? 2 : 1;
-    // REL: source coordinates are float32 offsets from their own box centre and
-    // each lane re-expresses its targets relative to the source box per segment
-    static constexpr bool rel = REL;
     // 3D Laplace in float64 evaluates 2/r (see two_inv_r); the factor is undone in the scale
     static constexpr bool twice = DIM == 3 && KIND == 0 && sizeof(R) == 8;
     static constexpr double gscale = twice ? 0.5 : 1.0;
 };
 
-// G(x_t, x_s) (times 4 pi for 3D, times 4 pi / 2 for 2D: the common factor is
-// applied once at the end).  Real kernels return gr only.
+// G(x_t, x_s) without the common factor 1/(4 pi) (for 2D: -log r^2, i.e. the
+// kernel times 4 pi), applied once at the end.  MASK: zero the pair at r = 0
+// (only needed where a box meets itself).  Real kernels return gr only.
 template <class P, bool CONJ, bool MASK>
-__device__ __forceinline__ void green(typename P::Rt dx, typename P::Rt dy, typename P::Rt dz,
-                                      typename P::Rt kappa, typename P::Rt& gr, typename P::Rt& gi) {
+__device__ __forceinline__ void green(double dx, double dy, double dz, typename P::Rt kappa,
+                                      typename P::Rt& gr, typename P::Rt& gi) {
     using R = typename P::Rt;
-    R r2 = dx * dx;
-    r2 = fma(dy, dy, r2);
-    if constexpr (P::dim == 3) r2 = fma(dz, dz, r2);
+    double r2d = dx * dx;
+    r2d = fma(dy, dy, r2d);
+    if constexpr (P::dim == 3) r2d = fma(dz, dz, r2d);
+    const R r2 = static_cast<R>(r2d);
     R ir;
     if constexpr (sizeof(R) == 8) ir = (P::twice) ? two_inv_r(r2) : inv_r(r2);
     else ir = inv_r_f<MASK>(r2);
@@ -208,19 +210,18 @@ struct alignas(32) BoxRec {
 
 // MODE 0: u += G w ;  1: u += G w, uh -= G wh ;  2: u += G w, uh -= G w ;  3: u += G (w - wh)
 template <class P, int TPL, bool CONJ, int MODE, bool MASK>
-__device__ __forceinline__ void near_loop(const Rec4<typename P::Rt>* __restrict__ X,
+__device__ __forceinline__ void near_loop(const Rec4<double>* __restrict__ X,
                                           const typename P::Vt* __restrict__ Q,
                                           const typename P::Vt* __restrict__ Qh, int s0, int s1,
                                           typename P::Rt kappa,
-                                          const typename P::Rt (&xt)[TPL], const typename P::Rt (&yt)[TPL],
-                                          const typename P::Rt (&zt)[TPL],
+                                          const double (&xt)[TPL], const double (&yt)[TPL], const double (&zt)[TPL],
                                           typename P::At (&acc)[TPL][P::nv], typename P::At (&acch)[TPL][P::nv]) {
     using R = typename P::Rt;
     using A = typename P::At;
     constexpr int nv = P::nv;
 #pragma unroll 2
     for (int s = s0; s < s1; ++s) {
-        const Rec4<R> xs = X[s];
+        const Rec4<double> xs = X[s];
         A w[nv], wh[nv];
 #pragma unroll
         for (int v = 0; v < nv; ++v) {
@@ -256,12 +257,12 @@ __device__ __forceinline__ void near_loop(const Rec4<typename P::Rt>* __restrict
 
 // All translation types of one source box into the lane's targets.
 template <class P, int TPL, bool CONJ, bool MASK>
-__device__ __forceinline__ void near_segment(int mode, bool has_h, const Rec4<typename P::Rt>* __restrict__ Xs,
+__device__ __forceinline__ void near_segment(int mode, bool has_h, const Rec4<double>* __restrict__ Xs,
                                              const typename P::Vt* __restrict__ Qs,
                                              const typename P::Vt* __restrict__ Qhs, int sn, int sk,
                                              typename P::Rt kappa,
-                                             const typename P::Rt (&xt)[TPL], const typename P::Rt (&yt)[TPL],
-                                             const typename P::Rt (&zt)[TPL],
+                                             const double (&xt)[TPL], const double (&yt)[TPL],
+                                             const double (&zt)[TPL],
                                              typename P::At (&acc)[TPL][P::nv], typename P::At (&acch)[TPL][P::nv]) {
     if (mode == SEG_IFO) {
         if (has_h) {
@@ -289,14 +290,11 @@ template <class P, int TPL, bool CONJ>
 __global__ void __launch_bounds__(256) k_near(const Task* __restrict__ tasks, int ntasks,
                                               const int32_t* __restrict__ seg_ptr, const int2* __restrict__ segs,
                                               const BoxRec* __restrict__ box,
-                                              const Rec4<typename P::Rt>* __restrict__ X,
-                                              const Rec4<double>* __restrict__ X64,
-                                              const double4* __restrict__ ctr,
+                                              const Rec4<double>* __restrict__ X,
                                               const typename P::Vt* __restrict__ Q,
                                               const typename P::Vt* __restrict__ Qh,
                                               typename P::Vt* __restrict__ U, typename P::Vt* __restrict__ Uh,
                                               typename P::Rt kappa, double scale) {
-    using R = typename P::Rt;
     using A = typename P::At;
     using V = typename P::Vt;
     constexpr int nv = P::nv;
@@ -308,19 +306,13 @@ __global__ void __launch_bounds__(256) k_near(const Task* __restrict__ tasks, in
     // boxes at or above the top level carry k = 0: no skeleton part
     const bool has_h = tk.t0 < tb.k;
 
-    R xt[TPL], yt[TPL], zt[TPL];
-    double xd[TPL], yd[TPL], zd[TPL];
+    double xt[TPL], yt[TPL], zt[TPL];
     A acc[TPL][nv], acch[TPL][nv];
 #pragma unroll
     for (int p = 0; p < TPL; ++p) {
         const int t = min(tk.t0 + lane + 64 * p, tb.n - 1);
-        if constexpr (P::rel) {
-            const Rec4<double> x = X64[tb.voff + t];
-            xd[p] = x.x; yd[p] = x.y; zd[p] = x.z;
-        } else {
-            const Rec4<R> x = X[tb.voff + t];
-            xt[p] = x.x; yt[p] = x.y; zt[p] = x.z;
-        }
+        const Rec4<double> x = X[tb.voff + t];
+        xt[p] = x.x; yt[p] = x.y; zt[p] = x.z;
 #pragma unroll
         for (int v = 0; v < nv; ++v) { acc[p][v] = A(0); acch[p][v] = A(0); }
     }
@@ -328,16 +320,7 @@ __global__ void __launch_bounds__(256) k_near(const Task* __restrict__ tasks, in
     for (int e = seg_ptr[tk.box]; e < e1; ++e) {
         const int2 sg = segs[e];
         const BoxRec sb = box[sg.x];
-        if constexpr (P::rel) {
-            const double4 c = ctr[sg.x];
-#pragma unroll
-            for (int p = 0; p < TPL; ++p) {
-                xt[p] = static_cast<R>(xd[p] - c.x);
-                yt[p] = static_cast<R>(yd[p] - c.y);
-                zt[p] = static_cast<R>(zd[p] - c.z);
-            }
-        }
-        const Rec4<R>* Xs = X + sb.voff;
+        const Rec4<double>* Xs = X + sb.voff;
         const V* Qs = Q + sb.voff * nv;
         const V* Qhs = Qh + sb.hoff * nv;
         const int mode = sg.y & SEG_MODE_MASK;
@@ -501,15 +484,15 @@ __global__ void __launch_bounds__(256) k_downward_mr(const BoxRec* __restrict__ 
 // sums of one source box accumulate in Am (float32 for the single-precision
 // policies) and are added to float64 totals at the end of the box.
 template <class P, int NR, bool CONJ, int MODE, bool MASK, typename Am>
-__device__ __forceinline__ void near_loop_mr(const Rec4<typename P::Rt>* __restrict__ X,
+__device__ __forceinline__ void near_loop_mr(const Rec4<double>* __restrict__ X,
                                              const typename P::Vt* __restrict__ Q,
                                              const typename P::Vt* __restrict__ Qh, int Wp, int s0, int s1,
-                                             typename P::Rt kappa, typename P::Rt xt, typename P::Rt yt,
-                                             typename P::Rt zt, Am (&pu)[NR * P::nv], Am (&ph)[NR * P::nv]) {
+                                             typename P::Rt kappa, double xt, double yt, double zt,
+                                             Am (&pu)[NR * P::nv], Am (&ph)[NR * P::nv]) {
     using R = typename P::Rt;
     constexpr int nv = P::nv;
     for (int s = s0; s < s1; ++s) {
-        const Rec4<R> xs = X[s];
+        const Rec4<double> xs = X[s];
         R gr, gi;
         green<P, CONJ, MASK>(xt - xs.x, yt - xs.y, zt - xs.z, kappa, gr, gi);
         const Am g = static_cast<Am>(gr);
@@ -547,9 +530,7 @@ template <class P, int NR, bool CONJ, typename Am>
 __global__ void __launch_bounds__(256) k_near_mr(const Task* __restrict__ tasks, int ntasks, int nchunks,
                                                  int Wp, const int32_t* __restrict__ seg_ptr,
                                                  const int2* __restrict__ segs, const BoxRec* __restrict__ box,
-                                                 const Rec4<typename P::Rt>* __restrict__ X,
-                                                 const Rec4<double>* __restrict__ X64,
-                                                 const double4* __restrict__ ctr,
+                                                 const Rec4<double>* __restrict__ X,
                                                  const typename P::Vt* __restrict__ Q,
                                                  const typename P::Vt* __restrict__ Qh,
                                                  typename P::Vt* __restrict__ U, typename P::Vt* __restrict__ Uh,
@@ -568,15 +549,8 @@ __global__ void __launch_bounds__(256) k_near_mr(const Task* __restrict__ tasks,
     const bool has_h = tk.t0 < tb.k;
     const int c0 = chunk * NW;
     const int t = min(tk.t0 + lane, tb.n - 1);
-    R xt, yt, zt;
-    double xd = 0, yd = 0, zd = 0;
-    if constexpr (P::rel) {
-        const Rec4<double> x = X64[tb.voff + t];
-        xd = x.x; yd = x.y; zd = x.z;
-    } else {
-        const Rec4<R> x = X[tb.voff + t];
-        xt = x.x; yt = x.y; zt = x.z;
-    }
+    const Rec4<double> xr = X[tb.voff + t];
+    const double xt = xr.x, yt = xr.y, zt = xr.z;
     double au[NW], ah[NW];
 #pragma unroll
     for (int v = 0; v < NW; ++v) { au[v] = 0.0; ah[v] = 0.0; }
@@ -584,11 +558,7 @@ __global__ void __launch_bounds__(256) k_near_mr(const Task* __restrict__ tasks,
     for (int e = seg_ptr[tk.box]; e < e1; ++e) {
         const int2 sg = segs[e];
         const BoxRec sb = box[sg.x];
-        if constexpr (P::rel) {
-            const double4 cc = ctr[sg.x];
-            xt = static_cast<R>(xd - cc.x); yt = static_cast<R>(yd - cc.y); zt = static_cast<R>(zd - cc.z);
-        }
-        const Rec4<R>* Xs = X + sb.voff;
+        const Rec4<double>* Xs = X + sb.voff;
         const V* Qs = Q + sb.voff * Wp + c0;
         const V* Qhs = Qh + sb.hoff * Wp + c0;
         const int mode = sg.y & SEG_MODE_MASK;

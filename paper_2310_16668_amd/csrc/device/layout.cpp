@@ -70,16 +70,8 @@ Layout make_layout(const Plan& p, bool keep_transparent, int tile) {
     L.n_hentries = h;
     if (e >= (int64_t(1) << 31)) throw std::runtime_error("too many entries for 32-bit maps");
 
-    // box centres (root-centred)
-    L.ctr.assign(static_cast<size_t>(nb) * 4, 0.0);
-    for (int b = 0; b < nb; ++b) {
-        const double a = std::ldexp(p.root_side, -p.level[b]);
-        for (int d = 0; d < p.dim; ++d)
-            L.ctr[4 * b + d] = p.root_lo[d] + (p.coord[3 * b + d] + 0.5) * a - L.center[d];
-    }
-    // entry coordinates (root-centred, and relative to the owning box) and leaf permutation
+    // entry coordinates (root-centred) and leaf permutation
     L.X.assign(static_cast<size_t>(e) * 4, 0.0);
-    L.Xrel.assign(static_cast<size_t>(e) * 4, 0.0f);
     L.perm.assign(e, -1);
     for (int b = 0; b < nb; ++b) {
         const int64_t n = L.nb[b];
@@ -88,11 +80,7 @@ Layout make_layout(const Plan& p, bool keep_transparent, int tile) {
         for (int64_t i = 0; i < n; ++i) {
             const int64_t pt = ix[ps[i]];
             double* x = &L.X[static_cast<size_t>(L.voff[b] + i) * 4];
-            float* xr = &L.Xrel[static_cast<size_t>(L.voff[b] + i) * 4];
-            for (int d = 0; d < p.dim; ++d) {
-                x[d] = p.pts[pt * p.dim + d] - L.center[d];
-                xr[d] = static_cast<float>(x[d] - L.ctr[4 * b + d]);
-            }
+            for (int d = 0; d < p.dim; ++d) x[d] = p.pts[pt * p.dim + d] - L.center[d];
             if (p.is_leaf[b]) L.perm[L.voff[b] + i] = static_cast<int32_t>(pt);
         }
         if (p.is_leaf[b]) {
@@ -235,7 +223,6 @@ Layout merge_layouts(const std::vector<const Layout*>& ls, std::vector<int64_t>&
     M.voff.resize(M.n_boxes); M.hoff.resize(M.n_boxes); M.toff.resize(M.n_boxes);
     M.nb.resize(M.n_boxes); M.kb.resize(M.n_boxes); M.level.resize(M.n_boxes);
     M.parent.resize(M.n_boxes); M.is_leaf.resize(M.n_boxes);
-    M.ctr.resize(static_cast<size_t>(M.n_boxes) * 4);
     M.seg_ptr.assign(M.n_boxes + 1, 0);
     for (int g = 0; g < M.n_boxes; ++g) {
         const auto [i, b] = owner[g];
@@ -248,7 +235,6 @@ Layout merge_layouts(const std::vector<const Layout*>& ls, std::vector<int64_t>&
         M.level[g] = L.level[b];
         M.parent[g] = L.parent[b] < 0 ? -1 : newid[i][L.parent[b]];
         M.is_leaf[g] = L.is_leaf[b];
-        for (int d = 0; d < 4; ++d) M.ctr[4 * g + d] = L.ctr[4 * b + d];
         for (int x = L.seg_ptr[b]; x < L.seg_ptr[b + 1]; ++x) {
             M.seg_src.push_back(newid[i][L.seg_src[x]]);
             M.seg_mode.push_back(L.seg_mode[x]);
@@ -257,14 +243,12 @@ Layout merge_layouts(const std::vector<const Layout*>& ls, std::vector<int64_t>&
     }
     // per-entry and per-skeleton-entry arrays, concatenated in operator order
     M.X.reserve(static_cast<size_t>(M.n_entries) * 4);
-    M.Xrel.reserve(static_cast<size_t>(M.n_entries) * 4);
     M.perm.reserve(M.n_entries);
     M.pmap.reserve(M.n_hentries);
     M.T.reserve(tbase[nops]);
     for (int i = 0; i < nops; ++i) {
         const Layout& L = *ls[i];
         M.X.insert(M.X.end(), L.X.begin(), L.X.end());
-        M.Xrel.insert(M.Xrel.end(), L.Xrel.begin(), L.Xrel.end());
         M.perm.insert(M.perm.end(), L.perm.begin(), L.perm.end());
         for (int32_t v : L.pmap) M.pmap.push_back(static_cast<int32_t>(v + entry_base[i]));
         M.T.insert(M.T.end(), L.T.begin(), L.T.end());
