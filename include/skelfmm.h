@@ -71,7 +71,7 @@ typedef struct {
 /* Build and apply options; a zero-initialised struct (or NULL) means defaults. */
 typedef struct {
     int32_t proxy_shape;     /* 0 default (2D circle, 3D Chebyshev box), 1 box, 2 circle (2D only) */
-    int32_t proxy_points;    /* per side (box) or total (circle); 0 = default (3D 12/side, 2D 128) */
+    int32_t proxy_points;    /* per side (box) or total (circle); 0 = default (3D 10/side, 2D 128) */
     double proxy_scale;      /* proxy box side / box side; 0 = default 2.95 (circle radius = scale/2 * side) */
     int32_t no_compression;  /* test mode: every box keeps all its points (k = n) */
     int32_t num_threads;     /* host threads for the build; 0 = all cores */

@@ -101,6 +101,10 @@ struct DeviceOp {
     DevMem voff, hoff, toff, nb, kb, pmap, gather_e, gather_p;
     DevMem X64, T64, T32, Tt64, Tt32;             // Tt: per-box transposes (multi-RHS downward)
     DevMem seg_ptr, segs, boxrec;
+    // one-RHS transfer work: (box, first row) items per level, and waves per item
+    DevMem upwork, downwork;
+    std::vector<int64_t> up_ptr, down_ptr;
+    std::vector<int> up_nw, down_nw;
     int tpl = kDefaultTPL;
     DevMem tasks[3];                              // work lists for 1, 2, 4 targets per lane
     int ntasks[3] = {0, 0, 0};
@@ -137,6 +141,42 @@ DeviceOp* device_create(const Plan& p, bool keep_transparent, bool f64_leaf) {
     return d.release();
 }
 
+// Work items of the one-RHS transfers: upward rows are a box's skeleton entries
+// (k, with n - k columns), downward rows its redundant entries (n - k, with k
+// columns; at least one item per box, which also updates the skeleton entries).
+// Waves per item follow the level's mean column count.
+static void build_transfer_work(DeviceOp* d) {
+    const Layout& L = d->L;
+    std::vector<int2> up, down;
+    d->up_ptr.assign(L.max_level + 2, 0);
+    d->down_ptr.assign(L.max_level + 2, 0);
+    d->up_nw.assign(L.max_level + 1, 1);
+    d->down_nw.assign(L.max_level + 1, 1);
+    for (int l = 0; l <= L.max_level; ++l) {
+        d->up_ptr[l] = static_cast<int64_t>(up.size());
+        d->down_ptr[l] = static_cast<int64_t>(down.size());
+        double cu = 0, cd = 0;
+        int nbk = 0;
+        for (int b = L.level_ptr[l]; b < L.level_ptr[l + 1]; ++b) {
+            const int k = L.kb[b], m = L.nb[b] - L.kb[b];
+            if (k <= 0) continue;
+            ++nbk;
+            cu += m;
+            cd += k;
+            for (int r = 0; r < k; r += 64) up.push_back(make_int2(b, r));
+            for (int r = 0; r < std::max(m, 1); r += 64) down.push_back(make_int2(b, r));
+        }
+        if (nbk > 0) {
+            d->up_nw[l] = std::min(16, std::max(1, static_cast<int>(cu / nbk / 32.0 + 0.5)));
+            d->down_nw[l] = std::min(16, std::max(1, static_cast<int>(cd / nbk / 32.0 + 0.5)));
+        }
+    }
+    d->up_ptr[L.max_level + 1] = static_cast<int64_t>(up.size());
+    d->down_ptr[L.max_level + 1] = static_cast<int64_t>(down.size());
+    d->upwork.upload(up);
+    d->downwork.upload(down);
+}
+
 static void upload(DeviceOp* d, int dtype) {
     const Layout& L = d->L;
     if (!d->uploaded) {
@@ -163,6 +203,7 @@ static void upload(DeviceOp* d, int dtype) {
             br[b] = kern::BoxRec{L.voff[b], L.hoff[b], L.nb[b], L.kb[b], L.level[b], L.is_leaf[b]};
         d->boxrec.upload(br);
         d->X64.upload(L.X);   // coordinates are float64 in every precision policy
+        build_transfer_work(d);
         d->uploaded = true;
     }
     const bool single = dtype_is_single(dtype);
@@ -188,7 +229,7 @@ static void upload_transposes(DeviceOp* d, bool single) {
 
 void device_prepare(DeviceOp* d, int64_t nrhs, int dtype) {
     upload(d, dtype);
-    if (nrhs > 1) upload_transposes(d, dtype_is_single(dtype));
+    upload_transposes(d, dtype_is_single(dtype));
     const size_t vb = dtype_is_single(dtype) ? 4 : 8;
     const size_t wp = static_cast<size_t>(padded_width(nrhs, dtype));
     const size_t need_e = static_cast<size_t>(d->L.n_entries) * wp * vb;
@@ -198,17 +239,6 @@ void device_prepare(DeviceOp* d, int64_t nrhs, int dtype) {
 }
 
 namespace {
-
-kern::BoxArgs box_args(const DeviceOp* d) {
-    kern::BoxArgs a{};
-    a.voff = d->voff.as<int64_t>();
-    a.hoff = d->hoff.as<int64_t>();
-    a.toff = d->toff.as<int64_t>();
-    a.nb = d->nb.as<int32_t>();
-    a.kb = d->kb.as<int32_t>();
-    a.pmap = d->pmap.as<int32_t>();
-    return a;
-}
 
 // The caller's buffers of one operator and its range of leaf entries.
 struct IO {
@@ -285,8 +315,9 @@ void sweep(DeviceOp* d, const std::vector<IO>& io, int64_t nrhs, int dtype, hipS
     V* Qh = d->Qh.as<V>();
     V* U = d->U.as<V>();
     V* Uh = d->Uh.as<V>();
-    const kern::BoxArgs ba = box_args(d);
     const kern::BoxRec* br = d->boxrec.as<kern::BoxRec>();
+    const int64_t* toff = d->toff.as<int64_t>();
+    const int32_t* pmap = d->pmap.as<int32_t>();
     const int32_t* ge = d->gather_e.as<int32_t>();
     const int32_t* gp = d->gather_p.as<int32_t>();
     PassMarks pm(d, s);
@@ -301,11 +332,21 @@ void sweep(DeviceOp* d, const std::vector<IO>& io, int64_t nrhs, int dtype, hipS
     for (int l = L.max_level; l >= 2; --l) {
         const int b0 = L.level_ptr[l], nbx = L.level_ptr[l + 1] - b0;
         if (nbx <= 0) continue;
-        if (multi)
-            hipLaunchKernelGGL((kern::k_upward_mr<V, TT>), dim3(nbx), dim3(256), 0, s, br, ba.toff, ba.pmap, b0, Wp,
-                               T, Q, Qh);
-        else
-            hipLaunchKernelGGL((kern::k_upward<V, TT>), dim3(nbx), dim3(256), 0, s, ba, b0, Wp, T, Q, Qh);
+        if (multi) {
+            hipLaunchKernelGGL((kern::k_upward_mr<V, TT>), dim3(nbx), dim3(256), 0, s, br, toff, pmap, b0, Wp, T, Q,
+                               Qh);
+        } else {
+            const int64_t w0 = d->up_ptr[l], nwk = d->up_ptr[l + 1] - w0;
+            if (nwk <= 0) continue;
+            const int nw = d->up_nw[l];
+            const int2* wk = d->upwork.as<int2>() + w0;
+            if (P::nv == 1)
+                hipLaunchKernelGGL((kern::k_up_gemv<V, TT, 1>), dim3(nwk), dim3(64 * nw), 0, s, wk, br, toff, pmap, T,
+                                   Q, Q, Qh, nw);
+            else
+                hipLaunchKernelGGL((kern::k_up_gemv<V, TT, 2>), dim3(nwk), dim3(64 * nw), 0, s, wk, br, toff, pmap, T,
+                                   Q, Q, Qh, nw);
+        }
         SKF_HIP(hipGetLastError());
     }
     pm.mark(2);
@@ -321,13 +362,19 @@ void sweep(DeviceOp* d, const std::vector<IO>& io, int64_t nrhs, int dtype, hipS
         const int b0 = L.level_ptr[l], nbx = L.level_ptr[l + 1] - b0;
         if (nbx <= 0) continue;
         if (multi) {
-            hipLaunchKernelGGL((kern::k_downward_mr<V, TT>), dim3(nbx), dim3(256), 0, s, br, ba.toff, ba.pmap, b0, Wp,
-                               Tt, Uh, U);
+            hipLaunchKernelGGL((kern::k_downward_mr<V, TT>), dim3(nbx), dim3(256), 0, s, br, toff, pmap, b0, Wp, Tt,
+                               Uh, U);
         } else {
-            int kmax = 0;
-            for (int b = b0; b < b0 + nbx; ++b) kmax = std::max(kmax, L.kb[b]);
-            const size_t lds = std::max<size_t>(8, static_cast<size_t>(kmax) * sizeof(double));
-            hipLaunchKernelGGL((kern::k_downward<V, TT>), dim3(nbx), dim3(256), lds, s, ba, b0, Wp, T, Uh, U);
+            const int64_t w0 = d->down_ptr[l], nwk = d->down_ptr[l + 1] - w0;
+            if (nwk <= 0) continue;
+            const int nw = d->down_nw[l];
+            const int2* wk = d->downwork.as<int2>() + w0;
+            if (P::nv == 1)
+                hipLaunchKernelGGL((kern::k_down_gemv<V, TT, 1>), dim3(nwk), dim3(64 * nw), 0, s, wk, br, toff, pmap,
+                                   Tt, Uh, U, U, nw);
+            else
+                hipLaunchKernelGGL((kern::k_down_gemv<V, TT, 2>), dim3(nwk), dim3(64 * nw), 0, s, wk, br, toff, pmap,
+                                   Tt, Uh, U, U, nw);
         }
         SKF_HIP(hipGetLastError());
     }

@@ -113,91 +113,6 @@ __device__ __forceinline__ void green(double dx, double dy, double dz, typename 
     }
 }
 
-// ---------------------------------------------------------------------------
-// upward pass, one block per box of a level:
-//   qhat[i] = q[i] + sum_j T[i + j k] q[k + j]     (i < k)
-// lanes own rows i, the block's four waves split the columns j, LDS reduces.
-// ---------------------------------------------------------------------------
-struct BoxArgs {
-    const int64_t* voff;
-    const int64_t* hoff;
-    const int64_t* toff;
-    const int32_t* nb;
-    const int32_t* kb;
-    const int32_t* pmap;
-};
-
-template <typename V, typename TT>
-__global__ void __launch_bounds__(256) k_upward(BoxArgs a, int b0, int W, const TT* __restrict__ T,
-                                               V* __restrict__ Q, V* __restrict__ Qh) {
-    __shared__ double part[4][64];
-    const int b = b0 + blockIdx.x;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t voff = a.voff[b], hoff = a.hoff[b];
-    const int n = a.nb[b], k = a.kb[b];
-    const int m = n - k;
-    const TT* Tb = T + a.toff[b];
-    for (int c = 0; c < W; ++c) {
-        for (int r0 = 0; r0 < k; r0 += 64) {
-            const int i = r0 + lane;
-            double acc = 0.0;
-            if (i < k)
-                for (int j = wave; j < m; j += 4)
-                    acc = fma(static_cast<double>(Tb[i + static_cast<int64_t>(j) * k]),
-                              static_cast<double>(Q[(voff + k + j) * W + c]), acc);
-            part[wave][lane] = acc;
-            __syncthreads();
-            if (wave == 0 && i < k) {
-                const double s = static_cast<double>(Q[(voff + i) * W + c]) + part[0][lane] + part[1][lane] +
-                                 part[2][lane] + part[3][lane];
-                const V v = static_cast<V>(s);
-                Qh[(hoff + i) * W + c] = v;
-                Q[static_cast<int64_t>(a.pmap[hoff + i]) * W + c] = v;
-            }
-            __syncthreads();
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// downward pass, one block per box of a level:
-//   uhat = Uh + U_parent[pmap]; u[i] += uhat[i] (i < k); u[k+j] += sum_i T[i + j k] uhat[i]
-// Columns of T are contiguous: a wave reads a column with consecutive lanes
-// and reduces across the wave.
-// ---------------------------------------------------------------------------
-template <typename V, typename TT>
-__global__ void __launch_bounds__(256) k_downward(BoxArgs a, int b0, int W, const TT* __restrict__ T,
-                                                 const V* __restrict__ Uh, V* __restrict__ U) {
-    extern __shared__ double uh_s[];
-    const int b = b0 + blockIdx.x;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t voff = a.voff[b], hoff = a.hoff[b];
-    const int n = a.nb[b], k = a.kb[b];
-    const int m = n - k;
-    const TT* Tb = T + a.toff[b];
-    for (int c = 0; c < W; ++c) {
-        for (int i = threadIdx.x; i < k; i += blockDim.x) {
-            const double uh = static_cast<double>(Uh[(hoff + i) * W + c]) +
-                              static_cast<double>(U[static_cast<int64_t>(a.pmap[hoff + i]) * W + c]);
-            uh_s[i] = uh;
-            U[(voff + i) * W + c] = static_cast<V>(static_cast<double>(U[(voff + i) * W + c]) + uh);
-        }
-        __syncthreads();
-        for (int j = wave; j < m; j += 4) {
-            const TT* col = Tb + static_cast<int64_t>(j) * k;
-            double acc = 0.0;
-            for (int i = lane; i < k; i += 64) acc = fma(static_cast<double>(col[i]), uh_s[i], acc);
-            for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-            if (lane == 0)
-                U[(voff + k + j) * W + c] = static_cast<V>(static_cast<double>(U[(voff + k + j) * W + c]) + acc);
-        }
-        __syncthreads();
-    }
-}
-
-// ---------------------------------------------------------------------------
-// near field: ifo, ifs, tfo and the top-level direct sum in one launch
-// ---------------------------------------------------------------------------
 // Per-box record read with one scalar load.
 struct alignas(32) BoxRec {
     int64_t voff;     // first entry
@@ -208,6 +123,134 @@ struct alignas(32) BoxRec {
     int32_t leaf;
 };
 
+// ---------------------------------------------------------------------------
+// transfers with one right-hand side: batched GEMVs over the boxes of a level.
+// A block owns one (box, group of 64 rows).  The columns are cut into at most
+// kChunks chunks whose length depends only on the box; the block's nw waves
+// take chunks round-robin and wave 0 adds the chunk partials in chunk order,
+// so the result does not depend on nw (a batch and a single apply agree bit
+// for bit).  The matrix is column-major, so a wave reads 64 consecutive rows
+// of one column per load; the vector entry of that column is wave-uniform (a
+// scalar load).  Many waves per box keep enough loads in flight to stream T
+// from HBM.
+// ---------------------------------------------------------------------------
+constexpr int kChunks = 32;
+
+__device__ __forceinline__ int chunk_len(int cols) {
+    const int nch = min(kChunks, (cols + 31) / 32);
+    return nch > 0 ? (cols + nch - 1) / nch : 0;
+}
+
+// upward: qhat = q[0:k] + T q[k:n], written to Qh and to the parent's entries.
+// Qin / Qout are the same workspace: reads touch this level's entries, writes
+// the parent level's, so the two never overlap.
+template <typename V, typename TT, int NV>
+__global__ void __launch_bounds__(1024) k_up_gemv(const int2* __restrict__ work, const BoxRec* __restrict__ box,
+                                                  const int64_t* __restrict__ toff,
+                                                  const int32_t* __restrict__ pmap, const TT* __restrict__ T,
+                                                  const V* __restrict__ Qin, V* __restrict__ Qout,
+                                                  V* __restrict__ Qh, int nw) {
+    __shared__ double part[kChunks][64 * NV];
+    const int2 wk = work[blockIdx.x];
+    const BoxRec tb = box[wk.x];
+    const int k = tb.k, m = tb.n - tb.k;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int i = wk.y + lane;
+    const bool act = i < k;
+    const TT* __restrict__ Tb = T + toff[wk.x];
+    const V* __restrict__ xr = Qin + (tb.voff + k) * NV;
+    const int ch = chunk_len(m);
+    const int nch = ch > 0 ? (m + ch - 1) / ch : 0;
+    for (int c = wave; c < nch; c += nw) {
+        double acc[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+        const int j1 = min(m, (c + 1) * ch);
+#pragma unroll 4
+        for (int j = c * ch; j < j1; ++j) {
+            const double t = act ? static_cast<double>(Tb[i + static_cast<int64_t>(j) * k]) : 0.0;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) acc[v] = fma(t, static_cast<double>(xr[j * NV + v]), acc[v]);
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) part[c][lane * NV + v] = acc[v];
+    }
+    __syncthreads();
+    if (wave == 0 && act) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            double sum = static_cast<double>(Qin[(tb.voff + i) * NV + v]);
+            for (int c = 0; c < nch; ++c) sum += part[c][lane * NV + v];
+            const V val = static_cast<V>(sum);
+            Qh[(tb.hoff + i) * NV + v] = val;
+            Qout[static_cast<int64_t>(pmap[tb.hoff + i]) * NV + v] = val;
+        }
+    }
+}
+
+// downward: uhat = Uh + U_parent[pmap]; u[0:k] += uhat; u[k:n] += T^T uhat,
+// with Tt = T^T stored column-major (m x k) so rows of the result are contiguous.
+// Upar reads the parent level's entries, Uown updates this box's entries.
+template <typename V, typename TT, int NV>
+__global__ void __launch_bounds__(1024) k_down_gemv(const int2* __restrict__ work, const BoxRec* __restrict__ box,
+                                                    const int64_t* __restrict__ toff,
+                                                    const int32_t* __restrict__ pmap, const TT* __restrict__ Tt,
+                                                    const V* __restrict__ Uh, const V* __restrict__ Upar,
+                                                    V* __restrict__ Uown, int nw) {
+    __shared__ double part[kChunks][64 * NV];
+    const int2 wk = work[blockIdx.x];
+    const BoxRec tb = box[wk.x];
+    const int k = tb.k, m = tb.n - tb.k;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int j = wk.y + lane;
+    const bool act = j < m;
+    const TT* __restrict__ Tb = Tt + toff[wk.x];
+    const V* __restrict__ uhb = Uh + tb.hoff * NV;
+    const int32_t* __restrict__ pm = pmap + tb.hoff;
+    const int ch = m > 0 ? chunk_len(k) : 0;   // an uncompressed box has no T
+    const int nch = ch > 0 ? (k + ch - 1) / ch : 0;
+    for (int c = wave; c < nch; c += nw) {
+        double acc[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+        const int i1 = min(k, (c + 1) * ch);
+#pragma unroll 4
+        for (int i = c * ch; i < i1; ++i) {
+            const double t = act ? static_cast<double>(Tb[j + static_cast<int64_t>(i) * m]) : 0.0;
+            const int64_t pe = static_cast<int64_t>(pm[i]) * NV;
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+                acc[v] = fma(t, static_cast<double>(uhb[i * NV + v]) + static_cast<double>(Upar[pe + v]), acc[v]);
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) part[c][lane * NV + v] = acc[v];
+    }
+    __syncthreads();
+    if (wave == 0 && act) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            double sum = 0.0;
+            for (int c = 0; c < nch; ++c) sum += part[c][lane * NV + v];
+            V* u = Uown + (tb.voff + k + j) * NV + v;
+            *u = static_cast<V>(static_cast<double>(*u) + sum);
+        }
+    }
+    // the first row group of a box also adds uhat to the skeleton entries
+    if (wk.y == 0) {
+        for (int t = threadIdx.x; t < k * NV; t += blockDim.x) {
+            const int ii = t / NV, v = t - ii * NV;
+            V* u = Uown + (tb.voff + ii) * NV + v;
+            const double uh = static_cast<double>(uhb[t]) + static_cast<double>(Upar[static_cast<int64_t>(pm[ii]) * NV + v]);
+            *u = static_cast<V>(static_cast<double>(*u) + uh);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// near field: ifo, ifs, tfo and the top-level direct sum in one launch
+// ---------------------------------------------------------------------------
 // MODE 0: u += G w ;  1: u += G w, uh -= G wh ;  2: u += G w, uh -= G w ;  3: u += G (w - wh)
 template <class P, int TPL, bool CONJ, int MODE, bool MASK>
 __device__ __forceinline__ void near_loop(const Rec4<double>* __restrict__ X,

@@ -45,7 +45,7 @@ void proxy_points(const Plan& p, int lev, const int32_t* c, std::vector<double>&
     const double scale = p.opt.proxy_scale > 0 ? p.opt.proxy_scale : 2.95;
     Y.clear();
     if (p.dim == 3) {
-        const int q = p.opt.proxy_points > 0 ? p.opt.proxy_points : 12;
+        const int q = p.opt.proxy_points > 0 ? p.opt.proxy_points : 10;
         const double h = 0.5 * scale * a;
         std::vector<double> t(q);
         for (int i = 0; i < q; ++i) t[i] = std::cos((2.0 * i + 1.0) * kPi / (2.0 * q));
