@@ -78,7 +78,10 @@ typedef struct {
     int32_t keep_transparent;/* 1: also evaluate pairs of two uncompressed boxes, whose
                                 ifo terms cancel exactly (default 0: they are skipped) */
     int32_t f64_leaf;        /* C64/F32 applies: evaluate and accumulate the near field in float64 */
-    int32_t reserved[8];
+    int32_t nonsymmetric;    /* 1: evaluate both orders of every colleague pair separately (default 0:
+                                for the real Laplace kernels one evaluation of G(B_i, B_j) serves
+                                the ifo terms i <- j and j <- i; single-RHS applies only) */
+    int32_t reserved[7];
 } skelfmm_options;
 
 /* Build-time and layout statistics (section 5 / table "Notation for reported results"). */
@@ -92,7 +95,11 @@ typedef struct {
     int64_t pairs_skel;              /* extra skeleton-pair FMAs per apply (uhat part) */
     int64_t n_tasks;                 /* near-field work items */
     int32_t tile_targets;            /* targets per near-field work item */
-    int32_t reserved[7];
+    int32_t n_sym_tasks;             /* symmetric colleague-pair work items (0 when not paired) */
+    int64_t pairs_sym;               /* kernel evaluations of the paired colleague blocks (each serves
+                                        two of the pairs counted in pairs_near) */
+    int64_t pairs_sym_skel;          /* skeleton pairs inside them (two uhat multiply-adds each) */
+    int32_t reserved[2];
 } skelfmm_stats;
 
 /* Read-only host view of the skeleton operators, valid while the operator lives.
@@ -154,12 +161,14 @@ skelfmm_status skelfmm_autotune(skelfmm_op* op, skelfmm_dtype dtype, void* hip_s
 skelfmm_status skelfmm_set_targets_per_lane(skelfmm_op* op, int32_t tpl);
 
 /* Per-pass GPU timing.  When enabled, each apply records HIP events on its stream
- * around its passes: [0] gather, [1] upward pass, [2] near field (ifo, ifs, tfo,
- * top level), [3] downward pass, [4] output of top-level leaves.
+ * around its passes: [0] gather, [1] upward pass, [2] near field over the segment
+ * lists (ifo, ifs, tfo, top level; with symmetric pairing, what is left after
+ * pairing), [3] symmetric pairs (0 when not paired), [4] reduction of the pair
+ * slots into u and uhat (0 when not paired), [5] downward pass, [6] output scatter.
  * skelfmm_timing(op, 1) enables and zeroes the accumulators; (op, 0) disables.
  * skelfmm_timing_read waits for the recorded events and returns the summed
  * milliseconds per pass (ms[SKELFMM_NPASS]) and the number of timed sweeps. */
-#define SKELFMM_NPASS 5
+#define SKELFMM_NPASS 7
 skelfmm_status skelfmm_timing(skelfmm_op* op, int32_t enable);
 skelfmm_status skelfmm_timing_read(skelfmm_op* op, double* ms, int64_t* sweeps);
 skelfmm_status skelfmm_export(const skelfmm_op* op, skelfmm_plan_view* out);

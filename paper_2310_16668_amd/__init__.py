@@ -46,7 +46,7 @@ class Options(ctypes.Structure):
     _fields_ = [("proxy_shape", ctypes.c_int32), ("proxy_points", ctypes.c_int32),
                 ("proxy_scale", ctypes.c_double), ("no_compression", ctypes.c_int32),
                 ("num_threads", ctypes.c_int32), ("keep_transparent", ctypes.c_int32),
-                ("f64_leaf", ctypes.c_int32), ("reserved", ctypes.c_int32 * 8)]
+                ("f64_leaf", ctypes.c_int32), ("nonsymmetric", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
 
 
 class Stats(ctypes.Structure):
@@ -55,7 +55,8 @@ class Stats(ctypes.Structure):
                 ("proxy_count", ctypes.c_int32), ("t_tree", ctypes.c_double), ("t_skel", ctypes.c_double),
                 ("m_proj_elems", ctypes.c_int64), ("n_entries", ctypes.c_int64),
                 ("pairs_near", ctypes.c_int64), ("pairs_skel", ctypes.c_int64), ("n_tasks", ctypes.c_int64),
-                ("tile_targets", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+                ("tile_targets", ctypes.c_int32), ("n_sym_tasks", ctypes.c_int32), ("pairs_sym", ctypes.c_int64),
+                ("pairs_sym_skel", ctypes.c_int64), ("reserved", ctypes.c_int32 * 2)]
 
 
 _P = ctypes.POINTER
@@ -102,7 +103,7 @@ EXPORTED = ("skelfmm_build", "skelfmm_prepare", "skelfmm_apply", "skelfmm_apply_
             "skelfmm_export", "skelfmm_batch_create", "skelfmm_batch_apply", "skelfmm_batch_destroy",
             "skelfmm_destroy", "skelfmm_last_error", "skelfmm_timing", "skelfmm_timing_read",
             "skelfmm_autotune", "skelfmm_set_targets_per_lane")
-PASSES = ("gather", "upward", "near_field", "downward", "output")
+PASSES = ("gather", "upward", "near_field", "near_pairs", "near_reduce", "downward", "output")
 
 
 def _check(status: int):
@@ -244,8 +245,12 @@ class Operator:
 
 def build(points, kind: str = "laplace", tol: float = 1e-6, leaf_size: int = 64, kappa: float = 0.0,
           proxy_shape: int = 0, proxy_points: int = 0, proxy_scale: float = 0.0, no_compression: bool = False,
-          num_threads: int = 0, keep_transparent: bool = False, f64_leaf: bool = False) -> Operator:
-    """Build the skeleton operator for ``points`` (n x dim, host, float64)."""
+          num_threads: int = 0, keep_transparent: bool = False, f64_leaf: bool = False,
+          symmetric: bool = True) -> Operator:
+    """Build the skeleton operator for ``points`` (n x dim, host, float64).
+
+    ``symmetric=False`` evaluates both orders of every colleague pair separately
+    (the pairing applies to the real Laplace kernels with one right-hand side)."""
     pts = np.ascontiguousarray(points, dtype=np.float64)
     if pts.ndim != 2:
         raise ValueError("points must be n x dim")
@@ -255,6 +260,7 @@ def build(points, kind: str = "laplace", tol: float = 1e-6, leaf_size: int = 64,
     o.proxy_shape, o.proxy_points, o.proxy_scale = proxy_shape, proxy_points, proxy_scale
     o.no_compression, o.num_threads = int(no_compression), num_threads
     o.keep_transparent, o.f64_leaf = int(keep_transparent), int(f64_leaf)
+    o.nonsymmetric = int(not symmetric)
     h = _vp()
     _check(_lib.skelfmm_build(pts.ctypes.data_as(_P(ctypes.c_double)), n, k, tol, leaf_size,
                               ctypes.byref(o), ctypes.byref(h)))

@@ -115,7 +115,8 @@ skelfmm_status skelfmm_build(const double* points, int64_t n, skelfmm_kernel ker
                 throw std::invalid_argument("invalid proxy options");
             if (p.opt.proxy_shape == 2 && p.dim == 3) throw std::invalid_argument("the proxy circle is 2D only");
             skelfmm::build_plan(p);
-            op->dev = skelfmm::device_create(p, op->opt.keep_transparent != 0, op->opt.f64_leaf != 0);
+            op->dev = skelfmm::device_create(p, op->opt.keep_transparent != 0, op->opt.f64_leaf != 0,
+                                             op->opt.nonsymmetric == 0);
         } catch (...) {
             delete op;
             throw;

@@ -30,6 +30,23 @@ struct Task {
     int32_t t0;       // first target entry (relative to the box)
 };
 
+// One symmetric colleague-pair work item: the kernel block G(B_i, B_j) is
+// evaluated once and serves u_i (forward) and u_j (reverse).
+struct SymTask {
+    int32_t bi, bj;   // target-side box (lanes) and source-side box (wave-uniform)
+    int32_t t0, t1;   // target entries [t0, t1) of bi
+    int64_t fwd;      // slots: u of targets [t0, t1), then uhat of targets [t0, min(k_i, t1))
+    int64_t rev;      // slots: u of all n_j sources, then (when t0 < k_i) uhat of the k_j skeleton sources
+};
+
+// A run of slots added into one box's u (kind 0) or uhat (kind 1) entries [e0, e1).
+struct Contrib {
+    int64_t slot;
+    int32_t e0, e1;
+    int32_t kind;
+    int32_t pad;
+};
+
 // Host copy of everything the GPU sweep reads.  Built without touching a GPU.
 struct Layout {
     int dim = 3, kind = 0;
@@ -56,11 +73,23 @@ struct Layout {
     std::vector<Task> tasks;        // built for `tile` targets per work item
     int tile = 128;
     int64_t pairs_near = 0, pairs_skel = 0;
+    // symmetric pairs (real kernels, one RHS): the colleague pairs they cover are
+    // removed from the *_ns segment lists, which serve the one-RHS near field
+    bool sym = false;
+    std::vector<int32_t> seg_ptr_ns, seg_src_ns, seg_mode_ns;
+    std::vector<SymTask> sym_tasks;
+    std::vector<int32_t> red_boxes, red_ptr;     // boxes receiving slots, CSR into red_list
+    std::vector<Contrib> red_list;
+    int64_t slot_size = 0;
+    int64_t pairs_sym = 0, pairs_sym_skel = 0;
 };
 
 Layout make_layout(const Plan& p, bool keep_transparent, int tile);
-// Work list for another tile size (same segments), largest estimated cost first.
-std::vector<Task> make_tasks(const Layout& L, int tile);
+// Work list for another tile size, largest estimated cost first, over the full
+// segment lists (ns = false) or the lists left after symmetric pairing (ns = true).
+std::vector<Task> make_tasks(const Layout& L, int tile, bool ns = false);
+// Pair up colleague segments of compressed boxes for the symmetric near field.
+void make_symmetric(Layout& L, int group);
 // One layout for several operators: boxes renumbered by (level, operator), entry,
 // skeleton-entry and T offsets shifted, one cost-sorted work list over all of
 // them.  entry_base / hentry_base receive each operator's first entry / skeleton entry.
@@ -69,7 +98,7 @@ Layout merge_layouts(const std::vector<const Layout*>& ls, std::vector<int64_t>&
 struct DeviceOp;
 struct DeviceBatch;
 
-DeviceOp* device_create(const Plan& p, bool keep_transparent, bool f64_leaf);
+DeviceOp* device_create(const Plan& p, bool keep_transparent, bool f64_leaf, bool symmetric);
 void device_prepare(DeviceOp* d, int64_t nrhs_max, int dtype);
 void device_apply(DeviceOp* d, const void* q, void* u, int64_t nrhs, int dtype, void* stream, bool adjoint);
 void device_fill_stats(const DeviceOp* d, skelfmm_stats* out);

@@ -108,12 +108,17 @@ struct DeviceOp {
     int tpl = kDefaultTPL;
     DevMem tasks[3];                              // work lists for 1, 2, 4 targets per lane
     int ntasks[3] = {0, 0, 0};
+    // symmetric near field (one RHS): segment lists without the paired ifo
+    // terms, their work lists, the pair items, the slot reduction lists
+    DevMem seg_ptr_ns, segs_ns, tasks_ns[3], symtasks, red_boxes, red_ptr, red_list, slots;
+    int ntasks_ns[3] = {0, 0, 0};
+    int nsym = 0, nred = 0;
     // workspace
     DevMem Q, Qh, U, Uh;
     // per-pass timing
     bool timing = false;
     std::vector<std::array<hipEvent_t, SKELFMM_NPASS + 1>> pending;
-    double pass_ms[SKELFMM_NPASS] = {0, 0, 0, 0, 0};
+    double pass_ms[SKELFMM_NPASS] = {};
     int64_t sweeps = 0;
     ~DeviceOp() {
         for (auto& ev : pending)
@@ -133,9 +138,14 @@ static void check_ranks(const Layout& L) {
     if (kmax > 8192) throw NotSupported("skeleton rank above 8192 is not supported by the downward kernel");
 }
 
-DeviceOp* device_create(const Plan& p, bool keep_transparent, bool f64_leaf) {
+// Targets of the larger box per symmetric work item (a multiple of 64 x 4).
+constexpr int kSymGroup = 512;
+
+DeviceOp* device_create(const Plan& p, bool keep_transparent, bool f64_leaf, bool symmetric) {
     auto d = std::make_unique<DeviceOp>();
     d->L = make_layout(p, keep_transparent, 64 * kDefaultTPL);
+    // the pairing needs G(x, y) = G(y, x) with real values
+    if (symmetric && p.kind == 0) make_symmetric(d->L, kSymGroup);
     d->f64_leaf = f64_leaf;
     check_ranks(d->L);
     return d.release();
@@ -198,6 +208,24 @@ static void upload(DeviceOp* d, int dtype) {
             d->tasks[tpl_slot(t)].upload(tl);
             d->ntasks[tpl_slot(t)] = static_cast<int>(tl.size());
         }
+        if (L.sym) {
+            d->seg_ptr_ns.upload(L.seg_ptr_ns);
+            std::vector<int2> sn(L.seg_src_ns.size());
+            for (size_t i = 0; i < sn.size(); ++i) sn[i] = make_int2(L.seg_src_ns[i], L.seg_mode_ns[i]);
+            d->segs_ns.upload(sn);
+            d->symtasks.upload(L.sym_tasks);
+            d->nsym = static_cast<int>(L.sym_tasks.size());
+            for (int t : {1, 2, 4}) {
+                const std::vector<Task> tl = make_tasks(L, 64 * t, true);
+                d->tasks_ns[tpl_slot(t)].upload(tl);
+                d->ntasks_ns[tpl_slot(t)] = static_cast<int>(tl.size());
+            }
+            d->red_boxes.upload(L.red_boxes);
+            d->red_ptr.upload(L.red_ptr);
+            d->red_list.upload(L.red_list);
+            d->nred = static_cast<int>(L.red_boxes.size());
+            d->slots.alloc(static_cast<size_t>(L.slot_size) * sizeof(double));
+        }
         std::vector<kern::BoxRec> br(L.n_boxes);
         for (int b = 0; b < L.n_boxes; ++b)
             br[b] = kern::BoxRec{L.voff[b], L.hoff[b], L.nb[b], L.kb[b], L.level[b], L.is_leaf[b]};
@@ -248,25 +276,68 @@ struct IO {
     int64_t cnt;    // number of points
 };
 
+// Events bracketing the passes of one sweep (only when timing is on).
+struct PassMarks {
+    DeviceOp* d;
+    hipStream_t s;
+    std::array<hipEvent_t, SKELFMM_NPASS + 1> ev{};
+    PassMarks(DeviceOp* d_, hipStream_t s_) : d(d_), s(s_) {
+        if (!d->timing) return;
+        for (auto& e : ev) SKF_HIP(hipEventCreate(&e));
+    }
+    void mark(int i) {
+        if (d->timing) SKF_HIP(hipEventRecord(ev[i], s));
+    }
+    void done() {
+        if (d->timing) d->pending.push_back(ev);
+    }
+};
+
+// The one-RHS near field: k_near over the segment lists; with symmetric pairing
+// it covers what is left after pairing, then k_near_sym evaluates the pairs
+// into slots and k_sym_reduce adds the slots to u and uhat.
 template <class P, int TPL, bool CONJ>
-void launch_near_t(const DeviceOp* d, hipStream_t s, void* Q, void* Qh, void* U, void* Uh) {
-    const int ntasks = d->ntasks[tpl_slot(TPL)];
-    if (ntasks == 0) return;
+void launch_near_t(const DeviceOp* d, hipStream_t s, void* Q, void* Qh, void* U, void* Uh, PassMarks* pm) {
     using R = typename P::Rt;
     using V = typename P::Vt;
-    hipLaunchKernelGGL((kern::k_near<P, TPL, CONJ>), dim3(blocks_for(ntasks, 4)), dim3(256), 0, s,
-                       d->tasks[tpl_slot(TPL)].as<Task>(), ntasks, d->seg_ptr.as<int32_t>(), d->segs.as<int2>(),
-                       d->boxrec.as<kern::BoxRec>(), d->X64.as<kern::Rec4<double>>(), static_cast<const V*>(Q),
-                       static_cast<const V*>(Qh), static_cast<V*>(U), static_cast<V*>(Uh),
-                       static_cast<R>(d->L.kappa), kern::kInv4Pi);
-    SKF_HIP(hipGetLastError());
+    const int ts = tpl_slot(TPL);
+    const bool sym = d->L.sym;
+    const int ntasks = sym ? d->ntasks_ns[ts] : d->ntasks[ts];
+    if (ntasks > 0) {
+        hipLaunchKernelGGL((kern::k_near<P, TPL, CONJ>), dim3(blocks_for(ntasks, 4)), dim3(256), 0, s,
+                           (sym ? d->tasks_ns[ts] : d->tasks[ts]).as<Task>(), ntasks,
+                           (sym ? d->seg_ptr_ns : d->seg_ptr).as<int32_t>(), (sym ? d->segs_ns : d->segs).as<int2>(),
+                           d->boxrec.as<kern::BoxRec>(), d->X64.as<kern::Rec4<double>>(), static_cast<const V*>(Q),
+                           static_cast<const V*>(Qh), static_cast<V*>(U), static_cast<V*>(Uh),
+                           static_cast<R>(d->L.kappa), kern::kInv4Pi);
+        SKF_HIP(hipGetLastError());
+    }
+    if (pm) pm->mark(3);
+    if constexpr (P::kind == 0) {
+        if (sym && d->nsym > 0) {
+            hipLaunchKernelGGL((kern::k_near_sym<P, TPL>), dim3(blocks_for(d->nsym, 4)), dim3(256), 0, s,
+                               d->symtasks.as<SymTask>(), d->nsym, d->boxrec.as<kern::BoxRec>(),
+                               d->X64.as<kern::Rec4<double>>(), static_cast<const V*>(Q), static_cast<const V*>(Qh),
+                               d->slots.as<double>(), kern::kInv4Pi);
+            SKF_HIP(hipGetLastError());
+        }
+    }
+    if (pm) pm->mark(4);
+    if constexpr (P::kind == 0) {
+        if (sym && d->nred > 0) {
+            hipLaunchKernelGGL((kern::k_sym_reduce<V>), dim3(d->nred), dim3(256), 0, s, d->red_boxes.as<int32_t>(),
+                               d->red_ptr.as<int32_t>(), d->red_list.as<Contrib>(), d->boxrec.as<kern::BoxRec>(),
+                               d->slots.as<double>(), static_cast<V*>(U), static_cast<V*>(Uh));
+            SKF_HIP(hipGetLastError());
+        }
+    }
 }
 
 template <class P, bool CONJ>
-void launch_near(const DeviceOp* d, hipStream_t s, void* Q, void* Qh, void* U, void* Uh) {
-    if (d->tpl == 1) launch_near_t<P, 1, CONJ>(d, s, Q, Qh, U, Uh);
-    else if (d->tpl == 4) launch_near_t<P, 4, CONJ>(d, s, Q, Qh, U, Uh);
-    else launch_near_t<P, 2, CONJ>(d, s, Q, Qh, U, Uh);
+void launch_near(const DeviceOp* d, hipStream_t s, void* Q, void* Qh, void* U, void* Uh, PassMarks* pm = nullptr) {
+    if (d->tpl == 1) launch_near_t<P, 1, CONJ>(d, s, Q, Qh, U, Uh, pm);
+    else if (d->tpl == 4) launch_near_t<P, 4, CONJ>(d, s, Q, Qh, U, Uh, pm);
+    else launch_near_t<P, 2, CONJ>(d, s, Q, Qh, U, Uh, pm);
 }
 
 template <class P, bool CONJ, typename Am>
@@ -284,23 +355,6 @@ void launch_near_mr(const DeviceOp* d, hipStream_t s, int Wp, void* Q, void* Qh,
                        static_cast<R>(d->L.kappa), kern::kInv4Pi);
     SKF_HIP(hipGetLastError());
 }
-
-// Events bracketing the passes of one sweep (only when timing is on).
-struct PassMarks {
-    DeviceOp* d;
-    hipStream_t s;
-    std::array<hipEvent_t, SKELFMM_NPASS + 1> ev{};
-    PassMarks(DeviceOp* d_, hipStream_t s_) : d(d_), s(s_) {
-        if (!d->timing) return;
-        for (auto& e : ev) SKF_HIP(hipEventCreate(&e));
-    }
-    void mark(int i) {
-        if (d->timing) SKF_HIP(hipEventRecord(ev[i], s));
-    }
-    void done() {
-        if (d->timing) d->pending.push_back(ev);
-    }
-};
 
 // One sweep.  V: stored values; TT: transfer matrices; P: near-field policy;
 // Am: accumulator of one source box's partial sums in the multi-RHS near field.
@@ -353,11 +407,13 @@ void sweep(DeviceOp* d, const std::vector<IO>& io, int64_t nrhs, int dtype, hipS
     if (multi) {
         if (adjoint && P::kind == 1) launch_near_mr<P, true, Am>(d, s, Wp, Q, Qh, U, Uh);
         else launch_near_mr<P, false, Am>(d, s, Wp, Q, Qh, U, Uh);
+        pm.mark(3);
+        pm.mark(4);
     } else {
-        if (adjoint && P::kind == 1) launch_near<P, true>(d, s, Q, Qh, U, Uh);
-        else launch_near<P, false>(d, s, Q, Qh, U, Uh);
+        if (adjoint && P::kind == 1) launch_near<P, true>(d, s, Q, Qh, U, Uh, &pm);
+        else launch_near<P, false>(d, s, Q, Qh, U, Uh, &pm);
     }
-    pm.mark(3);
+    pm.mark(5);
     for (int l = 2; l <= L.max_level; ++l) {
         const int b0 = L.level_ptr[l], nbx = L.level_ptr[l + 1] - b0;
         if (nbx <= 0) continue;
@@ -378,14 +434,14 @@ void sweep(DeviceOp* d, const std::vector<IO>& io, int64_t nrhs, int dtype, hipS
         }
         SKF_HIP(hipGetLastError());
     }
-    pm.mark(4);
+    pm.mark(6);
     for (const IO& x : io) {
         if (x.cnt <= 0) continue;
         hipLaunchKernelGGL((kern::k_scatter_pad<V, V>), dim3(blocks_for(x.cnt * Win, 256)), dim3(256), 0, s,
                            ge + x.g0, gp + x.g0, x.cnt, Win, Wp, U, static_cast<V*>(x.u));
         SKF_HIP(hipGetLastError());
     }
-    pm.mark(5);
+    pm.mark(7);
     pm.done();
 }
 
@@ -479,8 +535,12 @@ void device_fill_stats(const DeviceOp* d, skelfmm_stats* out) {
     out->n_entries = d->L.n_entries;
     out->pairs_near = d->L.pairs_near;
     out->pairs_skel = d->L.pairs_skel;
-    out->n_tasks = d->uploaded ? d->ntasks[tpl_slot(d->tpl)] : static_cast<int64_t>(d->L.tasks.size());
+    out->n_tasks = d->uploaded ? (d->L.sym ? d->ntasks_ns : d->ntasks)[tpl_slot(d->tpl)]
+                               : static_cast<int64_t>(d->L.tasks.size());
     out->tile_targets = 64 * d->tpl;
+    out->n_sym_tasks = static_cast<int32_t>(d->L.sym_tasks.size());
+    out->pairs_sym = d->L.pairs_sym;
+    out->pairs_sym_skel = d->L.pairs_sym_skel;
 }
 
 void device_destroy(DeviceOp* d) { delete d; }
@@ -521,6 +581,9 @@ DeviceBatch* batch_create(const std::vector<DeviceOp*>& ops) {
     std::vector<int64_t> ebase;
     b->merged = std::make_unique<DeviceOp>();
     b->merged->L = merge_layouts(ls, ebase);
+    for (auto* o : ops)
+        if (o->L.sym != ops[0]->L.sym) throw std::invalid_argument("batched operators must share the pairing option");
+    if (ops[0]->L.sym) make_symmetric(b->merged->L, kSymGroup);
     b->merged->f64_leaf = ops[0]->f64_leaf;
     check_ranks(b->merged->L);
     b->gbase.assign(ops.size() + 1, 0);

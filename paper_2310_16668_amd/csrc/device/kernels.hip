@@ -325,26 +325,19 @@ __device__ __forceinline__ void near_segment(int mode, bool has_h, const Rec4<do
     }
 }
 
-// One wavefront per work item; every pointer is a separate restrict argument so
-// the compiler can prove the source data is never written by this kernel and
-// read it with scalar loads.  Segment modes carry SEG_SELF when the source box
-// is the target box.
+// One work item of the segment lists: TPL targets per lane of one target box
+// against every source box on its list.  Segment modes carry SEG_SELF when the
+// source box is the target box.
 template <class P, int TPL, bool CONJ>
-__global__ void __launch_bounds__(256) k_near(const Task* __restrict__ tasks, int ntasks,
-                                              const int32_t* __restrict__ seg_ptr, const int2* __restrict__ segs,
-                                              const BoxRec* __restrict__ box,
-                                              const Rec4<double>* __restrict__ X,
-                                              const typename P::Vt* __restrict__ Q,
-                                              const typename P::Vt* __restrict__ Qh,
-                                              typename P::Vt* __restrict__ U, typename P::Vt* __restrict__ Uh,
-                                              typename P::Rt kappa, double scale) {
+__device__ __forceinline__ void near_item(const Task tk, const int32_t* __restrict__ seg_ptr,
+                                          const int2* __restrict__ segs, const BoxRec* __restrict__ box,
+                                          const Rec4<double>* __restrict__ X, const typename P::Vt* __restrict__ Q,
+                                          const typename P::Vt* __restrict__ Qh, typename P::Vt* __restrict__ U,
+                                          typename P::Vt* __restrict__ Uh, typename P::Rt kappa, double scale,
+                                          int lane) {
     using A = typename P::At;
     using V = typename P::Vt;
     constexpr int nv = P::nv;
-    const int lane = threadIdx.x & 63;
-    const int tid = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (tid >= ntasks) return;
-    const Task tk = tasks[tid];
     const BoxRec tb = box[tk.box];
     // boxes at or above the top level carry k = 0: no skeleton part
     const bool has_h = tk.t0 < tb.k;
@@ -384,6 +377,284 @@ __global__ void __launch_bounds__(256) k_near(const Task* __restrict__ tasks, in
                 for (int v = 0; v < nv; ++v) Uh[(tb.hoff + t) * nv + v] = static_cast<V>(acch[p][v] * sc);
             }
         }
+    }
+}
+
+// One wavefront per work item; every pointer is a separate restrict argument so
+// the compiler can prove the source data is never written by this kernel and
+// read it with scalar loads.
+template <class P, int TPL, bool CONJ>
+__global__ void __launch_bounds__(256) k_near(const Task* __restrict__ tasks, int ntasks,
+                                              const int32_t* __restrict__ seg_ptr, const int2* __restrict__ segs,
+                                              const BoxRec* __restrict__ box,
+                                              const Rec4<double>* __restrict__ X,
+                                              const typename P::Vt* __restrict__ Q,
+                                              const typename P::Vt* __restrict__ Qh,
+                                              typename P::Vt* __restrict__ U, typename P::Vt* __restrict__ Uh,
+                                              typename P::Rt kappa, double scale) {
+    const int lane = threadIdx.x & 63;
+    const int tid = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (tid >= ntasks) return;
+    near_item<P, TPL, CONJ>(tasks[tid], seg_ptr, segs, box, X, Q, Qh, U, Uh, kappa, scale, lane);
+}
+
+// ---------------------------------------------------------------------------
+// symmetric near field (real kernels, one right-hand side)
+// ---------------------------------------------------------------------------
+// For distinct colleagues i != j (and distinct boxes of the top level) the
+// terms i <- j and j <- i use the same block G(B_i, B_j) of a symmetric kernel,
+// the second as its transpose.  A work item holds up to 64 TPL targets of box i
+// per pass in its lanes and walks the sources of box j in wave-uniform blocks of
+// 16; each kernel value serves both directions:
+//   forward  u_i[t]  += G(t, s) q_j[s]          uhat_i[t] -= G(t, s) qhat_j[s]
+//   reverse  u_j[s]  += G(t, s) q_i[t]          uhat_j[s] -= G(t, s) qhat_i[t]
+// (uhat parts for skeleton targets and sources only; top-level boxes have none).
+// The forward sums stay in the lanes.  The reverse sums over the lanes are
+// formed per block: each lane keeps its partial for every source of the block,
+// the 16 x 64 partials pass through the wave's own LDS tile, four lanes add one
+// source's column and a quad exchange completes it.  All sums go to the item's
+// private slots in a fixed order; k_sym_reduce adds them to u and uhat.
+
+constexpr int kSymBlock = 16;            // sources per block
+constexpr int kSymRow = 68;              // LDS row pitch: the column reads below hit distinct banks
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Column sums of the wave's kSymBlock x 64 partials r[c] (lane = column of the
+// tile).  Returns, in every lane 4c..4c+3, the sum over the 64 lanes of r[c].
+template <typename B>
+__device__ __forceinline__ B column_sum(const B (&r)[kSymBlock], B* tile, int lane) {
+#pragma unroll
+    for (int c = 0; c < kSymBlock; ++c) tile[c * kSymRow + lane] = r[c];
+    wave_sync();
+    const int c = lane >> 2, q = lane & 3;
+    B v = B(0);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v += tile[c * kSymRow + q + 4 * i];
+    wave_sync();
+    v += __shfl_xor(v, 1);
+    v += __shfl_xor(v, 2);
+    return v;
+}
+
+// One source of a block, staged in the wave's LDS area.
+template <typename R>
+struct alignas(16) SrcRec {
+    double x, y, z;
+    R w, wh;
+};
+
+// One block of up to kSymBlock sources s0 .. s0 + cnt - 1 of box j, read from
+// the wave's staged copy src[0 .. kSymBlock).  H: the pass holds skeleton
+// targets and the block lies in j's skeleton, so the uhat terms run too.
+// Positions past cnt repeat the last source with zero charges (their reverse
+// sums are not stored), so the block is branch-free.  Reverse sums go to
+// rev_u[s] (and rev_h[s]), stored on the item's first pass and accumulated on
+// later ones.
+template <class P, int TPL, bool H>
+__device__ __forceinline__ void sym_block(const SrcRec<typename P::Rt>* src, int s0, int cnt,
+                                          const double (&xt)[TPL], const double (&yt)[TPL],
+                                          const double (&zt)[TPL], const typename P::Rt (&wi)[TPL],
+                                          const typename P::Rt (&whi)[TPL], typename P::At (&acc)[TPL],
+                                          typename P::At (&acch)[TPL], typename P::Rt* tile, int lane,
+                                          double* __restrict__ rev_u, double* __restrict__ rev_h, bool first,
+                                          double sc) {
+    using R = typename P::Rt;
+    using A = typename P::At;
+    // the running reverse sums of earlier passes are fetched before the block's
+    // arithmetic, so their latency overlaps it
+    const int cs = lane >> 2;
+    const bool own = (lane & 3) == 0 && cs < cnt;
+    double prev_u = 0.0, prev_h = 0.0;
+    if (own && !first) {
+        prev_u = rev_u[s0 + cs];
+        if constexpr (H) prev_h = rev_h[s0 + cs];
+    }
+    R bacc[TPL], bh[TPL];
+    R ru[kSymBlock], rh[kSymBlock];
+#pragma unroll
+    for (int p = 0; p < TPL; ++p) { bacc[p] = R(0); bh[p] = R(0); }
+#pragma unroll
+    for (int c = 0; c < kSymBlock; ++c) {
+        const SrcRec<R> sv = src[c];
+        ru[c] = R(0);
+        rh[c] = R(0);
+#pragma unroll
+        for (int p = 0; p < TPL; ++p) {
+            R g, gi;
+            green<P, false, false>(xt[p] - sv.x, yt[p] - sv.y, zt[p] - sv.z, R(0), g, gi);
+            bacc[p] = fma(g, sv.w, bacc[p]);
+            ru[c] = fma(g, wi[p], ru[c]);
+            if constexpr (H) {
+                bh[p] = fma(g, sv.wh, bh[p]);
+                rh[c] = fma(g, whi[p], rh[c]);
+            }
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < TPL; ++p) {
+        acc[p] += static_cast<A>(bacc[p]);
+        if constexpr (H) acch[p] += static_cast<A>(bh[p]);
+    }
+    {
+        const R v = column_sum<R>(ru, tile, lane);
+        if (own) rev_u[s0 + cs] = prev_u + sc * static_cast<double>(v);
+    }
+    if constexpr (H) {
+        const R v = column_sum<R>(rh, tile, lane);
+        if (own) rev_h[s0 + cs] = prev_h - sc * static_cast<double>(v);
+    }
+}
+
+// Sources of a pass in blocks: first the skeleton blocks [0, kH) (kH = k_j when
+// the uhat terms run, else 0), then the rest [kH, n_j), 16 at a time.
+struct BlockPlan {
+    int kH, nbH, nb, n;
+    __device__ void range(int b, int& s0, int& cnt) const {
+        if (b < nbH) { s0 = b * kSymBlock; cnt = min(kSymBlock, kH - s0); }
+        else { s0 = kH + (b - nbH) * kSymBlock; cnt = min(kSymBlock, n - s0); }
+    }
+};
+
+// Lanes 0..15 fetch the sources of block b from global memory into registers
+// (lanes past the block's count repeat its last source with zero charges).
+template <class P>
+__device__ __forceinline__ void stage_load(const BlockPlan& bp, int b, const Rec4<double>* __restrict__ Xs,
+                                           const typename P::Vt* __restrict__ Qs,
+                                           const typename P::Vt* __restrict__ Qhs, int lane,
+                                           SrcRec<typename P::Rt>& r) {
+    using R = typename P::Rt;
+    int s0, cnt;
+    bp.range(b, s0, cnt);
+    if (lane < kSymBlock) {
+        const int si = s0 + min(lane, cnt - 1);
+        const Rec4<double> x = Xs[si];
+        r.x = x.x;
+        r.y = x.y;
+        r.z = x.z;
+        r.w = lane < cnt ? static_cast<R>(Qs[si]) : R(0);
+        r.wh = (lane < cnt && b < bp.nbH) ? static_cast<R>(Qhs[si]) : R(0);
+    }
+}
+
+template <class P, int TPL>
+__device__ __forceinline__ void sym_item(const SymTask it, const BoxRec* __restrict__ box,
+                                         const Rec4<double>* __restrict__ X, const typename P::Vt* __restrict__ Q,
+                                         const typename P::Vt* __restrict__ Qh, double* __restrict__ slots,
+                                         double scale, typename P::Rt* tile, SrcRec<typename P::Rt>* src,
+                                         int lane) {
+    using R = typename P::Rt;
+    using A = typename P::At;
+    using V = typename P::Vt;
+    const BoxRec bi = box[it.bi];
+    const BoxRec bj = box[it.bj];
+    const Rec4<double>* Xs = X + bj.voff;
+    const V* Qs = Q + bj.voff;
+    const V* Qhs = Qh + bj.hoff;
+    double* fwd_u = slots + it.fwd;
+    double* fwd_h = fwd_u + (it.t1 - it.t0);
+    double* rev_u = slots + it.rev;
+    double* rev_h = rev_u + bj.n;
+    const double sc = scale * P::gscale;
+
+    for (int tp = it.t0; tp < it.t1; tp += 64 * TPL) {
+        const bool first = tp == it.t0;
+        // skeleton targets in this pass and a skeleton in box j: the uhat terms run
+        const bool hp = tp < bi.k && bj.k > 0;
+        BlockPlan bp;
+        bp.kH = hp ? bj.k : 0;
+        bp.nbH = (bp.kH + kSymBlock - 1) / kSymBlock;
+        bp.n = bj.n;
+        bp.nb = bp.nbH + (bj.n - bp.kH + kSymBlock - 1) / kSymBlock;
+        double xt[TPL], yt[TPL], zt[TPL];
+        R wi[TPL], whi[TPL];
+        A acc[TPL], acch[TPL];
+#pragma unroll
+        for (int p = 0; p < TPL; ++p) {
+            const int t = tp + lane + 64 * p;
+            const bool ok = t < it.t1;
+            const int tc = ok ? t : it.t1 - 1;
+            const Rec4<double> x = X[bi.voff + tc];
+            xt[p] = x.x; yt[p] = x.y; zt[p] = x.z;
+            wi[p] = ok ? static_cast<R>(Q[bi.voff + tc]) : R(0);
+            whi[p] = (ok && t < bi.k) ? static_cast<R>(Qh[bi.hoff + t]) : R(0);
+            acc[p] = A(0);
+            acch[p] = A(0);
+        }
+        // the next block's sources are fetched while the current one is evaluated
+        SrcRec<R> staged{};
+        stage_load<P>(bp, 0, Xs, Qs, Qhs, lane, staged);
+        for (int b = 0; b < bp.nb; ++b) {
+            int s0, cnt;
+            bp.range(b, s0, cnt);
+            wave_sync();
+            if (lane < kSymBlock) src[lane] = staged;
+            wave_sync();
+            if (b + 1 < bp.nb) stage_load<P>(bp, b + 1, Xs, Qs, Qhs, lane, staged);
+            if (b < bp.nbH)
+                sym_block<P, TPL, true>(src, s0, cnt, xt, yt, zt, wi, whi, acc, acch, tile, lane, rev_u, rev_h,
+                                        first, sc);
+            else
+                sym_block<P, TPL, false>(src, s0, cnt, xt, yt, zt, wi, whi, acc, acch, tile, lane, rev_u, rev_h,
+                                         first, sc);
+        }
+#pragma unroll
+        for (int p = 0; p < TPL; ++p) {
+            const int t = tp + lane + 64 * p;
+            if (t < it.t1) {
+                fwd_u[t - it.t0] = sc * static_cast<double>(acc[p]);
+                if (t < bi.k) fwd_h[t - it.t0] = -sc * static_cast<double>(acch[p]);
+            }
+        }
+    }
+}
+
+template <class P, int TPL>
+__global__ void __launch_bounds__(256) k_near_sym(const SymTask* __restrict__ tasks, int ntasks,
+                                                  const BoxRec* __restrict__ box,
+                                                  const Rec4<double>* __restrict__ X,
+                                                  const typename P::Vt* __restrict__ Q,
+                                                  const typename P::Vt* __restrict__ Qh,
+                                                  double* __restrict__ slots, double scale) {
+    using R = typename P::Rt;
+    __shared__ R tiles[4][kSymBlock * kSymRow];
+    __shared__ SrcRec<R> srcs[4][kSymBlock];
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int tid = blockIdx.x * 4 + wv;
+    if (tid >= ntasks) return;
+    sym_item<P, TPL>(tasks[tid], box, X, Q, Qh, slots, scale, tiles[wv], srcs[wv], lane);
+}
+
+// u and uhat of one box += its slot runs, in list order (deterministic).
+template <typename V>
+__global__ void __launch_bounds__(256) k_sym_reduce(const int32_t* __restrict__ boxes,
+                                                    const int32_t* __restrict__ ptr,
+                                                    const Contrib* __restrict__ list,
+                                                    const BoxRec* __restrict__ box,
+                                                    const double* __restrict__ slots, V* __restrict__ U,
+                                                    V* __restrict__ Uh) {
+    const int b = boxes[blockIdx.x];
+    const BoxRec rec = box[b];
+    const int x0 = ptr[blockIdx.x], x1 = ptr[blockIdx.x + 1];
+    for (int e = threadIdx.x; e < rec.n; e += blockDim.x) {
+        const bool sk = e < rec.k;
+        double su = static_cast<double>(U[rec.voff + e]);
+        double sh = sk ? static_cast<double>(Uh[rec.hoff + e]) : 0.0;
+        for (int x = x0; x < x1; ++x) {
+            const Contrib ct = list[x];
+            if (e >= ct.e0 && e < ct.e1) {
+                const double v = slots[ct.slot + (e - ct.e0)];
+                if (ct.kind == 0) su += v;
+                else sh += v;
+            }
+        }
+        U[rec.voff + e] = static_cast<V>(su);
+        if (sk) Uh[rec.hoff + e] = static_cast<V>(sh);
     }
 }
 

@@ -171,6 +171,91 @@ Layout make_layout(const Plan& p, bool keep_transparent, int tile) {
     return L;
 }
 
+// Symmetric near field.  An ifo segment (i <- j) and its mirror (j <- i) use the
+// same kernel block, and so do two top-level boxes' direct segments, so every
+// such unordered pair {i, j} (i != j; ifo pairs of two uncompressed boxes are
+// already absent) becomes work items that evaluate G(B_i, B_j) once: lanes run
+// over targets of the larger box, groups of at most `group` targets per item.
+// Each item writes private slots; a reduction adds them to the boxes' u and
+// uhat in a fixed order, so results stay deterministic.
+void make_symmetric(Layout& L, int group) {
+    L.sym = true;
+    const int nb = L.n_boxes;
+    std::vector<std::vector<int32_t>> rem(nb);
+    std::vector<std::vector<int32_t>> remm(nb);
+    std::vector<std::vector<Contrib>> contrib(nb);
+    std::vector<std::pair<int64_t, SymTask>> items;
+    int64_t slot = 0, pairs = 0, pairs_skel = 0;
+    for (int b = 0; b < nb; ++b) {
+        for (int x = L.seg_ptr[b]; x < L.seg_ptr[b + 1]; ++x) {
+            const int c = L.seg_src[x];
+            const int mode = L.seg_mode[x];
+            const int mt = mode & SEG_MODE_MASK;
+            if ((mt != SEG_IFO && mt != SEG_DIRECT) || c == b) {
+                rem[b].push_back(c);
+                remm[b].push_back(mode);
+                continue;
+            }
+            if (c < b) continue;   // the pair was handled from the smaller id
+            // i = the box with more entries (lanes), j = the other
+            int bi = b, bj = c;
+            if (L.nb[c] > L.nb[b]) { bi = c; bj = b; }
+            const int ni = L.nb[bi], nj = L.nb[bj], ki = L.kb[bi], kj = L.kb[bj];
+            if (nj == 0) continue;   // an empty box adds nothing either way
+            for (int t0 = 0; t0 < ni; t0 += group) {
+                const int t1 = std::min(ni, t0 + group);
+                SymTask st{bi, bj, t0, t1, slot, 0};
+                const int nh = std::max(0, std::min(ki, t1) - t0);
+                contrib[bi].push_back(Contrib{slot, t0, t1, 0, 0});
+                if (nh > 0) contrib[bi].push_back(Contrib{slot + (t1 - t0), t0, t0 + nh, 1, 0});
+                slot += (t1 - t0) + nh;
+                st.rev = slot;
+                contrib[bj].push_back(Contrib{slot, 0, nj, 0, 0});
+                if (t0 < ki && kj > 0) contrib[bj].push_back(Contrib{slot + nj, 0, kj, 1, 0});
+                slot += nj + (t0 < ki ? kj : 0);
+                items.push_back({int64_t(t1 - t0) * nj, st});
+                pairs += int64_t(t1 - t0) * nj;
+                pairs_skel += int64_t(nh) * kj;
+            }
+        }
+    }
+    L.slot_size = slot;
+    L.pairs_sym = pairs;
+    L.pairs_sym_skel = pairs_skel;
+    std::stable_sort(items.begin(), items.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
+    L.sym_tasks.clear();
+    for (auto& it : items) L.sym_tasks.push_back(it.second);
+    L.seg_ptr_ns.assign(nb + 1, 0);
+    L.seg_src_ns.clear();
+    L.seg_mode_ns.clear();
+    L.red_boxes.clear();
+    L.red_ptr.assign(1, 0);
+    L.red_list.clear();
+    // every slot a kernel or the reduction touches lies inside the slot array
+    for (const SymTask& st : L.sym_tasks) {
+        const int ni = L.nb[st.bi], nj = L.nb[st.bj], ki = L.kb[st.bi], kj = L.kb[st.bj];
+        const int nh = std::max(0, std::min(ki, st.t1) - st.t0);
+        if (st.bi == st.bj || st.t0 < 0 || st.t1 > ni || st.t0 >= st.t1 || nj <= 0 || st.fwd < 0 ||
+            st.fwd + (st.t1 - st.t0) + nh != st.rev || st.rev + nj + (st.t0 < ki ? kj : 0) > slot)
+            throw std::logic_error("symmetric work item out of range");
+    }
+    for (int b = 0; b < nb; ++b)
+        for (const Contrib& c : contrib[b])
+            if (c.slot < 0 || c.e0 < 0 || c.e0 > c.e1 || c.e1 > (c.kind ? L.kb[b] : L.nb[b]) ||
+                c.slot + (c.e1 - c.e0) > slot)
+                throw std::logic_error("symmetric slot run out of range");
+    for (int b = 0; b < nb; ++b) {
+        L.seg_src_ns.insert(L.seg_src_ns.end(), rem[b].begin(), rem[b].end());
+        L.seg_mode_ns.insert(L.seg_mode_ns.end(), remm[b].begin(), remm[b].end());
+        L.seg_ptr_ns[b + 1] = static_cast<int32_t>(L.seg_src_ns.size());
+        if (!contrib[b].empty()) {
+            L.red_boxes.push_back(b);
+            L.red_list.insert(L.red_list.end(), contrib[b].begin(), contrib[b].end());
+            L.red_ptr.push_back(static_cast<int32_t>(L.red_list.size()));
+        }
+    }
+}
+
 Layout merge_layouts(const std::vector<const Layout*>& ls, std::vector<int64_t>& entry_base) {
     Layout M;
     const Layout& L0 = *ls[0];
@@ -261,12 +346,14 @@ Layout merge_layouts(const std::vector<const Layout*>& ls, std::vector<int64_t>&
     return M;
 }
 
-std::vector<Task> make_tasks(const Layout& L, int tile) {
+std::vector<Task> make_tasks(const Layout& L, int tile, bool ns) {
+    const std::vector<int32_t>& sp = ns ? L.seg_ptr_ns : L.seg_ptr;
+    const std::vector<int32_t>& ss = ns ? L.seg_src_ns : L.seg_src;
     std::vector<std::pair<int64_t, Task>> work;
     for (int b = 0; b < L.n_boxes; ++b) {
         if (L.level[b] < L.top || L.nb[b] == 0) continue;
         int64_t src = 0;
-        for (int x = L.seg_ptr[b]; x < L.seg_ptr[b + 1]; ++x) src += L.nb[L.seg_src[x]];
+        for (int x = sp[b]; x < sp[b + 1]; ++x) src += L.nb[ss[x]];
         for (int t0 = 0; t0 < L.nb[b]; t0 += tile) work.push_back({int64_t(tile) * src + 64, Task{b, t0}});
     }
     std::stable_sort(work.begin(), work.end(), [](const auto& a, const auto& b) { return a.first > b.first; });

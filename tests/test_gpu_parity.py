@@ -45,13 +45,18 @@ CASES = {
     "lap3d_ellipsoid_60k": (lambda: workloads.ellipsoid_points(60000, 502), "laplace", 0.0, 1e-6, 64),
     "helm3d_uniform_32k": (lambda: workloads.uniform_points(32768, 3, 503), "helmholtz", 20.0, 1e-6, 64),
 }
+# layout-only cases (parity with O2, no accuracy bar against O1)
+EXTRA_CASES = {
+    # tight tolerance: tree boxes of up to ~2200 entries (several symmetric items per pair)
+    "lap3d_bigbox_40k": (lambda: workloads.uniform_points(40000, 3, 504), "laplace", 0.0, 1e-10, 256),
+}
 _built = {}
 
 
 def _op(name, **kw):
     key = (name, tuple(sorted(kw.items())))
     if key not in _built:
-        mk, kind, kappa, tol, b = CASES[name]
+        mk, kind, kappa, tol, b = {**CASES, **EXTRA_CASES}[name]
         x = mk()
         op = sk.build(x, kind, tol=tol, leaf_size=b, kappa=kappa, **kw)
         _built[key] = (x, op, op.export())
@@ -59,7 +64,7 @@ def _op(name, **kw):
 
 
 def _charges(name, n, seed):
-    kind = CASES[name][1]
+    kind = {**CASES, **EXTRA_CASES}[name][1]
     return workloads.charges(n, 1, seed, complex_=(kind == "helmholtz"))
 
 
@@ -264,3 +269,32 @@ def test_batch_graph_capture_replays():
             assert torch.equal(o, r)
         batch.apply(qs, adjoint=True)      # eager work between replays
         torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("name", ["lap2d_16k", "lap3d_uniform_64k", "lap3d_ellipsoid_60k", "lap3d_bigbox_40k"])
+def test_symmetric_pairing_matches_unpaired_and_o2(name):
+    """One kernel evaluation per colleague pair (both orders) against the unpaired
+    sweep and O2, for every targets-per-lane variant."""
+    _say("case", name)
+    x, op, P = _op(name)
+    _, op_ns, _ = _op(name, symmetric=False)
+    assert op.stats()["n_sym_tasks"] > 0
+    assert op_ns.stats()["n_sym_tasks"] == 0
+    q = _charges(name, x.shape[0], 11)
+    u2 = oracle.apply(P, q)
+    un = host(op_ns.apply(dev(q, torch.float64)))
+    for t in (1, 2, 4):
+        op.set_targets_per_lane(t)
+        u = host(op.apply(dev(q, torch.float64)))
+        e2, en = relerr(u, u2), relerr(u, un)
+        _say(name, "tpl", t, "paired vs O2", e2, "vs unpaired", en)
+        assert e2 <= 1e-12 and en <= 1e-12
+        w = host(op.apply_adjoint(dev(q, torch.float64)))
+        assert relerr(w, oracle.apply(P, q, adjoint=True)) <= 1e-12
+    op.set_targets_per_lane(2)
+    # float32: paired and unpaired agree to the float32 evaluation error
+    us = host(op.apply(dev(q, torch.float32))).astype(np.float64)
+    uns = host(op_ns.apply(dev(q, torch.float32))).astype(np.float64)
+    es, ens = relerr(us, u2), relerr(uns, u2)
+    _say(name, "f32 paired vs O2", es, "unpaired vs O2", ens)
+    assert es <= max(2 * ens, 1e-6)
