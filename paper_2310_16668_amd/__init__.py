@@ -320,7 +320,34 @@ def _make_autograd():
     return FmmApply
 
 
+def _make_batch_autograd():
+    torch = _torch()
+
+    class BatchFmmApply(torch.autograd.Function):
+        """[u_g] = [Atilde_g q_g] in one batched sweep; backward is one batched adjoint sweep."""
+
+        @staticmethod
+        def forward(ctx, batch, *qs):
+            ctx.batch = batch
+            return tuple(batch.apply(list(qs)))
+
+        @staticmethod
+        def backward(ctx, *grads):
+            return (None, *ctx.batch.apply([g.contiguous() for g in grads], adjoint=True))
+
+    return BatchFmmApply
+
+
 _FmmApply = None
+_BatchFmmApply = None
+
+
+def batch_fmm_apply(batch: "Batch", qs):
+    """Differentiable batched apply: one sweep forward, one adjoint sweep backward."""
+    global _BatchFmmApply
+    if _BatchFmmApply is None:
+        _BatchFmmApply = _make_batch_autograd()
+    return list(_BatchFmmApply.apply(batch, *qs))
 
 
 def fmm_apply(op: Operator, q):

@@ -31,20 +31,20 @@ struct Task {
 };
 
 // One symmetric colleague-pair work item: the kernel block G(B_i, B_j) is
-// evaluated once and serves u_i (forward) and u_j (reverse).
+// evaluated once and serves u_i (forward) and u_j (reverse).  Slot offsets:
+// fwd_u / fwd_h are the slots of target t0 in box i's u / uhat row (target t at
+// offset t - t0); rev_u / rev_h the first slot of box j's u / uhat row.
 struct SymTask {
     int32_t bi, bj;   // target-side box (lanes) and source-side box (wave-uniform)
     int32_t t0, t1;   // target entries [t0, t1) of bi
-    int64_t fwd;      // slots: u of targets [t0, t1), then uhat of targets [t0, min(k_i, t1))
-    int64_t rev;      // slots: u of all n_j sources, then (when t0 < k_i) uhat of the k_j skeleton sources
+    int64_t fwd_u, fwd_h, rev_u, rev_h;
 };
 
-// A run of slots added into one box's u (kind 0) or uhat (kind 1) entries [e0, e1).
-struct Contrib {
-    int64_t slot;
-    int32_t e0, e1;
-    int32_t kind;
-    int32_t pad;
+// The slot rows of one box: ru rows of n entries from base_u (added to u) and
+// rh rows of k entries from base_h (added to uhat).
+struct SymRows {
+    int32_t box, ru, rh, pad;
+    int64_t base_u, base_h;
 };
 
 // Host copy of everything the GPU sweep reads.  Built without touching a GPU.
@@ -78,8 +78,7 @@ struct Layout {
     bool sym = false;
     std::vector<int32_t> seg_ptr_ns, seg_src_ns, seg_mode_ns;
     std::vector<SymTask> sym_tasks;
-    std::vector<int32_t> red_boxes, red_ptr;     // boxes receiving slots, CSR into red_list
-    std::vector<Contrib> red_list;
+    std::vector<SymRows> sym_rows;               // boxes receiving slot rows
     int64_t slot_size = 0;
     int64_t pairs_sym = 0, pairs_sym_skel = 0;
 };

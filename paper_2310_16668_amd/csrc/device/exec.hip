@@ -110,7 +110,7 @@ struct DeviceOp {
     int ntasks[3] = {0, 0, 0};
     // symmetric near field (one RHS): segment lists without the paired ifo
     // terms, their work lists, the pair items, the slot reduction lists
-    DevMem seg_ptr_ns, segs_ns, tasks_ns[3], symtasks, red_boxes, red_ptr, red_list, slots;
+    DevMem seg_ptr_ns, segs_ns, tasks_ns[3], symtasks, symrows, slots;
     int ntasks_ns[3] = {0, 0, 0};
     int nsym = 0, nred = 0;
     // workspace
@@ -220,10 +220,8 @@ static void upload(DeviceOp* d, int dtype) {
                 d->tasks_ns[tpl_slot(t)].upload(tl);
                 d->ntasks_ns[tpl_slot(t)] = static_cast<int>(tl.size());
             }
-            d->red_boxes.upload(L.red_boxes);
-            d->red_ptr.upload(L.red_ptr);
-            d->red_list.upload(L.red_list);
-            d->nred = static_cast<int>(L.red_boxes.size());
+            d->symrows.upload(L.sym_rows);
+            d->nred = static_cast<int>(L.sym_rows.size());
             d->slots.alloc(static_cast<size_t>(L.slot_size) * sizeof(double));
         }
         std::vector<kern::BoxRec> br(L.n_boxes);
@@ -325,9 +323,9 @@ void launch_near_t(const DeviceOp* d, hipStream_t s, void* Q, void* Qh, void* U,
     if (pm) pm->mark(4);
     if constexpr (P::kind == 0) {
         if (sym && d->nred > 0) {
-            hipLaunchKernelGGL((kern::k_sym_reduce<V>), dim3(d->nred), dim3(256), 0, s, d->red_boxes.as<int32_t>(),
-                               d->red_ptr.as<int32_t>(), d->red_list.as<Contrib>(), d->boxrec.as<kern::BoxRec>(),
-                               d->slots.as<double>(), static_cast<V*>(U), static_cast<V*>(Uh));
+            hipLaunchKernelGGL((kern::k_sym_reduce<V>), dim3(d->nred), dim3(256), 0, s, d->symrows.as<SymRows>(),
+                               d->boxrec.as<kern::BoxRec>(), d->slots.as<double>(), static_cast<V*>(U),
+                               static_cast<V*>(Uh));
             SKF_HIP(hipGetLastError());
         }
     }

@@ -541,80 +541,116 @@ __device__ __forceinline__ void stage_load(const BlockPlan& bp, int b, const Rec
     }
 }
 
+// Item context shared by its passes.
+struct SymCtx {
+    BoxRec bi, bj;
+    int t0, t1;
+    double* fwd_u;
+    double* fwd_h;
+    double* rev_u;
+    double* rev_h;
+    double sc;
+};
+
+// One pass: targets tp .. tp + 64 TPL - 1 of box i (those below t1) against all
+// sources of box j.
+template <class P, int TPL>
+__device__ __forceinline__ void sym_pass(const SymCtx& cx, int tp, const Rec4<double>* __restrict__ X,
+                                         const typename P::Vt* __restrict__ Q,
+                                         const typename P::Vt* __restrict__ Qh,
+                                         const Rec4<double>* __restrict__ Xs, const typename P::Vt* __restrict__ Qs,
+                                         const typename P::Vt* __restrict__ Qhs, typename P::Rt* tile,
+                                         SrcRec<typename P::Rt>* src, int lane) {
+    using R = typename P::Rt;
+    using A = typename P::At;
+    const BoxRec& bi = cx.bi;
+    const BoxRec& bj = cx.bj;
+    const bool first = tp == cx.t0;
+    // skeleton targets in this pass and a skeleton in box j: the uhat terms run
+    const bool hp = tp < bi.k && bj.k > 0;
+    BlockPlan bp;
+    bp.kH = hp ? bj.k : 0;
+    bp.nbH = (bp.kH + kSymBlock - 1) / kSymBlock;
+    bp.n = bj.n;
+    bp.nb = bp.nbH + (bj.n - bp.kH + kSymBlock - 1) / kSymBlock;
+    double xt[TPL], yt[TPL], zt[TPL];
+    R wi[TPL], whi[TPL];
+    A acc[TPL], acch[TPL];
+#pragma unroll
+    for (int p = 0; p < TPL; ++p) {
+        const int t = tp + lane + 64 * p;
+        const bool ok = t < cx.t1;
+        const int tc = ok ? t : cx.t1 - 1;
+        const Rec4<double> x = X[bi.voff + tc];
+        xt[p] = x.x; yt[p] = x.y; zt[p] = x.z;
+        wi[p] = ok ? static_cast<R>(Q[bi.voff + tc]) : R(0);
+        whi[p] = (ok && t < bi.k) ? static_cast<R>(Qh[bi.hoff + t]) : R(0);
+        acc[p] = A(0);
+        acch[p] = A(0);
+    }
+    // the next block's sources are fetched while the current one is evaluated
+    SrcRec<R> staged{};
+    stage_load<P>(bp, 0, Xs, Qs, Qhs, lane, staged);
+    for (int b = 0; b < bp.nb; ++b) {
+        int s0, cnt;
+        bp.range(b, s0, cnt);
+        wave_sync();
+        if (lane < kSymBlock) src[lane] = staged;
+        wave_sync();
+        if (b + 1 < bp.nb) stage_load<P>(bp, b + 1, Xs, Qs, Qhs, lane, staged);
+        if (b < bp.nbH)
+            sym_block<P, TPL, true>(src, s0, cnt, xt, yt, zt, wi, whi, acc, acch, tile, lane, cx.rev_u, cx.rev_h,
+                                    first, cx.sc);
+        else
+            sym_block<P, TPL, false>(src, s0, cnt, xt, yt, zt, wi, whi, acc, acch, tile, lane, cx.rev_u, cx.rev_h,
+                                     first, cx.sc);
+    }
+#pragma unroll
+    for (int p = 0; p < TPL; ++p) {
+        const int t = tp + lane + 64 * p;
+        if (t < cx.t1) {
+            cx.fwd_u[t - cx.t0] = cx.sc * static_cast<double>(acc[p]);
+            if (t < bi.k) cx.fwd_h[t - cx.t0] = -cx.sc * static_cast<double>(acch[p]);
+        }
+    }
+}
+
+// A pair item: passes of 64 TPL targets; a last pass of at most 64 targets runs
+// with one target per lane, so a ragged end wastes at most one wave's lanes.
 template <class P, int TPL>
 __device__ __forceinline__ void sym_item(const SymTask it, const BoxRec* __restrict__ box,
                                          const Rec4<double>* __restrict__ X, const typename P::Vt* __restrict__ Q,
                                          const typename P::Vt* __restrict__ Qh, double* __restrict__ slots,
                                          double scale, typename P::Rt* tile, SrcRec<typename P::Rt>* src,
                                          int lane) {
-    using R = typename P::Rt;
-    using A = typename P::At;
     using V = typename P::Vt;
-    const BoxRec bi = box[it.bi];
-    const BoxRec bj = box[it.bj];
-    const Rec4<double>* Xs = X + bj.voff;
-    const V* Qs = Q + bj.voff;
-    const V* Qhs = Qh + bj.hoff;
-    double* fwd_u = slots + it.fwd;
-    double* fwd_h = fwd_u + (it.t1 - it.t0);
-    double* rev_u = slots + it.rev;
-    double* rev_h = rev_u + bj.n;
-    const double sc = scale * P::gscale;
-
-    for (int tp = it.t0; tp < it.t1; tp += 64 * TPL) {
-        const bool first = tp == it.t0;
-        // skeleton targets in this pass and a skeleton in box j: the uhat terms run
-        const bool hp = tp < bi.k && bj.k > 0;
-        BlockPlan bp;
-        bp.kH = hp ? bj.k : 0;
-        bp.nbH = (bp.kH + kSymBlock - 1) / kSymBlock;
-        bp.n = bj.n;
-        bp.nb = bp.nbH + (bj.n - bp.kH + kSymBlock - 1) / kSymBlock;
-        double xt[TPL], yt[TPL], zt[TPL];
-        R wi[TPL], whi[TPL];
-        A acc[TPL], acch[TPL];
-#pragma unroll
-        for (int p = 0; p < TPL; ++p) {
-            const int t = tp + lane + 64 * p;
-            const bool ok = t < it.t1;
-            const int tc = ok ? t : it.t1 - 1;
-            const Rec4<double> x = X[bi.voff + tc];
-            xt[p] = x.x; yt[p] = x.y; zt[p] = x.z;
-            wi[p] = ok ? static_cast<R>(Q[bi.voff + tc]) : R(0);
-            whi[p] = (ok && t < bi.k) ? static_cast<R>(Qh[bi.hoff + t]) : R(0);
-            acc[p] = A(0);
-            acch[p] = A(0);
-        }
-        // the next block's sources are fetched while the current one is evaluated
-        SrcRec<R> staged{};
-        stage_load<P>(bp, 0, Xs, Qs, Qhs, lane, staged);
-        for (int b = 0; b < bp.nb; ++b) {
-            int s0, cnt;
-            bp.range(b, s0, cnt);
-            wave_sync();
-            if (lane < kSymBlock) src[lane] = staged;
-            wave_sync();
-            if (b + 1 < bp.nb) stage_load<P>(bp, b + 1, Xs, Qs, Qhs, lane, staged);
-            if (b < bp.nbH)
-                sym_block<P, TPL, true>(src, s0, cnt, xt, yt, zt, wi, whi, acc, acch, tile, lane, rev_u, rev_h,
-                                        first, sc);
-            else
-                sym_block<P, TPL, false>(src, s0, cnt, xt, yt, zt, wi, whi, acc, acch, tile, lane, rev_u, rev_h,
-                                         first, sc);
-        }
-#pragma unroll
-        for (int p = 0; p < TPL; ++p) {
-            const int t = tp + lane + 64 * p;
-            if (t < it.t1) {
-                fwd_u[t - it.t0] = sc * static_cast<double>(acc[p]);
-                if (t < bi.k) fwd_h[t - it.t0] = -sc * static_cast<double>(acch[p]);
-            }
-        }
-    }
+    SymCtx cx;
+    cx.bi = box[it.bi];
+    cx.bj = box[it.bj];
+    cx.t0 = it.t0;
+    cx.t1 = it.t1;
+    // uhat rows exist only where an item touches them (offsets < 0 are never used)
+    cx.fwd_u = slots + it.fwd_u;
+    cx.fwd_h = slots + (it.fwd_h >= 0 ? it.fwd_h : 0);
+    cx.rev_u = slots + it.rev_u;
+    cx.rev_h = slots + (it.rev_h >= 0 ? it.rev_h : 0);
+    cx.sc = scale * P::gscale;
+    const Rec4<double>* Xs = X + cx.bj.voff;
+    const V* Qs = Q + cx.bj.voff;
+    const V* Qhs = Qh + cx.bj.hoff;
+    int tp = it.t0;
+    for (; it.t1 - tp > 64; tp += 64 * TPL)
+        sym_pass<P, TPL>(cx, tp, X, Q, Qh, Xs, Qs, Qhs, tile, src, lane);
+    if (tp < it.t1) sym_pass<P, 1>(cx, tp, X, Q, Qh, Xs, Qs, Qhs, tile, src, lane);
 }
 
+// Waves per SIMD the pair kernel is compiled for: the float32 evaluation with
+// up to two targets per lane fits four waves' registers.
 template <class P, int TPL>
-__global__ void __launch_bounds__(256) k_near_sym(const SymTask* __restrict__ tasks, int ntasks,
+constexpr int sym_waves() { return (sizeof(typename P::Rt) == 4 && TPL <= 2) ? 4 : 1; }
+
+template <class P, int TPL>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sym_waves<P, TPL>(), 8))) k_near_sym(const SymTask* __restrict__ tasks, int ntasks,
                                                   const BoxRec* __restrict__ box,
                                                   const Rec4<double>* __restrict__ X,
                                                   const typename P::Vt* __restrict__ Q,
@@ -630,31 +666,38 @@ __global__ void __launch_bounds__(256) k_near_sym(const SymTask* __restrict__ ta
     sym_item<P, TPL>(tasks[tid], box, X, Q, Qh, slots, scale, tiles[wv], srcs[wv], lane);
 }
 
-// u and uhat of one box += its slot runs, in list order (deterministic).
+// acc + p[0] + p[ld] + ... + p[(rows - 1) ld], added in row order; the loads of
+// four rows are issued together.
+__device__ __forceinline__ double add_rows(double acc, const double* __restrict__ p, int rows, int ld) {
+    int i = 0;
+    for (; i + 4 <= rows; i += 4) {
+        const double a0 = p[static_cast<int64_t>(i) * ld], a1 = p[static_cast<int64_t>(i + 1) * ld];
+        const double a2 = p[static_cast<int64_t>(i + 2) * ld], a3 = p[static_cast<int64_t>(i + 3) * ld];
+        acc += a0;
+        acc += a1;
+        acc += a2;
+        acc += a3;
+    }
+    for (; i < rows; ++i) acc += p[static_cast<int64_t>(i) * ld];
+    return acc;
+}
+
+// u and uhat of one box += its slot rows, in row order (deterministic).  A
+// block per receiving box; threads run over the box's entries, so every row is
+// read with coalesced loads.
 template <typename V>
-__global__ void __launch_bounds__(256) k_sym_reduce(const int32_t* __restrict__ boxes,
-                                                    const int32_t* __restrict__ ptr,
-                                                    const Contrib* __restrict__ list,
+__global__ void __launch_bounds__(256) k_sym_reduce(const SymRows* __restrict__ rows,
                                                     const BoxRec* __restrict__ box,
                                                     const double* __restrict__ slots, V* __restrict__ U,
                                                     V* __restrict__ Uh) {
-    const int b = boxes[blockIdx.x];
-    const BoxRec rec = box[b];
-    const int x0 = ptr[blockIdx.x], x1 = ptr[blockIdx.x + 1];
+    const SymRows r = rows[blockIdx.x];
+    const BoxRec rec = box[r.box];
     for (int e = threadIdx.x; e < rec.n; e += blockDim.x) {
-        const bool sk = e < rec.k;
-        double su = static_cast<double>(U[rec.voff + e]);
-        double sh = sk ? static_cast<double>(Uh[rec.hoff + e]) : 0.0;
-        for (int x = x0; x < x1; ++x) {
-            const Contrib ct = list[x];
-            if (e >= ct.e0 && e < ct.e1) {
-                const double v = slots[ct.slot + (e - ct.e0)];
-                if (ct.kind == 0) su += v;
-                else sh += v;
-            }
-        }
-        U[rec.voff + e] = static_cast<V>(su);
-        if (sk) Uh[rec.hoff + e] = static_cast<V>(sh);
+        U[rec.voff + e] = static_cast<V>(add_rows(static_cast<double>(U[rec.voff + e]), slots + r.base_u + e,
+                                                  r.ru, rec.n));
+        if (e < rec.k && r.rh > 0)
+            Uh[rec.hoff + e] = static_cast<V>(add_rows(static_cast<double>(Uh[rec.hoff + e]),
+                                                       slots + r.base_h + e, r.rh, rec.k));
     }
 }
 

@@ -175,17 +175,19 @@ Layout make_layout(const Plan& p, bool keep_transparent, int tile) {
 // same kernel block, and so do two top-level boxes' direct segments, so every
 // such unordered pair {i, j} (i != j; ifo pairs of two uncompressed boxes are
 // already absent) becomes work items that evaluate G(B_i, B_j) once: lanes run
-// over targets of the larger box, groups of at most `group` targets per item.
-// Each item writes private slots; a reduction adds them to the boxes' u and
-// uhat in a fixed order, so results stay deterministic.
+// over targets of box i, groups of at most `group` targets per item.
+//
+// Items write private slots laid out as dense rows per receiving box: for each
+// pair, one u row (and one uhat row) of box i that its groups fill by target
+// range, and per group one u row (and, when the group holds skeleton targets of
+// i, one uhat row) of box j.  The reduction adds a box's rows to its u and uhat
+// in row order, so results stay deterministic.
 void make_symmetric(Layout& L, int group) {
     L.sym = true;
     const int nb = L.n_boxes;
-    std::vector<std::vector<int32_t>> rem(nb);
-    std::vector<std::vector<int32_t>> remm(nb);
-    std::vector<std::vector<Contrib>> contrib(nb);
-    std::vector<std::pair<int64_t, SymTask>> items;
-    int64_t slot = 0, pairs = 0, pairs_skel = 0;
+    struct Pair { int32_t bi, bj; };
+    std::vector<Pair> pairs_list;
+    std::vector<std::vector<int32_t>> rem(nb), remm(nb);
     for (int b = 0; b < nb; ++b) {
         for (int x = L.seg_ptr[b]; x < L.seg_ptr[b + 1]; ++x) {
             const int c = L.seg_src[x];
@@ -197,62 +199,89 @@ void make_symmetric(Layout& L, int group) {
                 continue;
             }
             if (c < b) continue;   // the pair was handled from the smaller id
-            // i = the box with more entries (lanes), j = the other
+            // i = the box on the lanes: the side whose targets fill the passes
+            // (128 lanes, a last pass of 64) with fewer idle lanes per source
+            // pair; on a tie the box with more entries
+            auto lanes = [](int64_t m) {
+                const int64_t full = m / 128, r = m % 128;
+                return 128 * full + (r == 0 ? 0 : (r <= 64 ? 64 : 128));
+            };
+            const int64_t cost_b = lanes(L.nb[b]) * L.nb[c], cost_c = lanes(L.nb[c]) * L.nb[b];
             int bi = b, bj = c;
-            if (L.nb[c] > L.nb[b]) { bi = c; bj = b; }
-            const int ni = L.nb[bi], nj = L.nb[bj], ki = L.kb[bi], kj = L.kb[bj];
-            if (nj == 0) continue;   // an empty box adds nothing either way
-            for (int t0 = 0; t0 < ni; t0 += group) {
-                const int t1 = std::min(ni, t0 + group);
-                SymTask st{bi, bj, t0, t1, slot, 0};
-                const int nh = std::max(0, std::min(ki, t1) - t0);
-                contrib[bi].push_back(Contrib{slot, t0, t1, 0, 0});
-                if (nh > 0) contrib[bi].push_back(Contrib{slot + (t1 - t0), t0, t0 + nh, 1, 0});
-                slot += (t1 - t0) + nh;
-                st.rev = slot;
-                contrib[bj].push_back(Contrib{slot, 0, nj, 0, 0});
-                if (t0 < ki && kj > 0) contrib[bj].push_back(Contrib{slot + nj, 0, kj, 1, 0});
-                slot += nj + (t0 < ki ? kj : 0);
-                items.push_back({int64_t(t1 - t0) * nj, st});
-                pairs += int64_t(t1 - t0) * nj;
-                pairs_skel += int64_t(nh) * kj;
-            }
+            if (cost_c < cost_b || (cost_c == cost_b && L.nb[c] > L.nb[b])) { bi = c; bj = b; }
+            if (L.nb[bi] == 0 || L.nb[bj] == 0) continue;   // an empty box adds nothing either way
+            pairs_list.push_back(Pair{bi, bj});
         }
     }
+    // rows per receiving box
+    std::vector<int32_t> ru(nb, 0), rh(nb, 0);
+    for (const Pair& pr : pairs_list) {
+        const int ni = L.nb[pr.bi], ki = L.kb[pr.bi], kj = L.kb[pr.bj];
+        ru[pr.bi] += 1;
+        if (ki > 0) rh[pr.bi] += 1;
+        for (int t0 = 0; t0 < ni; t0 += group) {
+            ru[pr.bj] += 1;
+            if (t0 < ki && kj > 0) rh[pr.bj] += 1;
+        }
+    }
+    std::vector<int64_t> base_u(nb, 0), base_h(nb, 0);
+    int64_t slot = 0;
+    L.sym_rows.clear();
+    for (int b = 0; b < nb; ++b) {
+        base_u[b] = slot;
+        slot += int64_t(ru[b]) * L.nb[b];
+        base_h[b] = slot;
+        slot += int64_t(rh[b]) * L.kb[b];
+        if (ru[b] > 0 || rh[b] > 0) L.sym_rows.push_back(SymRows{b, ru[b], rh[b], 0, base_u[b], base_h[b]});
+    }
     L.slot_size = slot;
-    L.pairs_sym = pairs;
-    L.pairs_sym_skel = pairs_skel;
+    // items, rows assigned in pair order
+    std::vector<int32_t> nu(nb, 0), nh(nb, 0);
+    std::vector<std::pair<int64_t, SymTask>> items;
+    int64_t npairs = 0, nskel = 0;
+    for (const Pair& pr : pairs_list) {
+        const int bi = pr.bi, bj = pr.bj;
+        const int ni = L.nb[bi], nj = L.nb[bj], ki = L.kb[bi], kj = L.kb[bj];
+        const int64_t row_u = base_u[bi] + int64_t(nu[bi]++) * ni;
+        const int64_t row_h = ki > 0 ? base_h[bi] + int64_t(nh[bi]++) * ki : -1;
+        for (int t0 = 0; t0 < ni; t0 += group) {
+            const int t1 = std::min(ni, t0 + group);
+            SymTask st{bi, bj, t0, t1, row_u + t0, -1, base_u[bj] + int64_t(nu[bj]++) * nj, -1};
+            if (t0 < ki) st.fwd_h = row_h + t0;
+            if (t0 < ki && kj > 0) st.rev_h = base_h[bj] + int64_t(nh[bj]++) * kj;
+            items.push_back({int64_t(t1 - t0) * nj, st});
+            npairs += int64_t(t1 - t0) * nj;
+            nskel += int64_t(std::max(0, std::min(ki, t1) - t0)) * kj;
+        }
+    }
+    L.pairs_sym = npairs;
+    L.pairs_sym_skel = nskel;
     std::stable_sort(items.begin(), items.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
     L.sym_tasks.clear();
     for (auto& it : items) L.sym_tasks.push_back(it.second);
+    // every slot a kernel or the reduction touches lies inside the slot array,
+    // and every row is filled exactly once per sweep
+    for (int b = 0; b < nb; ++b)
+        if (nu[b] != ru[b] || nh[b] != rh[b]) throw std::logic_error("symmetric row count mismatch");
+    for (const SymTask& st : L.sym_tasks) {
+        const int ni = L.nb[st.bi], nj = L.nb[st.bj], ki = L.kb[st.bi], kj = L.kb[st.bj];
+        const bool hrow = st.t0 < ki, hrev = st.t0 < ki && kj > 0;
+        if (st.bi == st.bj || st.t0 < 0 || st.t1 > ni || st.t0 >= st.t1 || nj <= 0 ||
+            st.fwd_u < base_u[st.bi] || st.fwd_u + (st.t1 - st.t0) > base_u[st.bi] + int64_t(ru[st.bi]) * ni ||
+            (hrow && (st.fwd_h < base_h[st.bi] ||
+                      st.fwd_h + (std::min(ki, st.t1) - st.t0) > base_h[st.bi] + int64_t(rh[st.bi]) * ki)) ||
+            st.rev_u < base_u[st.bj] || st.rev_u + nj > base_u[st.bj] + int64_t(ru[st.bj]) * nj ||
+            (hrev && (st.rev_h < base_h[st.bj] || st.rev_h + kj > base_h[st.bj] + int64_t(rh[st.bj]) * kj)) ||
+            st.rev_u + nj > slot || (hrev && st.rev_h + kj > slot))
+            throw std::logic_error("symmetric work item out of range");
+    }
     L.seg_ptr_ns.assign(nb + 1, 0);
     L.seg_src_ns.clear();
     L.seg_mode_ns.clear();
-    L.red_boxes.clear();
-    L.red_ptr.assign(1, 0);
-    L.red_list.clear();
-    // every slot a kernel or the reduction touches lies inside the slot array
-    for (const SymTask& st : L.sym_tasks) {
-        const int ni = L.nb[st.bi], nj = L.nb[st.bj], ki = L.kb[st.bi], kj = L.kb[st.bj];
-        const int nh = std::max(0, std::min(ki, st.t1) - st.t0);
-        if (st.bi == st.bj || st.t0 < 0 || st.t1 > ni || st.t0 >= st.t1 || nj <= 0 || st.fwd < 0 ||
-            st.fwd + (st.t1 - st.t0) + nh != st.rev || st.rev + nj + (st.t0 < ki ? kj : 0) > slot)
-            throw std::logic_error("symmetric work item out of range");
-    }
-    for (int b = 0; b < nb; ++b)
-        for (const Contrib& c : contrib[b])
-            if (c.slot < 0 || c.e0 < 0 || c.e0 > c.e1 || c.e1 > (c.kind ? L.kb[b] : L.nb[b]) ||
-                c.slot + (c.e1 - c.e0) > slot)
-                throw std::logic_error("symmetric slot run out of range");
     for (int b = 0; b < nb; ++b) {
         L.seg_src_ns.insert(L.seg_src_ns.end(), rem[b].begin(), rem[b].end());
         L.seg_mode_ns.insert(L.seg_mode_ns.end(), remm[b].begin(), remm[b].end());
         L.seg_ptr_ns[b + 1] = static_cast<int32_t>(L.seg_src_ns.size());
-        if (!contrib[b].empty()) {
-            L.red_boxes.push_back(b);
-            L.red_list.insert(L.red_list.end(), contrib[b].begin(), contrib[b].end());
-            L.red_ptr.push_back(static_cast<int32_t>(L.red_list.size()));
-        }
     }
 }
 

@@ -8,6 +8,8 @@ Bars: float64 vs O2 <= 1e-12 at the sampled leaves; every path vs O1 <= 10 x
 the ID tolerance (the 1M cube's float32 path must also meet 1e-6, the accuracy
 its benchmark line is quoted at).
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -107,3 +109,79 @@ def test_helmholtz_1m_c64_f64_leaf():
     wa = op.apply_adjoint(qd).cpu().numpy()
     wb = np.conj(op.apply(torch.conj(qd).resolve_conj()).cpu().numpy())
     assert relerr(wa, wb) <= 1e-5
+
+
+def test_batched_eight_geometries_graph_and_gradient():
+    """Eight 3D Laplace geometries (65,536 .. 2,097,152 points, cube / ellipsoid),
+    64 right-hand sides in float32: one captured batched sweep forward, then the
+    autograd backward of L = sum(w * u) through one batched adjoint sweep.
+
+    Checks: graph replay equals the eager sweep bit for bit; the float32 gradient
+    against the dense A^T w (O1; Laplace A^T = A) at 512 targets per geometry
+    over all 64 columns (<= 10 x tol); and float64 central differences with
+    h = 1, exact for the linear L, against the float64 adjoint on the same plans
+    at 16 (index, column) pairs per geometry (<= 1e-10), with the float32
+    gradient's error against them stated."""
+    wls = workloads.batch_workloads()
+    xs, ops = [], []
+    for w in wls:
+        say("build", w.name)
+        x = w.points()
+        xs.append(x)
+        ops.append(sk.build(x, "laplace", tol=w.tol, leaf_size=w.leaf_size))
+    batch = sk.Batch(ops)
+    q_h = [w.charges() for w in wls]
+    w_h = [w.weights() for w in wls]
+    q = [torch.from_numpy(a).to("cuda:0", torch.float32) for a in q_h]
+    wt = [torch.from_numpy(a).to("cuda:0", torch.float32) for a in w_h]
+    # one captured forward sweep, replayed, against the eager sweep
+    batch.apply(q)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        ug = batch.apply(q)
+    graph.replay()
+    torch.cuda.synchronize()
+    ue = batch.apply(q)
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, b) for a, b in zip(ug, ue))
+    say("graph replay == eager")
+    # autograd backward
+    qg = [t.clone().requires_grad_(True) for t in q]
+    outs = sk.batch_fmm_apply(batch, qg)
+    loss = sum((o * ww).sum() for o, ww in zip(outs, wt))
+    loss.backward()
+    grads = [t.grad.double().cpu().numpy() for t in qg]
+    for g, (w, x) in enumerate(zip(wls, xs)):
+        tg = w.targets(512)
+        dense = oracle.direct(x, w_h[g], targets=tg)
+        e = relerr(grads[g][tg], dense)
+        say(w.name, "f32 gradient vs dense A^T w", e)
+        assert e <= 10 * w.tol
+    # float64 central differences on the same plans
+    rng = np.random.default_rng(4242)
+    picks = [(rng.choice(w.n, 16, replace=False), rng.choice(w.nrhs, 16, replace=False)) for w in wls]
+    cols = []
+    for g, w in enumerate(wls):
+        idx, col = picks[g]
+        c = np.empty((w.n, 32))
+        for m in range(16):
+            base = q_h[g][:, col[m]]
+            c[:, 2 * m] = base
+            c[:, 2 * m + 1] = base
+            c[idx[m], 2 * m] += 1.0
+            c[idx[m], 2 * m + 1] -= 1.0
+        cols.append(torch.from_numpy(c).to("cuda:0", torch.float64))
+    up = [u.cpu().numpy() for u in batch.apply(cols)]
+    g64 = [u.cpu().numpy() for u in batch.apply([torch.from_numpy(a).to("cuda:0", torch.float64) for a in w_h],
+                                               adjoint=True)]
+    for g, w in enumerate(wls):
+        idx, col = picks[g]
+        fd = np.array([(math.fsum(w_h[g][:, col[m]] * up[g][:, 2 * m])
+                        - math.fsum(w_h[g][:, col[m]] * up[g][:, 2 * m + 1])) / 2 for m in range(16)])
+        ref = g64[g][idx, col]
+        e64 = relerr(fd, ref)
+        e32 = relerr(grads[g][idx, col], fd)
+        say(w.name, "FD (f64) vs f64 adjoint", e64, "f32 gradient vs FD", e32)
+        assert e64 <= 1e-10
+        assert e32 <= 10 * w.tol
