@@ -10,7 +10,11 @@ sum on 2,048 random targets, the near-field kernel's arithmetic roofline (HIP
 events around that pass, on the apply's stream), the transfer passes' HBM
 rate, and the CPU oracle timed on a bounded sample of the same workload.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--dtype f32|f64]
+It also times the eight-geometry, 64-RHS float32 batch (one captured hipGraph
+holding a batched forward and a batched adjoint sweep) and reports it beside
+the float64 single-RHS rate of the 1M cube.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--only f32|f64]
 """
 from __future__ import annotations
 
@@ -42,8 +46,10 @@ FLOPS_PER_SYM_PAIR = 13
 FLOPS_PER_SYM_SKEL_PAIR = 4
 # HBM bytes per near-field launch from rocprofv3 FETCH_SIZE + WRITE_SIZE runs of this
 # workload (scaled by a plain 512 MiB copy: x2.000 fetch, x1.000 write), valid only for
-# the kernel source they were measured on (first 16 hex digits of its sha256).
-NEAR_TRAFFIC = {}
+# the kernel, targets-per-lane variant and kernel source they were measured on (first
+# 16 hex digits of the source's sha256).
+NEAR_TRAFFIC = {"f32": {"kernel": "k_near_sym", "targets_per_lane": 4, "kernels_sha256": "707a54e4768dfec5",
+                         "bytes": 1.5905e9 + 0.6966e9}}
 
 
 def log(*a):
@@ -62,6 +68,8 @@ def parse():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run one plain device-to-device copy of MIB MiB (counter calibration)")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the eight-geometry, 64-RHS float32 batched measurement")
     return ap.parse_args()
 
 
@@ -93,12 +101,16 @@ def pair_counts(P) -> np.ndarray:
     return cnt
 
 
-def cpu_baseline(P, q, budget_s: float, nrhs: int = 1):
-    """Time the oracle's apply on a bounded, random sample of target boxes and
-    scale the translation time to the whole workload; the upward and downward
-    passes run in full in both timings."""
+def cpu_baseline(P, q, v, budget_s: float, nrhs: int = 1):
+    """Time the oracle's float64 apply (O2) of the same skeleton operators on the
+    host cores: the full forward apply, then the full adjoint apply when both fit
+    the budget.  A forward apply longer than the budget is instead timed on a
+    random sample of target boxes (upward and downward passes in full) and
+    scaled by the pair counts, with the adjoint taken equal to it."""
     import oracle
 
+    n = P["points"].shape[0]
+    cores = oracle.num_threads()
     cnt = pair_counts(P)
     total = cnt.sum()
     rng = np.random.default_rng(77)
@@ -106,31 +118,84 @@ def cpu_baseline(P, q, budget_s: float, nrhs: int = 1):
     t0 = time.perf_counter()
     oracle.apply(P, q, box_mask=mask0)
     t_base = time.perf_counter() - t0
-    # calibrate: a small sample first, then one sized to the budget
     frac = 2e-3
     mask = (rng.random(P["n_boxes"]) < frac).astype(np.uint8)
     t0 = time.perf_counter()
     oracle.apply(P, q, box_mask=mask)
     t_cal = max(time.perf_counter() - t0 - t_base, 1e-3)
-    rate = cnt[mask == 1].sum() / t_cal if mask.any() else 1e9
-    frac = min(1.0, budget_s * rate / total)
+    est_full = t_base + t_cal * total / max(cnt[mask == 1].sum(), 1.0)
+    if est_full <= budget_s:
+        t0 = time.perf_counter()
+        oracle.apply(P, q)
+        t_f = time.perf_counter() - t0
+        if 2 * t_f <= 1.5 * budget_s:
+            t0 = time.perf_counter()
+            oracle.apply(P, v, adjoint=True)
+            t_a = time.perf_counter() - t0
+            return {"value": n * nrhs / (t_f + t_a), "unit": "points/s", "cores": cores, "kind": "oracle",
+                    "sample": (f"CPU float64 apply (oracle O2) of the same skeleton operators, whole workload: "
+                               f"forward {t_f:.1f}s + adjoint {t_a:.1f}s")}
+        return {"value": n * nrhs / (2 * t_f), "unit": "points/s", "cores": cores, "kind": "oracle",
+                "sample": (f"CPU float64 apply (oracle O2) of the same skeleton operators: full forward "
+                           f"{t_f:.1f}s, adjoint taken equal")}
+    frac = min(1.0, budget_s * (total / max(est_full - t_base, 1e-3)) / total)
     mask = (rng.random(P["n_boxes"]) < frac).astype(np.uint8)
     t0 = time.perf_counter()
     oracle.apply(P, q, box_mask=mask)
     t_s = time.perf_counter() - t0
     sampled = cnt[mask == 1].sum()
     t_full = t_base + (t_s - t_base) * total / max(sampled, 1.0)
-    n = P["points"].shape[0]
     return {
         "value": n * nrhs / (2.0 * t_full),
         "unit": "points/s",
-        "cores": oracle.num_threads(),
+        "cores": cores,
         "kind": "oracle",
         "sample": (f"CPU float64 apply (oracle O2) of the same skeleton operators; translations for "
                    f"{int(mask.sum())} of {P['n_boxes']} target boxes ({100 * sampled / total:.2f}% of "
                    f"{total:.3e} pair evaluations) in {t_s:.1f}s, upward/downward passes in full "
                    f"({t_base:.1f}s); forward+adjoint time extrapolated as 2 x {t_full:.1f}s"),
     }
+
+
+def batched_run(steps: int, warmup: int):
+    """Eight 3D Laplace geometries (65,536 .. 2,097,152 points, cube / ellipsoid,
+    tol 1e-6, leaf 128), 64 float32 right-hand sides each: one captured hipGraph
+    holds a batched forward sweep and a batched adjoint sweep; value = total
+    points x RHS per second of that step."""
+    import torch
+
+    import workloads
+    import paper_2310_16668_amd as sk
+
+    wls = workloads.batch_workloads()
+    t0 = time.perf_counter()
+    ops = [sk.build(w.points(), "laplace", tol=w.tol, leaf_size=w.leaf_size) for w in wls]
+    t_build = time.perf_counter() - t0
+    batch = sk.Batch(ops)
+    dev = torch.device("cuda:0")
+    q = [torch.from_numpy(w.charges()).to(dev, torch.float32) for w in wls]
+    v = [torch.from_numpy(w.weights()).to(dev, torch.float32) for w in wls]
+    batch.apply(q)
+    batch.apply(v, adjoint=True)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        batch.apply(q)
+        batch.apply(v, adjoint=True)
+    for _ in range(warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        graph.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    n_total = sum(w.n for w in wls)
+    return {"value": n_total * 64 / (ms * 1e-3), "unit": "points x RHS/s (fwd+adjoint)", "ms_per_step": ms,
+            "n_total": n_total, "sizes": [w.n for w in wls], "nrhs": 64, "dtype": "f32", "graph": True,
+            "build_s": t_build}
 
 
 def main():
@@ -234,7 +299,9 @@ def main():
     src = os.path.join(ROOT, "paper_2310_16668_amd", "csrc", "device", "kernels.hip")
     digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     tr = NEAR_TRAFFIC.get(chosen)
-    traffic = tr["bytes"] if tr and tr["kernels_sha256"] == digest and tr.get("kernel") == dom else None
+    tpl = tuned.get(chosen, {}).get("targets_per_lane")
+    traffic = (tr["bytes"] if tr and tr["kernels_sha256"] == digest and tr.get("kernel") == dom
+               and tr.get("targets_per_lane") == tpl else None)
     sT = 8 if chosen == "f64" else 4
     # upward and downward each read every T once, plus their vectors (n and k entries)
     t_bytes = st["m_proj_elems"] * sT
@@ -271,9 +338,19 @@ def main():
         "autotune": tuned,
         "build_s": t_build,
     }
+    if not args.no_batched and not args.profile_only:
+        log("[bench] eight-geometry batched run")
+        bt = batched_run(args.steps, args.warmup)
+        if "f64" in results:
+            # the float64 single-RHS apply (fwd + adjoint) of the 1M cube, for comparison
+            f64_rate = w.n / (results["f64"]["ms_per_step"] * 1e-3)
+            bt["f64_single_rhs_points_per_s"] = f64_rate
+            bt["ratio_to_f64_single_rhs"] = bt["value"] / f64_rate
+        out["batched"] = bt
+        log(f"[bench] batched: {bt}")
     if not args.no_cpu_baseline and not args.profile_only:
         log("[bench] timing the CPU oracle on a sample")
-        out["cpu_baseline"] = cpu_baseline(op.export(), q_h, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(op.export(), q_h, v_h, args.cpu_budget)
     print(json.dumps(out))
     return 0
 
