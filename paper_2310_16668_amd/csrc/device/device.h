@@ -66,7 +66,12 @@ struct Layout {
     std::vector<int32_t> pmap;      // skeleton entry -> entry in the parent's vector
     std::vector<int32_t> gather_e, gather_p;     // leaf entries and their user indices
     std::vector<int32_t> topleaf_e, topleaf_p;   // entries of top-level leaves
-    std::vector<double> T;          // interpolation matrices, column-major per box
+    std::vector<double> T;          // interpolation matrices, column-major per box (at toff)
+    // device copies of T (k x m per box) and of its transpose (m x k) have their
+    // columns padded to kTPad entries, so no 128-byte line is shared by two row
+    // groups of a transfer; tpad / ttpad are the padded per-box offsets
+    std::vector<int64_t> tpad, ttpad;
+    int64_t tpad_size = 0, ttpad_size = 0;
     // near field
     std::vector<int32_t> seg_ptr;   // per target box
     std::vector<int32_t> seg_src, seg_mode;
@@ -82,6 +87,11 @@ struct Layout {
     int64_t slot_size = 0;
     int64_t pairs_sym = 0, pairs_sym_skel = 0;
 };
+
+constexpr int kTPad = 32;
+inline int64_t pad_ld(int64_t x) { return (x + kTPad - 1) / kTPad * kTPad; }
+// Padded offsets of the device copies of T and T^T (tpad, ttpad).
+void pad_transfer_offsets(Layout& L);
 
 Layout make_layout(const Plan& p, bool keep_transparent, int tile);
 // Work list for another tile size, largest estimated cost first, over the full

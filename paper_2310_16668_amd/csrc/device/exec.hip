@@ -98,12 +98,12 @@ struct DeviceOp {
     int device = -1;
     bool uploaded = false;
     // static arrays
-    DevMem voff, hoff, toff, nb, kb, pmap, gather_e, gather_p;
-    DevMem X64, T64, T32, Tt64, Tt32;             // Tt: per-box transposes (multi-RHS downward)
+    DevMem voff, hoff, toff, ttoff, nb, kb, pmap, gather_e, gather_p;
+    DevMem X64, T64, T32, Tt64, Tt32;             // T and its per-box transposes, columns padded
     DevMem seg_ptr, segs, boxrec;
     // one-RHS transfer work: (box, first row) items per level, and waves per item
-    DevMem upwork, downwork;
-    std::vector<int64_t> up_ptr, down_ptr;
+    DevMem upwork[2], downwork[2];                // [0]: float64 T row groups, [1]: float32
+    std::vector<int64_t> up_ptr[2], down_ptr[2];
     std::vector<int> up_nw, down_nw;
     int tpl = kDefaultTPL;
     DevMem tasks[3];                              // work lists for 1, 2, 4 targets per lane
@@ -157,34 +157,62 @@ DeviceOp* device_create(const Plan& p, bool keep_transparent, bool f64_leaf, boo
 // Waves per item follow the level's mean column count.
 static void build_transfer_work(DeviceOp* d) {
     const Layout& L = d->L;
-    std::vector<int2> up, down;
-    d->up_ptr.assign(L.max_level + 2, 0);
-    d->down_ptr.assign(L.max_level + 2, 0);
     d->up_nw.assign(L.max_level + 1, 1);
     d->down_nw.assign(L.max_level + 1, 1);
-    for (int l = 0; l <= L.max_level; ++l) {
-        d->up_ptr[l] = static_cast<int64_t>(up.size());
-        d->down_ptr[l] = static_cast<int64_t>(down.size());
-        double cu = 0, cd = 0;
-        int nbk = 0;
-        for (int b = L.level_ptr[l]; b < L.level_ptr[l + 1]; ++b) {
-            const int k = L.kb[b], m = L.nb[b] - L.kb[b];
-            if (k <= 0) continue;
-            ++nbk;
-            cu += m;
-            cd += k;
-            for (int r = 0; r < k; r += 64) up.push_back(make_int2(b, r));
-            for (int r = 0; r < std::max(m, 1); r += 64) down.push_back(make_int2(b, r));
+    for (int g = 0; g < 2; ++g) {
+        // row groups: 64 rows of float64 T, 128 rows of float32 T (one 8-byte load per lane)
+        const int G = g == 0 ? kern::RowMap<double>::group : kern::RowMap<float>::group;
+        std::vector<int2> up, down;
+        d->up_ptr[g].assign(L.max_level + 2, 0);
+        d->down_ptr[g].assign(L.max_level + 2, 0);
+        for (int l = 0; l <= L.max_level; ++l) {
+            d->up_ptr[g][l] = static_cast<int64_t>(up.size());
+            d->down_ptr[g][l] = static_cast<int64_t>(down.size());
+            double cu = 0, cd = 0;
+            int nbk = 0;
+            for (int b = L.level_ptr[l]; b < L.level_ptr[l + 1]; ++b) {
+                const int k = L.kb[b], m = L.nb[b] - L.kb[b];
+                if (k <= 0) continue;
+                ++nbk;
+                cu += m;
+                cd += k;
+                for (int r = 0; r * G < k; ++r) up.push_back(make_int2(b, r));
+                for (int r = 0; r * G < std::max(m, 1); ++r) down.push_back(make_int2(b, r));
+            }
+            if (g == 0 && nbk > 0) {
+                d->up_nw[l] = std::min(16, std::max(1, static_cast<int>(cu / nbk / 32.0 + 0.5)));
+                d->down_nw[l] = std::min(16, std::max(1, static_cast<int>(cd / nbk / 32.0 + 0.5)));
+            }
         }
-        if (nbk > 0) {
-            d->up_nw[l] = std::min(16, std::max(1, static_cast<int>(cu / nbk / 32.0 + 0.5)));
-            d->down_nw[l] = std::min(16, std::max(1, static_cast<int>(cd / nbk / 32.0 + 0.5)));
+        d->up_ptr[g][L.max_level + 1] = static_cast<int64_t>(up.size());
+        d->down_ptr[g][L.max_level + 1] = static_cast<int64_t>(down.size());
+        d->upwork[g].upload(up);
+        d->downwork[g].upload(down);
+    }
+}
+
+// T (k x m per box) or its transpose (m x k) with columns padded to pad_ld rows,
+// in the precision of the vectors; padding entries are zero.
+template <typename TT>
+static std::vector<TT> padded_t(const Layout& L, bool transpose) {
+    std::vector<TT> out(static_cast<size_t>(transpose ? L.ttpad_size : L.tpad_size), TT(0));
+    for (int b = 0; b < L.n_boxes; ++b) {
+        const int64_t k = L.kb[b], m = L.nb[b] - L.kb[b];
+        if (k <= 0 || m <= 0) continue;
+        const double* src = L.T.data() + L.toff[b];
+        if (!transpose) {
+            const int64_t ld = pad_ld(k);
+            TT* dst = out.data() + L.tpad[b];
+            for (int64_t j = 0; j < m; ++j)
+                for (int64_t i = 0; i < k; ++i) dst[i + j * ld] = static_cast<TT>(src[i + j * k]);
+        } else {
+            const int64_t ld = pad_ld(m);
+            TT* dst = out.data() + L.ttpad[b];
+            for (int64_t j = 0; j < m; ++j)
+                for (int64_t i = 0; i < k; ++i) dst[j + i * ld] = static_cast<TT>(src[i + j * k]);
         }
     }
-    d->up_ptr[L.max_level + 1] = static_cast<int64_t>(up.size());
-    d->down_ptr[L.max_level + 1] = static_cast<int64_t>(down.size());
-    d->upwork.upload(up);
-    d->downwork.upload(down);
+    return out;
 }
 
 static void upload(DeviceOp* d, int dtype) {
@@ -193,7 +221,8 @@ static void upload(DeviceOp* d, int dtype) {
         SKF_HIP(hipGetDevice(&d->device));
         d->voff.upload(L.voff);
         d->hoff.upload(L.hoff);
-        d->toff.upload(L.toff);
+        d->toff.upload(L.tpad);
+        d->ttoff.upload(L.ttpad);
         d->nb.upload(L.nb);
         d->kb.upload(L.kb);
         d->pmap.upload(L.pmap);
@@ -233,24 +262,14 @@ static void upload(DeviceOp* d, int dtype) {
         d->uploaded = true;
     }
     const bool single = dtype_is_single(dtype);
-    if (!single && !d->T64.p) d->T64.upload(L.T);
-    if (single && !d->T32.p) d->T32.upload(std::vector<float>(L.T.begin(), L.T.end()));
+    if (!single && !d->T64.p) d->T64.upload(padded_t<double>(L, false));
+    if (single && !d->T32.p) d->T32.upload(padded_t<float>(L, false));
 }
 
 static void upload_transposes(DeviceOp* d, bool single) {
-    const Layout& L = d->L;
     if ((single && d->Tt32.p) || (!single && d->Tt64.p)) return;
-    std::vector<double> tt(L.T.size());
-    for (int b = 0; b < L.n_boxes; ++b) {
-        const int64_t k = L.kb[b], m = L.nb[b] - L.kb[b];
-        if (k <= 0 || m <= 0) continue;
-        const double* src = L.T.data() + L.toff[b];
-        double* dst = tt.data() + L.toff[b];
-        for (int64_t j = 0; j < m; ++j)
-            for (int64_t i = 0; i < k; ++i) dst[j + i * m] = src[i + j * k];
-    }
-    if (single) d->Tt32.upload(std::vector<float>(tt.begin(), tt.end()));
-    else d->Tt64.upload(tt);
+    if (single) d->Tt32.upload(padded_t<float>(d->L, true));
+    else d->Tt64.upload(padded_t<double>(d->L, true));
 }
 
 void device_prepare(DeviceOp* d, int64_t nrhs, int dtype) {
@@ -369,6 +388,7 @@ void sweep(DeviceOp* d, const std::vector<IO>& io, int64_t nrhs, int dtype, hipS
     V* Uh = d->Uh.as<V>();
     const kern::BoxRec* br = d->boxrec.as<kern::BoxRec>();
     const int64_t* toff = d->toff.as<int64_t>();
+    const int64_t* ttoff = d->ttoff.as<int64_t>();
     const int32_t* pmap = d->pmap.as<int32_t>();
     const int32_t* ge = d->gather_e.as<int32_t>();
     const int32_t* gp = d->gather_p.as<int32_t>();
@@ -388,10 +408,11 @@ void sweep(DeviceOp* d, const std::vector<IO>& io, int64_t nrhs, int dtype, hipS
             hipLaunchKernelGGL((kern::k_upward_mr<V, TT>), dim3(nbx), dim3(256), 0, s, br, toff, pmap, b0, Wp, T, Q,
                                Qh);
         } else {
-            const int64_t w0 = d->up_ptr[l], nwk = d->up_ptr[l + 1] - w0;
+            const int wg = sizeof(TT) == 4 ? 1 : 0;
+            const int64_t w0 = d->up_ptr[wg][l], nwk = d->up_ptr[wg][l + 1] - w0;
             if (nwk <= 0) continue;
             const int nw = d->up_nw[l];
-            const int2* wk = d->upwork.as<int2>() + w0;
+            const int2* wk = d->upwork[wg].as<int2>() + w0;
             if (P::nv == 1)
                 hipLaunchKernelGGL((kern::k_up_gemv<V, TT, 1>), dim3(nwk), dim3(64 * nw), 0, s, wk, br, toff, pmap, T,
                                    Q, Q, Qh, nw);
@@ -416,18 +437,19 @@ void sweep(DeviceOp* d, const std::vector<IO>& io, int64_t nrhs, int dtype, hipS
         const int b0 = L.level_ptr[l], nbx = L.level_ptr[l + 1] - b0;
         if (nbx <= 0) continue;
         if (multi) {
-            hipLaunchKernelGGL((kern::k_downward_mr<V, TT>), dim3(nbx), dim3(256), 0, s, br, toff, pmap, b0, Wp, Tt,
+            hipLaunchKernelGGL((kern::k_downward_mr<V, TT>), dim3(nbx), dim3(256), 0, s, br, ttoff, pmap, b0, Wp, Tt,
                                Uh, U);
         } else {
-            const int64_t w0 = d->down_ptr[l], nwk = d->down_ptr[l + 1] - w0;
+            const int wg = sizeof(TT) == 4 ? 1 : 0;
+            const int64_t w0 = d->down_ptr[wg][l], nwk = d->down_ptr[wg][l + 1] - w0;
             if (nwk <= 0) continue;
             const int nw = d->down_nw[l];
-            const int2* wk = d->downwork.as<int2>() + w0;
+            const int2* wk = d->downwork[wg].as<int2>() + w0;
             if (P::nv == 1)
-                hipLaunchKernelGGL((kern::k_down_gemv<V, TT, 1>), dim3(nwk), dim3(64 * nw), 0, s, wk, br, toff, pmap,
+                hipLaunchKernelGGL((kern::k_down_gemv<V, TT, 1>), dim3(nwk), dim3(64 * nw), 0, s, wk, br, ttoff, pmap,
                                    Tt, Uh, U, U, nw);
             else
-                hipLaunchKernelGGL((kern::k_down_gemv<V, TT, 2>), dim3(nwk), dim3(64 * nw), 0, s, wk, br, toff, pmap,
+                hipLaunchKernelGGL((kern::k_down_gemv<V, TT, 2>), dim3(nwk), dim3(64 * nw), 0, s, wk, br, ttoff, pmap,
                                    Tt, Uh, U, U, nw);
         }
         SKF_HIP(hipGetLastError());

@@ -125,20 +125,60 @@ struct alignas(32) BoxRec {
 
 // ---------------------------------------------------------------------------
 // transfers with one right-hand side: batched GEMVs over the boxes of a level.
-// A block owns one (box, group of 64 rows).  The columns are cut into at most
-// kChunks chunks whose length depends only on the box; the block's nw waves
-// take chunks round-robin and wave 0 adds the chunk partials in chunk order,
-// so the result does not depend on nw (a batch and a single apply agree bit
-// for bit).  The matrix is column-major, so a wave reads 64 consecutive rows
-// of one column per load; the vector entry of that column is wave-uniform (a
-// scalar load).  Many waves per box keep enough loads in flight to stream T
-// from HBM.
+// A block owns one (box, group of RowMap<TT>::group rows); each lane holds the
+// rows of one 8-byte load (one float64 or two float32 values; the columns are
+// padded to 128-byte lines, so a load never straddles a column).  The columns
+// are cut into at most chunks_max chunks whose length depends only on the box;
+// the block's nw waves take chunks round-robin and the partials are added in
+// chunk order, so the result does not depend on nw (a batch and a single apply
+// agree bit for bit).  The vector entry of a column is wave-uniform (a scalar
+// load).
 // ---------------------------------------------------------------------------
-constexpr int kChunks = 32;
+template <int NV>
+constexpr int chunks_max() { return 16 / NV; }
 
+template <int NV>
 __device__ __forceinline__ int chunk_len(int cols) {
-    const int nch = min(kChunks, (cols + 31) / 32);
+    const int nch = min(chunks_max<NV>(), (cols + 31) / 32);
     return nch > 0 ? (cols + nch - 1) / nch : 0;
+}
+
+// leading dimension of a padded column of T or T^T (columns start on 128-byte lines)
+__device__ __forceinline__ int64_t ld_pad(int x) { return (x + kTPad - 1) / kTPad * kTPad; }
+
+template <typename TT>
+struct Vec8;
+template <>
+struct Vec8<float> { using type = float2; };
+template <>
+struct Vec8<double> { using type = double; };
+
+// Rows of a group: lane l holds rows vec l .. vec l + vec - 1.
+template <typename TT>
+struct RowMap {
+    static constexpr int vec = 8 / static_cast<int>(sizeof(TT));
+    static constexpr int group = 64 * vec;
+};
+
+// acc[e] += sum over columns c in [c0, c1) of A[lane row e, c] x[c], A column-major
+// with leading dimension ld starting at the group's first row.
+template <typename TT, int NV, typename XF>
+__device__ __forceinline__ void gemv_chunk(const TT* __restrict__ A, int64_t ld, int rows, int lane, int c0,
+                                           int c1, XF xf, double (&acc)[RowMap<TT>::vec][NV]) {
+    using M = RowMap<TT>;
+    using VT = typename Vec8<TT>::type;
+    if (M::vec * lane >= rows) return;
+#pragma unroll 4
+    for (int c = c0; c < c1; ++c) {
+        double x[NV];
+        xf(c, x);
+        const VT t = *reinterpret_cast<const VT*>(A + M::vec * lane + c * ld);
+        const TT* te = reinterpret_cast<const TT*>(&t);
+#pragma unroll
+        for (int e = 0; e < M::vec; ++e)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) acc[e][v] = fma(static_cast<double>(te[e]), x[v], acc[e][v]);
+    }
 }
 
 // upward: qhat = q[0:k] + T q[k:n], written to Qh and to the parent's entries.
@@ -150,47 +190,53 @@ __global__ void __launch_bounds__(1024) k_up_gemv(const int2* __restrict__ work,
                                                   const int32_t* __restrict__ pmap, const TT* __restrict__ T,
                                                   const V* __restrict__ Qin, V* __restrict__ Qout,
                                                   V* __restrict__ Qh, int nw) {
-    __shared__ double part[kChunks][64 * NV];
+    using M = RowMap<TT>;
+    constexpr int NC = chunks_max<NV>();
+    __shared__ double part[NC][M::group * NV];
     const int2 wk = work[blockIdx.x];
     const BoxRec tb = box[wk.x];
     const int k = tb.k, m = tb.n - tb.k;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int i = wk.y + lane;
-    const bool act = i < k;
-    const TT* __restrict__ Tb = T + toff[wk.x];
+    const int r0 = wk.y * M::group;
+    const TT* __restrict__ Tb = T + toff[wk.x] + r0;
+    const int64_t ldk = ld_pad(k);
     const V* __restrict__ xr = Qin + (tb.voff + k) * NV;
-    const int ch = chunk_len(m);
+    const int ch = chunk_len<NV>(m);
     const int nch = ch > 0 ? (m + ch - 1) / ch : 0;
     for (int c = wave; c < nch; c += nw) {
-        double acc[NV];
+        double acc[M::vec][NV];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) acc[v] = 0.0;
-        const int j1 = min(m, (c + 1) * ch);
-#pragma unroll 4
-        for (int j = c * ch; j < j1; ++j) {
-            const double t = act ? static_cast<double>(Tb[i + static_cast<int64_t>(j) * k]) : 0.0;
+        for (int r = 0; r < M::vec; ++r)
 #pragma unroll
-            for (int v = 0; v < NV; ++v) acc[v] = fma(t, static_cast<double>(xr[j * NV + v]), acc[v]);
-        }
+            for (int v = 0; v < NV; ++v) acc[r][v] = 0.0;
+        gemv_chunk<TT, NV>(Tb, ldk, k - r0, lane, c * ch, min(m, (c + 1) * ch),
+                           [&](int j, double (&x)[NV]) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) part[c][lane * NV + v] = acc[v];
+                               for (int v = 0; v < NV; ++v) x[v] = static_cast<double>(xr[j * NV + v]);
+                           },
+                           acc);
+#pragma unroll
+        for (int e = 0; e < M::vec; ++e)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) part[c][(M::vec * lane + e) * NV + v] = acc[e][v];
     }
     __syncthreads();
-    if (wave == 0 && act) {
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            double sum = static_cast<double>(Qin[(tb.voff + i) * NV + v]);
-            for (int c = 0; c < nch; ++c) sum += part[c][lane * NV + v];
-            const V val = static_cast<V>(sum);
-            Qh[(tb.hoff + i) * NV + v] = val;
-            Qout[static_cast<int64_t>(pmap[tb.hoff + i]) * NV + v] = val;
-        }
+    const int rows = min(M::group, k - r0);
+    for (int t = threadIdx.x; t < rows * NV; t += blockDim.x) {
+        const int r = t / NV, v = t - r * NV;
+        const int i = r0 + r;
+        double sum = static_cast<double>(Qin[(tb.voff + i) * NV + v]);
+        for (int c = 0; c < nch; ++c) sum += part[c][t];
+        const V val = static_cast<V>(sum);
+        Qh[(tb.hoff + i) * NV + v] = val;
+        Qout[static_cast<int64_t>(pmap[tb.hoff + i]) * NV + v] = val;
     }
 }
 
 // downward: uhat = Uh + U_parent[pmap]; u[0:k] += uhat; u[k:n] += T^T uhat,
-// with Tt = T^T stored column-major (m x k) so rows of the result are contiguous.
+// with Tt = T^T stored column-major (m x k, columns padded) so rows of the
+// result are contiguous; toff here holds the offsets of the transposes.
 // Upar reads the parent level's entries, Uown updates this box's entries.
 template <typename V, typename TT, int NV>
 __global__ void __launch_bounds__(1024) k_down_gemv(const int2* __restrict__ work, const BoxRec* __restrict__ box,
@@ -198,47 +244,51 @@ __global__ void __launch_bounds__(1024) k_down_gemv(const int2* __restrict__ wor
                                                     const int32_t* __restrict__ pmap, const TT* __restrict__ Tt,
                                                     const V* __restrict__ Uh, const V* __restrict__ Upar,
                                                     V* __restrict__ Uown, int nw) {
-    __shared__ double part[kChunks][64 * NV];
+    using M = RowMap<TT>;
+    constexpr int NC = chunks_max<NV>();
+    __shared__ double part[NC][M::group * NV];
     const int2 wk = work[blockIdx.x];
     const BoxRec tb = box[wk.x];
     const int k = tb.k, m = tb.n - tb.k;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int j = wk.y + lane;
-    const bool act = j < m;
-    const TT* __restrict__ Tb = Tt + toff[wk.x];
+    const int r0 = wk.y * M::group;
+    const TT* __restrict__ Tb = Tt + toff[wk.x] + r0;
+    const int64_t ldm = ld_pad(m);
     const V* __restrict__ uhb = Uh + tb.hoff * NV;
     const int32_t* __restrict__ pm = pmap + tb.hoff;
-    const int ch = m > 0 ? chunk_len(k) : 0;   // an uncompressed box has no T
+    const int ch = m > 0 ? chunk_len<NV>(k) : 0;   // an uncompressed box has no T
     const int nch = ch > 0 ? (k + ch - 1) / ch : 0;
     for (int c = wave; c < nch; c += nw) {
-        double acc[NV];
+        double acc[M::vec][NV];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) acc[v] = 0.0;
-        const int i1 = min(k, (c + 1) * ch);
-#pragma unroll 4
-        for (int i = c * ch; i < i1; ++i) {
-            const double t = act ? static_cast<double>(Tb[j + static_cast<int64_t>(i) * m]) : 0.0;
-            const int64_t pe = static_cast<int64_t>(pm[i]) * NV;
+        for (int r = 0; r < M::vec; ++r)
 #pragma unroll
-            for (int v = 0; v < NV; ++v)
-                acc[v] = fma(t, static_cast<double>(uhb[i * NV + v]) + static_cast<double>(Upar[pe + v]), acc[v]);
-        }
+            for (int v = 0; v < NV; ++v) acc[r][v] = 0.0;
+        gemv_chunk<TT, NV>(Tb, ldm, m - r0, lane, c * ch, min(k, (c + 1) * ch),
+                           [&](int i, double (&x)[NV]) {
+                               const int64_t pe = static_cast<int64_t>(pm[i]) * NV;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) part[c][lane * NV + v] = acc[v];
+                               for (int v = 0; v < NV; ++v)
+                                   x[v] = static_cast<double>(uhb[i * NV + v]) + static_cast<double>(Upar[pe + v]);
+                           },
+                           acc);
+#pragma unroll
+        for (int e = 0; e < M::vec; ++e)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) part[c][(M::vec * lane + e) * NV + v] = acc[e][v];
     }
     __syncthreads();
-    if (wave == 0 && act) {
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            double sum = 0.0;
-            for (int c = 0; c < nch; ++c) sum += part[c][lane * NV + v];
-            V* u = Uown + (tb.voff + k + j) * NV + v;
-            *u = static_cast<V>(static_cast<double>(*u) + sum);
-        }
+    const int rows = max(0, min(M::group, m - r0));
+    for (int t = threadIdx.x; t < rows * NV; t += blockDim.x) {
+        const int r = t / NV, v = t - r * NV;
+        double sum = 0.0;
+        for (int c = 0; c < nch; ++c) sum += part[c][t];
+        V* u = Uown + (tb.voff + k + r0 + r) * NV + v;
+        *u = static_cast<V>(static_cast<double>(*u) + sum);
     }
     // the first row group of a box also adds uhat to the skeleton entries
-    if (wk.y == 0) {
+    if (r0 == 0) {
         for (int t = threadIdx.x; t < k * NV; t += blockDim.x) {
             const int ii = t / NV, v = t - ii * NV;
             V* u = Uown + (tb.voff + ii) * NV + v;
@@ -733,7 +783,7 @@ __global__ void k_scatter_pad(const int32_t* __restrict__ src_e, const int32_t* 
 // column are one wave-uniform scalar load; x rows are coalesced vector loads.
 constexpr int kRB = 16;
 
-// upward: qhat = q[0:k] + T q[k:n]  (T column-major k x m)
+// upward: qhat = q[0:k] + T q[k:n]  (T column-major k x m, columns padded to ld_pad(k))
 template <typename V, typename TT>
 __global__ void __launch_bounds__(256) k_upward_mr(const BoxRec* __restrict__ box, const int64_t* __restrict__ toff,
                                                   const int32_t* __restrict__ pmap, int b0, int Wp,
@@ -755,7 +805,7 @@ __global__ void __launch_bounds__(256) k_upward_mr(const BoxRec* __restrict__ bo
             const int nr = min(kRB, k - r0);
             for (int j = 0; j < m; ++j) {
                 const double x = act ? static_cast<double>(Q[(tb.voff + k + j) * Wp + c]) : 0.0;
-                const TT* col = Tb + r0 + static_cast<int64_t>(j) * k;
+                const TT* col = Tb + r0 + static_cast<int64_t>(j) * ld_pad(k);
                 if (nr == kRB) {
 #pragma unroll
                     for (int rr = 0; rr < kRB; ++rr) acc[rr] = fma(static_cast<double>(col[rr]), x, acc[rr]);
@@ -808,7 +858,7 @@ __global__ void __launch_bounds__(256) k_downward_mr(const BoxRec* __restrict__ 
                 const double x = act ? static_cast<double>(Uh[(tb.hoff + i) * Wp + c]) +
                                            static_cast<double>(U[static_cast<int64_t>(pmap[tb.hoff + i]) * Wp + c])
                                      : 0.0;
-                const TT* col = Tb + r0 + static_cast<int64_t>(i) * m;
+                const TT* col = Tb + r0 + static_cast<int64_t>(i) * ld_pad(m);
                 if (nr == kRB) {
 #pragma unroll
                     for (int rr = 0; rr < kRB; ++rr) acc[rr] = fma(static_cast<double>(col[rr]), x, acc[rr]);

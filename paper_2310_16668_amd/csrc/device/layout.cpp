@@ -153,6 +153,8 @@ Layout make_layout(const Plan& p, bool keep_transparent, int tile) {
         L.seg_ptr[b + 1] = static_cast<int32_t>(L.seg_src.size());
     }
 
+    pad_transfer_offsets(L);
+
     // work list and pair counts
     L.tasks = make_tasks(L, tile);
     for (int b = 0; b < nb; ++b) {
@@ -371,8 +373,26 @@ Layout merge_layouts(const std::vector<const Layout*>& ls, std::vector<int64_t>&
             M.gather_p.push_back(L.gather_p[j]);
         }
     }
+    pad_transfer_offsets(M);
     M.tasks = make_tasks(M, M.tile);
     return M;
+}
+
+void pad_transfer_offsets(Layout& L) {
+    L.tpad.assign(L.n_boxes, 0);
+    L.ttpad.assign(L.n_boxes, 0);
+    int64_t a = 0, b = 0;
+    for (int i = 0; i < L.n_boxes; ++i) {
+        const int64_t k = L.kb[i], m = L.nb[i] - L.kb[i];
+        L.tpad[i] = a;
+        L.ttpad[i] = b;
+        if (k > 0 && m > 0) {
+            a += pad_ld(k) * m;
+            b += pad_ld(m) * k;
+        }
+    }
+    L.tpad_size = a;
+    L.ttpad_size = b;
 }
 
 std::vector<Task> make_tasks(const Layout& L, int tile, bool ns) {
