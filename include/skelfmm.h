@@ -152,11 +152,13 @@ skelfmm_status skelfmm_apply_adjoint(skelfmm_op* op, const void* v, void* w, int
 skelfmm_status skelfmm_stats_get(const skelfmm_op* op, skelfmm_stats* out);
 
 /* Near-field launch shape (an in-library autotuner).  Each near-field work item is
- * one wavefront holding 64 x tpl targets (tpl targets per lane, tpl in {1, 2, 4}).
- * skelfmm_autotune prepares the operator for `dtype`, times the near-field launch
- * for each tpl on `hip_stream` (synchronously; it overwrites the workspace), keeps
- * the fastest and returns it in *chosen, with the three timings in ms[3] (may be
- * NULL).  skelfmm_set_targets_per_lane fixes tpl without timing. */
+ * one wavefront holding 64 x tpl targets per pass (tpl targets per lane, tpl in
+ * 1..SKELFMM_NTPL).  skelfmm_autotune prepares the operator for `dtype`, times the
+ * near-field launches for each tpl on `hip_stream` (synchronously; it overwrites
+ * the workspace), keeps the fastest and returns it in *chosen, with the timings
+ * in ms[SKELFMM_NTPL] (ms[tpl - 1]; may be NULL).  skelfmm_set_targets_per_lane
+ * fixes tpl without timing. */
+#define SKELFMM_NTPL 4
 skelfmm_status skelfmm_autotune(skelfmm_op* op, skelfmm_dtype dtype, void* hip_stream, int32_t* chosen, float* ms);
 skelfmm_status skelfmm_set_targets_per_lane(skelfmm_op* op, int32_t tpl);
 

@@ -186,16 +186,16 @@ class Operator:
         }
 
     def autotune(self, dtype=None) -> dict:
-        """Time the near-field launch with 1, 2 and 4 targets per lane; keep the fastest."""
+        """Time the near-field launches with 1 .. 4 targets per lane; keep the fastest."""
         torch = _torch()
         if dtype is None:
             dtype = torch.complex128 if self.kind == HELMHOLTZ else torch.float64
         code = _dtype_code(torch.empty(0, dtype=dtype))
         chosen = ctypes.c_int32()
-        ms = (ctypes.c_float * 3)()
+        ms = (ctypes.c_float * 4)()
         stream = torch.cuda.current_stream().cuda_stream
         _check(_lib.skelfmm_autotune(self._h, code, stream, ctypes.byref(chosen), ms))
-        return {"targets_per_lane": chosen.value, "ms": {1: ms[0], 2: ms[1], 4: ms[2]}}
+        return {"targets_per_lane": chosen.value, "ms": {t: ms[t - 1] for t in (1, 2, 3, 4)}}
 
     def set_targets_per_lane(self, tpl: int):
         _check(_lib.skelfmm_set_targets_per_lane(self._h, tpl))

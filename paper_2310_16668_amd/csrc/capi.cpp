@@ -187,16 +187,16 @@ skelfmm_status skelfmm_autotune(skelfmm_op* op, skelfmm_dtype dtype, void* hip_s
     if (!chosen) return fail(SKELFMM_EINVAL, "chosen is NULL");
     if (skelfmm_status s = check_dtype(op, dtype)) return s;
     return guarded([&]() -> skelfmm_status {
-        float t[3] = {0, 0, 0};
+        float t[SKELFMM_NTPL] = {};
         *chosen = skelfmm::device_autotune(op->dev, static_cast<int>(dtype), hip_stream, t);
-        if (ms) for (int i = 0; i < 3; ++i) ms[i] = t[i];
+        if (ms) for (int i = 0; i < SKELFMM_NTPL; ++i) ms[i] = t[i];
         return SKELFMM_OK;
     });
 }
 
 skelfmm_status skelfmm_set_targets_per_lane(skelfmm_op* op, int32_t tpl) {
     if (!alive(op)) return fail(SKELFMM_EINVAL, "invalid operator");
-    if (tpl != 1 && tpl != 2 && tpl != 4) return fail(SKELFMM_EINVAL, "targets per lane must be 1, 2 or 4");
+    if (tpl < 1 || tpl > SKELFMM_NTPL) return fail(SKELFMM_EINVAL, "targets per lane must be 1 .. 4");
     return guarded([&]() -> skelfmm_status {
         skelfmm::device_set_tpl(op->dev, tpl);
         return SKELFMM_OK;

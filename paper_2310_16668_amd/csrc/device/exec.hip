@@ -75,10 +75,10 @@ struct DevMem {
 int dtype_is_complex(int dt) { return dt == SKELFMM_C128 || dt == SKELFMM_C64; }
 int dtype_is_single(int dt) { return dt == SKELFMM_F32 || dt == SKELFMM_C64; }
 
-constexpr int kDefaultTPL = 2;   // targets per lane in the single-RHS near-field kernel (1, 2 or 4)
+constexpr int kDefaultTPL = 2;   // targets per lane in the single-RHS near-field kernels (1 .. 4)
 constexpr int kChunkReals = 8;   // right-hand-side reals per multi-RHS near-field work item
 
-int tpl_slot(int tpl) { return tpl == 1 ? 0 : (tpl == 2 ? 1 : 2); }
+int tpl_slot(int tpl) { return tpl - 1; }
 
 // Values per entry inside the workspace: nv for one RHS; several RHS are padded
 // to a multiple of the near-field chunk.
@@ -106,12 +106,12 @@ struct DeviceOp {
     std::vector<int64_t> up_ptr[2], down_ptr[2];
     std::vector<int> up_nw, down_nw;
     int tpl = kDefaultTPL;
-    DevMem tasks[3];                              // work lists for 1, 2, 4 targets per lane
-    int ntasks[3] = {0, 0, 0};
+    DevMem tasks[SKELFMM_NTPL];                   // work lists for 1 .. 4 targets per lane
+    int ntasks[SKELFMM_NTPL] = {};
     // symmetric near field (one RHS): segment lists without the paired ifo
     // terms, their work lists, the pair items, the slot reduction lists
-    DevMem seg_ptr_ns, segs_ns, tasks_ns[3], symtasks, symrows, slots;
-    int ntasks_ns[3] = {0, 0, 0};
+    DevMem seg_ptr_ns, segs_ns, tasks_ns[SKELFMM_NTPL], symtasks, symrows, slots;
+    int ntasks_ns[SKELFMM_NTPL] = {};
     int nsym = 0, nred = 0;
     // workspace
     DevMem Q, Qh, U, Uh;
@@ -138,8 +138,9 @@ static void check_ranks(const Layout& L) {
     if (kmax > 8192) throw NotSupported("skeleton rank above 8192 is not supported by the downward kernel");
 }
 
-// Targets of the larger box per symmetric work item (a multiple of 64 x 4).
-constexpr int kSymGroup = 512;
+// Targets of the lane-side box per symmetric work item (a multiple of 64 x tpl
+// for every tpl in 1 .. 4).
+constexpr int kSymGroup = 768;
 
 DeviceOp* device_create(const Plan& p, bool keep_transparent, bool f64_leaf, bool symmetric) {
     auto d = std::make_unique<DeviceOp>();
@@ -232,7 +233,7 @@ static void upload(DeviceOp* d, int dtype) {
         std::vector<int2> sg(L.seg_src.size());
         for (size_t i = 0; i < sg.size(); ++i) sg[i] = make_int2(L.seg_src[i], L.seg_mode[i]);
         d->segs.upload(sg);
-        for (int t : {1, 2, 4}) {
+        for (int t : {1, 2, 3, 4}) {
             const std::vector<Task> tl = (64 * t == L.tile) ? L.tasks : make_tasks(L, 64 * t);
             d->tasks[tpl_slot(t)].upload(tl);
             d->ntasks[tpl_slot(t)] = static_cast<int>(tl.size());
@@ -244,7 +245,7 @@ static void upload(DeviceOp* d, int dtype) {
             d->segs_ns.upload(sn);
             d->symtasks.upload(L.sym_tasks);
             d->nsym = static_cast<int>(L.sym_tasks.size());
-            for (int t : {1, 2, 4}) {
+            for (int t : {1, 2, 3, 4}) {
                 const std::vector<Task> tl = make_tasks(L, 64 * t, true);
                 d->tasks_ns[tpl_slot(t)].upload(tl);
                 d->ntasks_ns[tpl_slot(t)] = static_cast<int>(tl.size());
@@ -353,6 +354,7 @@ void launch_near_t(const DeviceOp* d, hipStream_t s, void* Q, void* Qh, void* U,
 template <class P, bool CONJ>
 void launch_near(const DeviceOp* d, hipStream_t s, void* Q, void* Qh, void* U, void* Uh, PassMarks* pm = nullptr) {
     if (d->tpl == 1) launch_near_t<P, 1, CONJ>(d, s, Q, Qh, U, Uh, pm);
+    else if (d->tpl == 3) launch_near_t<P, 3, CONJ>(d, s, Q, Qh, U, Uh, pm);
     else if (d->tpl == 4) launch_near_t<P, 4, CONJ>(d, s, Q, Qh, U, Uh, pm);
     else launch_near_t<P, 2, CONJ>(d, s, Q, Qh, U, Uh, pm);
 }
@@ -498,13 +500,13 @@ void device_apply(DeviceOp* d, const void* q, void* u, int64_t nrhs, int dtype, 
     run(d, {IO{q, u, 0, d->L.n_points}}, nrhs, dtype, stream, adjoint);
 }
 
-// Time the near-field launch for 1, 2 and 4 targets per lane on this operator
+// Time the near-field launches for 1 .. 4 targets per lane on this operator
 // (workspace contents are whatever the last apply left; timing does not depend
 // on values) and keep the fastest.
 template <int DIM, int KIND>
 static void tune_near(DeviceOp* d, int dtype, hipStream_t s, float* ms_out) {
     const bool single = dtype_is_single(dtype);
-    for (int t : {1, 2, 4}) {
+    for (int t : {1, 2, 3, 4}) {
         d->tpl = t;
         hipEvent_t a, b;
         SKF_HIP(hipEventCreate(&a));
@@ -531,7 +533,7 @@ static void tune_near(DeviceOp* d, int dtype, hipStream_t s, float* ms_out) {
         (void)hipEventDestroy(b);
     }
     int best = 1;
-    for (int t : {1, 2, 4})
+    for (int t : {1, 2, 3, 4})
         if (ms_out[tpl_slot(t)] < ms_out[tpl_slot(best)]) best = t;
     d->tpl = best;
 }
@@ -547,7 +549,7 @@ int device_autotune(DeviceOp* d, int dtype, void* stream, float* ms_out) {
 }
 
 void device_set_tpl(DeviceOp* d, int tpl) {
-    if (tpl != 1 && tpl != 2 && tpl != 4) throw std::invalid_argument("targets per lane must be 1, 2 or 4");
+    if (tpl < 1 || tpl > SKELFMM_NTPL) throw std::invalid_argument("targets per lane must be 1 .. 4");
     d->tpl = tpl;
 }
 

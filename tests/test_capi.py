@@ -89,7 +89,9 @@ def test_apply_argument_errors_before_gpu_work():
     assert lib.skelfmm_apply(op.handle, buf, ctypes.c_void_p(0x2000), 1, sk.C128, None) == -1
     assert lib.skelfmm_apply(op.handle, buf, ctypes.c_void_p(0x2000), 1, 9, None) == -1
     assert lib.skelfmm_apply(None, buf, ctypes.c_void_p(0x2000), 1, sk.F64, None) == -1
-    assert lib.skelfmm_set_targets_per_lane(op.handle, 3) == -1
+    assert lib.skelfmm_set_targets_per_lane(op.handle, 5) == -1
+    assert lib.skelfmm_set_targets_per_lane(op.handle, 0) == -1
+    assert lib.skelfmm_set_targets_per_lane(op.handle, 3) == 0
     assert lib.skelfmm_set_targets_per_lane(op.handle, 4) == 0
     assert b"complex" in lib.skelfmm_last_error() or lib.skelfmm_last_error() != b""
 

@@ -283,7 +283,7 @@ def test_symmetric_pairing_matches_unpaired_and_o2(name):
     q = _charges(name, x.shape[0], 11)
     u2 = oracle.apply(P, q)
     un = host(op_ns.apply(dev(q, torch.float64)))
-    for t in (1, 2, 4):
+    for t in (1, 2, 3, 4):
         op.set_targets_per_lane(t)
         u = host(op.apply(dev(q, torch.float64)))
         e2, en = relerr(u, u2), relerr(u, un)
