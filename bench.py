@@ -283,14 +283,19 @@ def main():
         chosen = min(ok or list(results), key=lambda k: results[k]["ms_per_step"])
     r = results[chosen]
     pm = r["passes_ms_per_sweep"]
+    # pair counts at the headline path's targets per lane (the diagonal tiles depend on it)
+    if chosen in tuned:
+        op.set_targets_per_lane(tuned[chosen]["targets_per_lane"])
+    st = op.stats()
     # pairs left to k_near after symmetric pairing (each paired evaluation covers two)
-    pairs_ns = st["pairs_near"] - 2 * st["pairs_sym"]
-    skel_ns = st["pairs_skel"] - 2 * st["pairs_sym_skel"]
+    pairs_ns = st["pairs_near"] - 2 * st["pairs_sym"] - st["pairs_tile"]
+    skel_ns = st["pairs_skel"] - 2 * st["pairs_sym_skel"] - st["pairs_tile_skel"]
     # per near-field kernel: (ms per launch, algorithmic flops per launch)
     kernels = {
         "k_near": (pm["near_field"], FLOPS_PER_PAIR * pairs_ns + FLOPS_PER_SKEL_PAIR * skel_ns),
         "k_near_sym": (pm["near_pairs"], FLOPS_PER_SYM_PAIR * st["pairs_sym"]
-                       + FLOPS_PER_SYM_SKEL_PAIR * st["pairs_sym_skel"]),
+                       + FLOPS_PER_SYM_SKEL_PAIR * st["pairs_sym_skel"]
+                       + FLOPS_PER_PAIR * st["pairs_tile"] + FLOPS_PER_SKEL_PAIR * st["pairs_tile_skel"]),
     }
     dom = max(kernels, key=lambda k: kernels[k][0])
     near_ms, flops = kernels[dom]
@@ -326,6 +331,7 @@ def main():
                      "frac": achieved / PEAK_TFLOPS[chosen], "traffic": traffic,
                      "kernel": dom, "ms_per_launch": near_ms,
                      "sym_pairs_per_launch": st["pairs_sym"], "sym_skel_pairs_per_launch": st["pairs_sym_skel"],
+                     "tile_pairs_per_launch": st["pairs_tile"], "tile_skel_pairs_per_launch": st["pairs_tile_skel"],
                      "segment_pairs_per_launch": pairs_ns, "segment_skel_pairs_per_launch": skel_ns,
                      "near_kernels": {k: {"ms": v[0], "tflops": v[1] / (v[0] * 1e-3) / 1e12 if v[0] > 0 else None}
                                       for k, v in kernels.items()},

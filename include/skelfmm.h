@@ -96,9 +96,12 @@ typedef struct {
     int64_t n_tasks;                 /* near-field work items */
     int32_t tile_targets;            /* targets per near-field work item */
     int32_t n_sym_tasks;             /* symmetric colleague-pair work items (0 when not paired) */
-    int64_t pairs_sym;               /* kernel evaluations of the paired colleague blocks (each serves
-                                        two of the pairs counted in pairs_near) */
+    int64_t pairs_sym;               /* kernel evaluations of the symmetric pair items that serve both
+                                        directions (each covers two of the pairs in pairs_near) */
     int64_t pairs_sym_skel;          /* skeleton pairs inside them (two uhat multiply-adds each) */
+    int64_t pairs_tile;              /* one-direction evaluations in the diagonal tiles of a box
+                                        paired with itself (for the current targets per lane) */
+    int64_t pairs_tile_skel;         /* skeleton pairs inside them */
     int32_t reserved[2];
 } skelfmm_stats;
 

@@ -56,7 +56,8 @@ class Stats(ctypes.Structure):
                 ("m_proj_elems", ctypes.c_int64), ("n_entries", ctypes.c_int64),
                 ("pairs_near", ctypes.c_int64), ("pairs_skel", ctypes.c_int64), ("n_tasks", ctypes.c_int64),
                 ("tile_targets", ctypes.c_int32), ("n_sym_tasks", ctypes.c_int32), ("pairs_sym", ctypes.c_int64),
-                ("pairs_sym_skel", ctypes.c_int64), ("reserved", ctypes.c_int32 * 2)]
+                ("pairs_sym_skel", ctypes.c_int64), ("pairs_tile", ctypes.c_int64),
+                ("pairs_tile_skel", ctypes.c_int64), ("reserved", ctypes.c_int32 * 2)]
 
 
 _P = ctypes.POINTER

@@ -85,7 +85,6 @@ struct Layout {
     std::vector<SymTask> sym_tasks;
     std::vector<SymRows> sym_rows;               // boxes receiving slot rows
     int64_t slot_size = 0;
-    int64_t pairs_sym = 0, pairs_sym_skel = 0;
 };
 
 constexpr int kTPad = 32;
@@ -99,6 +98,10 @@ Layout make_layout(const Plan& p, bool keep_transparent, int tile);
 std::vector<Task> make_tasks(const Layout& L, int tile, bool ns = false);
 // Pair up colleague segments of compressed boxes for the symmetric near field.
 void make_symmetric(Layout& L, int group);
+// Kernel evaluations of the pair items with tpl targets per lane: out[0] pairs
+// serving both directions, out[1] their skeleton pairs, out[2] one-direction
+// evaluations in the diagonal tiles of self items, out[3] their skeleton pairs.
+void sym_pair_counts(const Layout& L, int tpl, int64_t out[4]);
 // One layout for several operators: boxes renumbered by (level, operator), entry,
 // skeleton-entry and T offsets shifted, one cost-sorted work list over all of
 // them.  entry_base / hentry_base receive each operator's first entry / skeleton entry.

@@ -561,8 +561,12 @@ void device_fill_stats(const DeviceOp* d, skelfmm_stats* out) {
                                : static_cast<int64_t>(d->L.tasks.size());
     out->tile_targets = 64 * d->tpl;
     out->n_sym_tasks = static_cast<int32_t>(d->L.sym_tasks.size());
-    out->pairs_sym = d->L.pairs_sym;
-    out->pairs_sym_skel = d->L.pairs_sym_skel;
+    int64_t pc[4];
+    sym_pair_counts(d->L, d->tpl, pc);
+    out->pairs_sym = pc[0];
+    out->pairs_sym_skel = pc[1];
+    out->pairs_tile = pc[2];
+    out->pairs_tile_skel = pc[3];
 }
 
 void device_destroy(DeviceOp* d) { delete d; }

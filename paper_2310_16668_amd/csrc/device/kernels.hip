@@ -501,11 +501,12 @@ struct alignas(16) SrcRec {
 // One block of up to kSymBlock sources s0 .. s0 + cnt - 1 of box j, read from
 // the wave's staged copy src[0 .. kSymBlock).  H: the pass holds skeleton
 // targets and the block lies in j's skeleton, so the uhat terms run too.
+// MASK: zero the pairs at distance 0 (needed where a box meets itself).
 // Positions past cnt repeat the last source with zero charges (their reverse
 // sums are not stored), so the block is branch-free.  Reverse sums go to
 // rev_u[s] (and rev_h[s]), stored on the item's first pass and accumulated on
 // later ones.
-template <class P, int TPL, bool H>
+template <class P, int TPL, bool H, bool MASK>
 __device__ __forceinline__ void sym_block(const SrcRec<typename P::Rt>* src, int s0, int cnt,
                                           const double (&xt)[TPL], const double (&yt)[TPL],
                                           const double (&zt)[TPL], const typename P::Rt (&wi)[TPL],
@@ -536,7 +537,7 @@ __device__ __forceinline__ void sym_block(const SrcRec<typename P::Rt>* src, int
 #pragma unroll
         for (int p = 0; p < TPL; ++p) {
             R g, gi;
-            green<P, false, false>(xt[p] - sv.x, yt[p] - sv.y, zt[p] - sv.z, R(0), g, gi);
+            green<P, false, MASK>(xt[p] - sv.x, yt[p] - sv.y, zt[p] - sv.z, R(0), g, gi);
             bacc[p] = fma(g, sv.w, bacc[p]);
             ru[c] = fma(g, wi[p], ru[c]);
             if constexpr (H) {
@@ -560,12 +561,20 @@ __device__ __forceinline__ void sym_block(const SrcRec<typename P::Rt>* src, int
     }
 }
 
-// Sources of a pass in blocks: first the skeleton blocks [0, kH) (kH = k_j when
-// the uhat terms run, else 0), then the rest [kH, n_j), 16 at a time.
+// Sources [s_begin, n_j) of a pass in blocks: first the skeleton blocks
+// [s_begin, kH) (kH = k_j when the uhat terms run, else s_begin), then the rest
+// [kH, n_j), 16 at a time.
 struct BlockPlan {
-    int kH, nbH, nb, n;
+    int sb, kH, nbH, nb, n;
+    __device__ void init(int s_begin, int k_h, int n_j) {
+        sb = s_begin;
+        kH = max(s_begin, k_h);
+        n = n_j;
+        nbH = (kH - sb + kSymBlock - 1) / kSymBlock;
+        nb = nbH + (max(0, n - kH) + kSymBlock - 1) / kSymBlock;
+    }
     __device__ void range(int b, int& s0, int& cnt) const {
-        if (b < nbH) { s0 = b * kSymBlock; cnt = min(kSymBlock, kH - s0); }
+        if (b < nbH) { s0 = sb + b * kSymBlock; cnt = min(kSymBlock, kH - s0); }
         else { s0 = kH + (b - nbH) * kSymBlock; cnt = min(kSymBlock, n - s0); }
     }
 };
@@ -604,7 +613,7 @@ struct SymCtx {
 
 // One pass: targets tp .. tp + 64 TPL - 1 of box i (those below t1) against all
 // sources of box j.
-template <class P, int TPL>
+template <class P, int TPL, bool SELF>
 __device__ __forceinline__ void sym_pass(const SymCtx& cx, int tp, const Rec4<double>* __restrict__ X,
                                          const typename P::Vt* __restrict__ Q,
                                          const typename P::Vt* __restrict__ Qh,
@@ -618,11 +627,12 @@ __device__ __forceinline__ void sym_pass(const SymCtx& cx, int tp, const Rec4<do
     const bool first = tp == cx.t0;
     // skeleton targets in this pass and a skeleton in box j: the uhat terms run
     const bool hp = tp < bi.k && bj.k > 0;
+    // a box paired with itself: the diagonal tile (sources = this pass's
+    // targets) is evaluated in the forward direction only, the sources after it
+    // in both
+    const int tile_end = SELF ? min(tp + 64 * TPL, cx.t1) : 0;
     BlockPlan bp;
-    bp.kH = hp ? bj.k : 0;
-    bp.nbH = (bp.kH + kSymBlock - 1) / kSymBlock;
-    bp.n = bj.n;
-    bp.nb = bp.nbH + (bj.n - bp.kH + kSymBlock - 1) / kSymBlock;
+    bp.init(tile_end, hp ? bj.k : 0, bj.n);
     double xt[TPL], yt[TPL], zt[TPL];
     R wi[TPL], whi[TPL];
     A acc[TPL], acch[TPL];
@@ -638,22 +648,39 @@ __device__ __forceinline__ void sym_pass(const SymCtx& cx, int tp, const Rec4<do
         acc[p] = A(0);
         acch[p] = A(0);
     }
+    if constexpr (SELF) {
+        A ad[TPL][1], adh[TPL][1];
+#pragma unroll
+        for (int p = 0; p < TPL; ++p) { ad[p][0] = A(0); adh[p][0] = A(0); }
+        if (hp) {
+            near_loop<P, TPL, false, 1, true>(Xs, Qs, Qhs, tp, min(tile_end, bj.k), R(0), xt, yt, zt, ad, adh);
+            near_loop<P, TPL, false, 0, true>(Xs, Qs, Qhs, max(tp, bj.k), tile_end, R(0), xt, yt, zt, ad, adh);
+        } else {
+            near_loop<P, TPL, false, 0, true>(Xs, Qs, Qhs, tp, tile_end, R(0), xt, yt, zt, ad, adh);
+        }
+        // near_loop accumulates the uhat part with its minus sign; the pair
+        // blocks below accumulate it positive and the store negates
+#pragma unroll
+        for (int p = 0; p < TPL; ++p) { acc[p] = ad[p][0]; acch[p] = -adh[p][0]; }
+    }
     // the next block's sources are fetched while the current one is evaluated
-    SrcRec<R> staged{};
-    stage_load<P>(bp, 0, Xs, Qs, Qhs, lane, staged);
-    for (int b = 0; b < bp.nb; ++b) {
-        int s0, cnt;
-        bp.range(b, s0, cnt);
-        wave_sync();
-        if (lane < kSymBlock) src[lane] = staged;
-        wave_sync();
-        if (b + 1 < bp.nb) stage_load<P>(bp, b + 1, Xs, Qs, Qhs, lane, staged);
-        if (b < bp.nbH)
-            sym_block<P, TPL, true>(src, s0, cnt, xt, yt, zt, wi, whi, acc, acch, tile, lane, cx.rev_u, cx.rev_h,
-                                    first, cx.sc);
-        else
-            sym_block<P, TPL, false>(src, s0, cnt, xt, yt, zt, wi, whi, acc, acch, tile, lane, cx.rev_u, cx.rev_h,
-                                     first, cx.sc);
+    if (bp.nb > 0) {
+        SrcRec<R> staged{};
+        stage_load<P>(bp, 0, Xs, Qs, Qhs, lane, staged);
+        for (int b = 0; b < bp.nb; ++b) {
+            int s0, cnt;
+            bp.range(b, s0, cnt);
+            wave_sync();
+            if (lane < kSymBlock) src[lane] = staged;
+            wave_sync();
+            if (b + 1 < bp.nb) stage_load<P>(bp, b + 1, Xs, Qs, Qhs, lane, staged);
+            if (b < bp.nbH)
+                sym_block<P, TPL, true, SELF>(src, s0, cnt, xt, yt, zt, wi, whi, acc, acch, tile, lane, cx.rev_u,
+                                              cx.rev_h, first, cx.sc);
+            else
+                sym_block<P, TPL, false, SELF>(src, s0, cnt, xt, yt, zt, wi, whi, acc, acch, tile, lane, cx.rev_u,
+                                               cx.rev_h, first, cx.sc);
+        }
     }
 #pragma unroll
     for (int p = 0; p < TPL; ++p) {
@@ -661,12 +688,21 @@ __device__ __forceinline__ void sym_pass(const SymCtx& cx, int tp, const Rec4<do
         if (t < cx.t1) {
             cx.fwd_u[t - cx.t0] = cx.sc * static_cast<double>(acc[p]);
             if (t < bi.k) cx.fwd_h[t - cx.t0] = -cx.sc * static_cast<double>(acch[p]);
+            // a self item's reverse row starts past the first diagonal tile; the
+            // first pass writes zeros before it so the whole row is defined
+            if (SELF && first) {
+                cx.rev_u[t] = 0.0;
+                if (t < bi.k) cx.rev_h[t] = 0.0;
+            }
         }
     }
 }
 
 // A pair item: passes of 64 TPL targets; a last pass of at most 64 targets runs
 // with one target per lane, so a ragged end wastes at most one wave's lanes.
+// A box paired with itself (bi == bj, one item over all its targets) evaluates
+// each unordered pair of distinct entries once, except inside the diagonal
+// tiles, which run in one direction with the zero distances masked.
 template <class P, int TPL>
 __device__ __forceinline__ void sym_item(const SymTask it, const BoxRec* __restrict__ box,
                                          const Rec4<double>* __restrict__ X, const typename P::Vt* __restrict__ Q,
@@ -689,9 +725,15 @@ __device__ __forceinline__ void sym_item(const SymTask it, const BoxRec* __restr
     const V* Qs = Q + cx.bj.voff;
     const V* Qhs = Qh + cx.bj.hoff;
     int tp = it.t0;
-    for (; it.t1 - tp > 64; tp += 64 * TPL)
-        sym_pass<P, TPL>(cx, tp, X, Q, Qh, Xs, Qs, Qhs, tile, src, lane);
-    if (tp < it.t1) sym_pass<P, 1>(cx, tp, X, Q, Qh, Xs, Qs, Qhs, tile, src, lane);
+    if (it.bi != it.bj) {
+        for (; it.t1 - tp > 64; tp += 64 * TPL)
+            sym_pass<P, TPL, false>(cx, tp, X, Q, Qh, Xs, Qs, Qhs, tile, src, lane);
+        if (tp < it.t1) sym_pass<P, 1, false>(cx, tp, X, Q, Qh, Xs, Qs, Qhs, tile, src, lane);
+    } else {
+        for (; it.t1 - tp > 64; tp += 64 * TPL)
+            sym_pass<P, TPL, true>(cx, tp, X, Q, Qh, Xs, Qs, Qhs, tile, src, lane);
+        if (tp < it.t1) sym_pass<P, 1, true>(cx, tp, X, Q, Qh, Xs, Qs, Qhs, tile, src, lane);
+    }
 }
 
 // Waves per SIMD the pair kernel is compiled for: the float32 evaluation fits

@@ -177,12 +177,15 @@ Layout make_layout(const Plan& p, bool keep_transparent, int tile) {
 // same kernel block, and so do two top-level boxes' direct segments, so every
 // such unordered pair {i, j} (i != j; ifo pairs of two uncompressed boxes are
 // already absent) becomes work items that evaluate G(B_i, B_j) once: lanes run
-// over targets of box i, groups of at most `group` targets per item.
+// over targets of box i, groups of at most `group` targets per item.  A box's
+// segment with itself becomes one item over all its targets that evaluates each
+// unordered pair of its entries once outside the diagonal tiles of its passes.
 //
 // Items write private slots laid out as dense rows per receiving box: for each
 // pair, one u row (and one uhat row) of box i that its groups fill by target
 // range, and per group one u row (and, when the group holds skeleton targets of
-// i, one uhat row) of box j.  The reduction adds a box's rows to its u and uhat
+// i, one uhat row) of box j; a box paired with itself has a forward and a
+// reverse row of each kind.  The reduction adds a box's rows to its u and uhat
 // in row order, so results stay deterministic.
 void make_symmetric(Layout& L, int group) {
     L.sym = true;
@@ -195,9 +198,13 @@ void make_symmetric(Layout& L, int group) {
             const int c = L.seg_src[x];
             const int mode = L.seg_mode[x];
             const int mt = mode & SEG_MODE_MASK;
-            if ((mt != SEG_IFO && mt != SEG_DIRECT) || c == b) {
+            if (mt != SEG_IFO && mt != SEG_DIRECT) {
                 rem[b].push_back(c);
                 remm[b].push_back(mode);
+                continue;
+            }
+            if (c == b) {   // a box with itself: one item over all its targets
+                if (L.nb[b] > 0) pairs_list.push_back(Pair{b, b});
                 continue;
             }
             if (c < b) continue;   // the pair was handled from the smaller id
@@ -219,6 +226,11 @@ void make_symmetric(Layout& L, int group) {
     std::vector<int32_t> ru(nb, 0), rh(nb, 0);
     for (const Pair& pr : pairs_list) {
         const int ni = L.nb[pr.bi], ki = L.kb[pr.bi], kj = L.kb[pr.bj];
+        if (pr.bi == pr.bj) {   // forward row and reverse row
+            ru[pr.bi] += 2;
+            if (ki > 0) rh[pr.bi] += 2;
+            continue;
+        }
         ru[pr.bi] += 1;
         if (ki > 0) rh[pr.bi] += 1;
         for (int t0 = 0; t0 < ni; t0 += group) {
@@ -240,10 +252,21 @@ void make_symmetric(Layout& L, int group) {
     // items, rows assigned in pair order
     std::vector<int32_t> nu(nb, 0), nh(nb, 0);
     std::vector<std::pair<int64_t, SymTask>> items;
-    int64_t npairs = 0, nskel = 0;
     for (const Pair& pr : pairs_list) {
         const int bi = pr.bi, bj = pr.bj;
         const int ni = L.nb[bi], nj = L.nb[bj], ki = L.kb[bi], kj = L.kb[bj];
+        if (bi == bj) {
+            SymTask st{bi, bi, 0, ni, base_u[bi] + int64_t(nu[bi]) * ni, -1, base_u[bi] + int64_t(nu[bi] + 1) * ni, -1};
+            nu[bi] += 2;
+            if (ki > 0) {
+                st.fwd_h = base_h[bi] + int64_t(nh[bi]) * ki;
+                st.rev_h = base_h[bi] + int64_t(nh[bi] + 1) * ki;
+                nh[bi] += 2;
+            }
+            // about half the block is evaluated; the reverse sums make it dearer per pair
+            items.push_back({int64_t(ni) * ni * 5 / 8, st});
+            continue;
+        }
         const int64_t row_u = base_u[bi] + int64_t(nu[bi]++) * ni;
         const int64_t row_h = ki > 0 ? base_h[bi] + int64_t(nh[bi]++) * ki : -1;
         for (int t0 = 0; t0 < ni; t0 += group) {
@@ -252,12 +275,8 @@ void make_symmetric(Layout& L, int group) {
             if (t0 < ki) st.fwd_h = row_h + t0;
             if (t0 < ki && kj > 0) st.rev_h = base_h[bj] + int64_t(nh[bj]++) * kj;
             items.push_back({int64_t(t1 - t0) * nj, st});
-            npairs += int64_t(t1 - t0) * nj;
-            nskel += int64_t(std::max(0, std::min(ki, t1) - t0)) * kj;
         }
     }
-    L.pairs_sym = npairs;
-    L.pairs_sym_skel = nskel;
     std::stable_sort(items.begin(), items.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
     L.sym_tasks.clear();
     for (auto& it : items) L.sym_tasks.push_back(it.second);
@@ -268,7 +287,8 @@ void make_symmetric(Layout& L, int group) {
     for (const SymTask& st : L.sym_tasks) {
         const int ni = L.nb[st.bi], nj = L.nb[st.bj], ki = L.kb[st.bi], kj = L.kb[st.bj];
         const bool hrow = st.t0 < ki, hrev = st.t0 < ki && kj > 0;
-        if (st.bi == st.bj || st.t0 < 0 || st.t1 > ni || st.t0 >= st.t1 || nj <= 0 ||
+        if ((st.bi == st.bj && (st.t0 != 0 || st.t1 != ni)) || st.t0 < 0 || st.t1 > ni || st.t0 >= st.t1 ||
+            nj <= 0 ||
             st.fwd_u < base_u[st.bi] || st.fwd_u + (st.t1 - st.t0) > base_u[st.bi] + int64_t(ru[st.bi]) * ni ||
             (hrow && (st.fwd_h < base_h[st.bi] ||
                       st.fwd_h + (std::min(ki, st.t1) - st.t0) > base_h[st.bi] + int64_t(rh[st.bi]) * ki)) ||
@@ -284,6 +304,33 @@ void make_symmetric(Layout& L, int group) {
         L.seg_src_ns.insert(L.seg_src_ns.end(), rem[b].begin(), rem[b].end());
         L.seg_mode_ns.insert(L.seg_mode_ns.end(), remm[b].begin(), remm[b].end());
         L.seg_ptr_ns[b + 1] = static_cast<int32_t>(L.seg_src_ns.size());
+    }
+}
+
+void sym_pair_counts(const Layout& L, int tpl, int64_t out[4]) {
+    out[0] = out[1] = out[2] = out[3] = 0;
+    for (const SymTask& st : L.sym_tasks) {
+        const int64_t ni = L.nb[st.bi], nj = L.nb[st.bj], ki = L.kb[st.bi], kj = L.kb[st.bj];
+        if (st.bi != st.bj) {
+            out[0] += int64_t(st.t1 - st.t0) * nj;
+            out[1] += std::max<int64_t>(0, std::min<int64_t>(ki, st.t1) - st.t0) * kj;
+            continue;
+        }
+        // passes of 64 tpl targets, a last one of at most 64; the diagonal tiles
+        // run in one direction, the rest of the block in both
+        int64_t d = 0, dk = 0;
+        for (int64_t tp = 0; tp < ni;) {
+            const int64_t w = ni - tp > 64 ? 64 * tpl : 64;
+            const int64_t e = std::min(ni, tp + w);
+            d += (e - tp) * (e - tp);
+            const int64_t ek = std::max<int64_t>(0, std::min(e, ki) - tp);
+            dk += ek * ek;
+            tp = e;
+        }
+        out[0] += (ni * ni - d) / 2;
+        out[1] += (ki * ki - dk) / 2;
+        out[2] += d;
+        out[3] += dk;
     }
 }
 
