@@ -102,7 +102,9 @@ typedef struct {
     int64_t pairs_tile;              /* one-direction evaluations in the diagonal tiles of a box
                                         paired with itself (for the current targets per lane) */
     int64_t pairs_tile_skel;         /* skeleton pairs inside them */
-    int32_t reserved[2];
+    int32_t n_sym_expanded;          /* pair items whose float32 evaluation expands |d|^2 about an
+                                        origin (the build's distance bound allows it) */
+    int32_t reserved[1];
 } skelfmm_stats;
 
 /* Read-only host view of the skeleton operators, valid while the operator lives.

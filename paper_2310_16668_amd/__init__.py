@@ -57,7 +57,8 @@ class Stats(ctypes.Structure):
                 ("pairs_near", ctypes.c_int64), ("pairs_skel", ctypes.c_int64), ("n_tasks", ctypes.c_int64),
                 ("tile_targets", ctypes.c_int32), ("n_sym_tasks", ctypes.c_int32), ("pairs_sym", ctypes.c_int64),
                 ("pairs_sym_skel", ctypes.c_int64), ("pairs_tile", ctypes.c_int64),
-                ("pairs_tile_skel", ctypes.c_int64), ("reserved", ctypes.c_int32 * 2)]
+                ("pairs_tile_skel", ctypes.c_int64), ("n_sym_expanded", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 1)]
 
 
 _P = ctypes.POINTER

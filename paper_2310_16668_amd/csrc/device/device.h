@@ -37,8 +37,11 @@ struct Task {
 struct SymTask {
     int32_t bi, bj;   // target-side box (lanes) and source-side box (wave-uniform)
     int32_t t0, t1;   // target entries [t0, t1) of bi
+    int32_t flags;    // SYM_EXPANDED: |d|^2 may be expanded about the item's origin
+    int32_t pad;
     int64_t fwd_u, fwd_h, rev_u, rev_h;
 };
+enum SymFlags : int32_t { SYM_EXPANDED = 1 };
 
 // The slot rows of one box: ru rows of n entries from base_u (added to u) and
 // rh rows of k entries from base_h (added to uhat).
@@ -62,6 +65,9 @@ struct Layout {
     // in [skeleton | redundant] order
     int64_t n_entries = 0, n_hentries = 0;
     std::vector<double> X;          // n_entries x 4 (x, y, z, 0), root-centred
+    // per box: lower bound of the distance between its entries and any other point,
+    // box centre (root-centred) and radius of its entries about it
+    std::vector<double> dmin, bcenter, brad;
     std::vector<int32_t> perm;      // user index of leaf entries, -1 elsewhere
     std::vector<int32_t> pmap;      // skeleton entry -> entry in the parent's vector
     std::vector<int32_t> gather_e, gather_p;     // leaf entries and their user indices

@@ -567,6 +567,8 @@ void device_fill_stats(const DeviceOp* d, skelfmm_stats* out) {
     out->pairs_sym_skel = pc[1];
     out->pairs_tile = pc[2];
     out->pairs_tile_skel = pc[3];
+    out->n_sym_expanded = 0;
+    for (const SymTask& st : d->L.sym_tasks) out->n_sym_expanded += (st.flags & SYM_EXPANDED) ? 1 : 0;
 }
 
 void device_destroy(DeviceOp* d) { delete d; }

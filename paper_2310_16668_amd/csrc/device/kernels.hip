@@ -90,12 +90,9 @@ struct Pol {
 // kernel times 4 pi), applied once at the end.  MASK: zero the pair at r = 0
 // (only needed where a box meets itself).  Real kernels return gr only.
 template <class P, bool CONJ, bool MASK>
-__device__ __forceinline__ void green(double dx, double dy, double dz, typename P::Rt kappa,
-                                      typename P::Rt& gr, typename P::Rt& gi) {
+__device__ __forceinline__ void green_r2(double r2d, typename P::Rt kappa, typename P::Rt& gr,
+                                         typename P::Rt& gi) {
     using R = typename P::Rt;
-    double r2d = dx * dx;
-    r2d = fma(dy, dy, r2d);
-    if constexpr (P::dim == 3) r2d = fma(dz, dz, r2d);
     const R r2 = static_cast<R>(r2d);
     R ir;
     if constexpr (sizeof(R) == 8) ir = (P::twice) ? two_inv_r(r2) : inv_r(r2);
@@ -111,6 +108,15 @@ __device__ __forceinline__ void green(double dx, double dy, double dz, typename 
         gr = c * ir;
         gi = CONJ ? -s * ir : s * ir;
     }
+}
+
+template <class P, bool CONJ, bool MASK>
+__device__ __forceinline__ void green(double dx, double dy, double dz, typename P::Rt kappa,
+                                      typename P::Rt& gr, typename P::Rt& gi) {
+    double r2d = dx * dx;
+    r2d = fma(dy, dy, r2d);
+    if constexpr (P::dim == 3) r2d = fma(dz, dz, r2d);
+    green_r2<P, CONJ, MASK>(r2d, kappa, gr, gi);
 }
 
 // Per-box record read with one scalar load.
@@ -492,9 +498,26 @@ __device__ __forceinline__ B column_sum(const B (&r)[kSymBlock], B* tile, int la
 }
 
 // One source of a block, staged in the wave's LDS area.
+// A block's sources staged in the wave's LDS area: positions and charges in
+// separate arrays, so a source costs two 16-byte reads and one charge read.
+// Exact form: (x, y, z) = the source's coordinates.  Expanded form (see
+// sym_pass): (x, y, z) = -2 (x_s - o) and n = |x_s - o|^2 for the item's origin o.
+struct alignas(32) SrcPos {
+    double x, y, z, n;
+};
 template <typename R>
-struct alignas(16) SrcRec {
-    double x, y, z;
+struct alignas(2 * sizeof(R)) SrcW {
+    R w, wh;
+};
+template <typename R>
+struct SrcStage {
+    SrcPos p[kSymBlock];
+    SrcW<R> w[kSymBlock];
+};
+// one lane's staged source (registers)
+template <typename R>
+struct SrcRec {
+    double x, y, z, n;
     R w, wh;
 };
 
@@ -506,10 +529,11 @@ struct alignas(16) SrcRec {
 // sums are not stored), so the block is branch-free.  Reverse sums go to
 // rev_u[s] (and rev_h[s]), stored on the item's first pass and accumulated on
 // later ones.
-template <class P, int TPL, bool H, bool MASK>
-__device__ __forceinline__ void sym_block(const SrcRec<typename P::Rt>* src, int s0, int cnt,
+template <class P, int TPL, bool H, bool MASK, bool FAST>
+__device__ __forceinline__ void sym_block(const SrcStage<typename P::Rt>* src, int s0, int cnt,
                                           const double (&xt)[TPL], const double (&yt)[TPL],
-                                          const double (&zt)[TPL], const typename P::Rt (&wi)[TPL],
+                                          const double (&zt)[TPL], const double (&nt)[TPL],
+                                          const typename P::Rt (&wi)[TPL],
                                           const typename P::Rt (&whi)[TPL], typename P::At (&acc)[TPL],
                                           typename P::At (&acch)[TPL], typename P::Rt* tile, int lane,
                                           double* __restrict__ rev_u, double* __restrict__ rev_h, bool first,
@@ -531,17 +555,26 @@ __device__ __forceinline__ void sym_block(const SrcRec<typename P::Rt>* src, int
     for (int p = 0; p < TPL; ++p) { bacc[p] = R(0); bh[p] = R(0); }
 #pragma unroll
     for (int c = 0; c < kSymBlock; ++c) {
-        const SrcRec<R> sv = src[c];
+        const SrcPos sv = src->p[c];
+        const R svw = src->w[c].w;
+        R svwh = R(0);
+        if constexpr (H) svwh = src->w[c].wh;
         ru[c] = R(0);
         rh[c] = R(0);
 #pragma unroll
         for (int p = 0; p < TPL; ++p) {
             R g, gi;
-            green<P, false, MASK>(xt[p] - sv.x, yt[p] - sv.y, zt[p] - sv.z, R(0), g, gi);
-            bacc[p] = fma(g, sv.w, bacc[p]);
+            if constexpr (FAST) {
+                // |t - s|^2 = |t'|^2 + |s'|^2 - 2 t'.s' relative to the item's origin
+                const double r2 = fma(xt[p], sv.x, fma(yt[p], sv.y, fma(zt[p], sv.z, nt[p] + sv.n)));
+                green_r2<P, false, MASK>(r2, R(0), g, gi);
+            } else {
+                green<P, false, MASK>(xt[p] - sv.x, yt[p] - sv.y, zt[p] - sv.z, R(0), g, gi);
+            }
+            bacc[p] = fma(g, svw, bacc[p]);
             ru[c] = fma(g, wi[p], ru[c]);
             if constexpr (H) {
-                bh[p] = fma(g, sv.wh, bh[p]);
+                bh[p] = fma(g, svwh, bh[p]);
                 rh[c] = fma(g, whi[p], rh[c]);
             }
         }
@@ -581,10 +614,10 @@ struct BlockPlan {
 
 // Lanes 0..15 fetch the sources of block b from global memory into registers
 // (lanes past the block's count repeat its last source with zero charges).
-template <class P>
+template <class P, bool FAST>
 __device__ __forceinline__ void stage_load(const BlockPlan& bp, int b, const Rec4<double>* __restrict__ Xs,
                                            const typename P::Vt* __restrict__ Qs,
-                                           const typename P::Vt* __restrict__ Qhs, int lane,
+                                           const typename P::Vt* __restrict__ Qhs, int lane, const double (&o)[3],
                                            SrcRec<typename P::Rt>& r) {
     using R = typename P::Rt;
     int s0, cnt;
@@ -592,9 +625,18 @@ __device__ __forceinline__ void stage_load(const BlockPlan& bp, int b, const Rec
     if (lane < kSymBlock) {
         const int si = s0 + min(lane, cnt - 1);
         const Rec4<double> x = Xs[si];
-        r.x = x.x;
-        r.y = x.y;
-        r.z = x.z;
+        if constexpr (FAST) {
+            const double dx = x.x - o[0], dy = x.y - o[1], dz = x.z - o[2];
+            r.x = -2.0 * dx;
+            r.y = -2.0 * dy;
+            r.z = -2.0 * dz;
+            r.n = fma(dx, dx, fma(dy, dy, dz * dz));
+        } else {
+            r.x = x.x;
+            r.y = x.y;
+            r.z = x.z;
+            r.n = 0.0;
+        }
         r.w = lane < cnt ? static_cast<R>(Qs[si]) : R(0);
         r.wh = (lane < cnt && b < bp.nbH) ? static_cast<R>(Qhs[si]) : R(0);
     }
@@ -613,13 +655,13 @@ struct SymCtx {
 
 // One pass: targets tp .. tp + 64 TPL - 1 of box i (those below t1) against all
 // sources of box j.
-template <class P, int TPL, bool SELF>
+template <class P, int TPL, bool SELF, bool FAST>
 __device__ __forceinline__ void sym_pass(const SymCtx& cx, int tp, const Rec4<double>* __restrict__ X,
                                          const typename P::Vt* __restrict__ Q,
                                          const typename P::Vt* __restrict__ Qh,
                                          const Rec4<double>* __restrict__ Xs, const typename P::Vt* __restrict__ Qs,
                                          const typename P::Vt* __restrict__ Qhs, typename P::Rt* tile,
-                                         SrcRec<typename P::Rt>* src, int lane) {
+                                         SrcStage<typename P::Rt>* src, int lane) {
     using R = typename P::Rt;
     using A = typename P::At;
     const BoxRec& bi = cx.bi;
@@ -633,16 +675,23 @@ __device__ __forceinline__ void sym_pass(const SymCtx& cx, int tp, const Rec4<do
     const int tile_end = SELF ? min(tp + 64 * TPL, cx.t1) : 0;
     BlockPlan bp;
     bp.init(tile_end, hp ? bj.k : 0, bj.n);
-    double xt[TPL], yt[TPL], zt[TPL];
+    double xt[TPL], yt[TPL], zt[TPL], nt[TPL];
     R wi[TPL], whi[TPL];
     A acc[TPL], acch[TPL];
+    // expanded form: coordinates relative to the item's origin (the first entry of box i)
+    double o[3] = {0.0, 0.0, 0.0};
+    if constexpr (FAST) {
+        const Rec4<double> x0 = X[bi.voff];
+        o[0] = x0.x; o[1] = x0.y; o[2] = x0.z;
+    }
 #pragma unroll
     for (int p = 0; p < TPL; ++p) {
         const int t = tp + lane + 64 * p;
         const bool ok = t < cx.t1;
         const int tc = ok ? t : cx.t1 - 1;
         const Rec4<double> x = X[bi.voff + tc];
-        xt[p] = x.x; yt[p] = x.y; zt[p] = x.z;
+        xt[p] = x.x - o[0]; yt[p] = x.y - o[1]; zt[p] = x.z - o[2];
+        nt[p] = fma(xt[p], xt[p], fma(yt[p], yt[p], zt[p] * zt[p]));
         wi[p] = ok ? static_cast<R>(Q[bi.voff + tc]) : R(0);
         whi[p] = (ok && t < bi.k) ? static_cast<R>(Qh[bi.hoff + t]) : R(0);
         acc[p] = A(0);
@@ -666,20 +715,23 @@ __device__ __forceinline__ void sym_pass(const SymCtx& cx, int tp, const Rec4<do
     // the next block's sources are fetched while the current one is evaluated
     if (bp.nb > 0) {
         SrcRec<R> staged{};
-        stage_load<P>(bp, 0, Xs, Qs, Qhs, lane, staged);
+        stage_load<P, FAST>(bp, 0, Xs, Qs, Qhs, lane, o, staged);
         for (int b = 0; b < bp.nb; ++b) {
             int s0, cnt;
             bp.range(b, s0, cnt);
             wave_sync();
-            if (lane < kSymBlock) src[lane] = staged;
+            if (lane < kSymBlock) {
+                src->p[lane] = SrcPos{staged.x, staged.y, staged.z, staged.n};
+                src->w[lane] = SrcW<R>{staged.w, staged.wh};
+            }
             wave_sync();
-            if (b + 1 < bp.nb) stage_load<P>(bp, b + 1, Xs, Qs, Qhs, lane, staged);
+            if (b + 1 < bp.nb) stage_load<P, FAST>(bp, b + 1, Xs, Qs, Qhs, lane, o, staged);
             if (b < bp.nbH)
-                sym_block<P, TPL, true, SELF>(src, s0, cnt, xt, yt, zt, wi, whi, acc, acch, tile, lane, cx.rev_u,
-                                              cx.rev_h, first, cx.sc);
+                sym_block<P, TPL, true, SELF, FAST>(src, s0, cnt, xt, yt, zt, nt, wi, whi, acc, acch, tile, lane,
+                                                    cx.rev_u, cx.rev_h, first, cx.sc);
             else
-                sym_block<P, TPL, false, SELF>(src, s0, cnt, xt, yt, zt, wi, whi, acc, acch, tile, lane, cx.rev_u,
-                                               cx.rev_h, first, cx.sc);
+                sym_block<P, TPL, false, SELF, FAST>(src, s0, cnt, xt, yt, zt, nt, wi, whi, acc, acch, tile, lane,
+                                                     cx.rev_u, cx.rev_h, first, cx.sc);
         }
     }
 #pragma unroll
@@ -707,7 +759,7 @@ template <class P, int TPL>
 __device__ __forceinline__ void sym_item(const SymTask it, const BoxRec* __restrict__ box,
                                          const Rec4<double>* __restrict__ X, const typename P::Vt* __restrict__ Q,
                                          const typename P::Vt* __restrict__ Qh, double* __restrict__ slots,
-                                         double scale, typename P::Rt* tile, SrcRec<typename P::Rt>* src,
+                                         double scale, typename P::Rt* tile, SrcStage<typename P::Rt>* src,
                                          int lane) {
     using V = typename P::Vt;
     SymCtx cx;
@@ -725,14 +777,19 @@ __device__ __forceinline__ void sym_item(const SymTask it, const BoxRec* __restr
     const V* Qs = Q + cx.bj.voff;
     const V* Qhs = Qh + cx.bj.hoff;
     int tp = it.t0;
-    if (it.bi != it.bj) {
+    // the expanded |d|^2 serves the float32 evaluation of items the build marked safe for it
+    if (sizeof(typename P::Rt) == 4 && (it.flags & SYM_EXPANDED)) {
         for (; it.t1 - tp > 64; tp += 64 * TPL)
-            sym_pass<P, TPL, false>(cx, tp, X, Q, Qh, Xs, Qs, Qhs, tile, src, lane);
-        if (tp < it.t1) sym_pass<P, 1, false>(cx, tp, X, Q, Qh, Xs, Qs, Qhs, tile, src, lane);
+            sym_pass<P, TPL, false, true>(cx, tp, X, Q, Qh, Xs, Qs, Qhs, tile, src, lane);
+        if (tp < it.t1) sym_pass<P, 1, false, true>(cx, tp, X, Q, Qh, Xs, Qs, Qhs, tile, src, lane);
+    } else if (it.bi != it.bj) {
+        for (; it.t1 - tp > 64; tp += 64 * TPL)
+            sym_pass<P, TPL, false, false>(cx, tp, X, Q, Qh, Xs, Qs, Qhs, tile, src, lane);
+        if (tp < it.t1) sym_pass<P, 1, false, false>(cx, tp, X, Q, Qh, Xs, Qs, Qhs, tile, src, lane);
     } else {
         for (; it.t1 - tp > 64; tp += 64 * TPL)
-            sym_pass<P, TPL, true>(cx, tp, X, Q, Qh, Xs, Qs, Qhs, tile, src, lane);
-        if (tp < it.t1) sym_pass<P, 1, true>(cx, tp, X, Q, Qh, Xs, Qs, Qhs, tile, src, lane);
+            sym_pass<P, TPL, true, false>(cx, tp, X, Q, Qh, Xs, Qs, Qhs, tile, src, lane);
+        if (tp < it.t1) sym_pass<P, 1, true, false>(cx, tp, X, Q, Qh, Xs, Qs, Qhs, tile, src, lane);
     }
 }
 
@@ -750,12 +807,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sym_wa
                                                   double* __restrict__ slots, double scale) {
     using R = typename P::Rt;
     __shared__ R tiles[4][kSymBlock * kSymRow];
-    __shared__ SrcRec<R> srcs[4][kSymBlock];
+    __shared__ SrcStage<R> srcs[4];
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int tid = blockIdx.x * 4 + wv;
     if (tid >= ntasks) return;
-    sym_item<P, TPL>(tasks[tid], box, X, Q, Qh, slots, scale, tiles[wv], srcs[wv], lane);
+    sym_item<P, TPL>(tasks[tid], box, X, Q, Qh, slots, scale, tiles[wv], &srcs[wv], lane);
 }
 
 // acc + p[0] + p[ld] + ... + p[(rows - 1) ld], added in row order; the loads of

@@ -24,13 +24,101 @@
 // target and a tfo pair with a transparent source.
 #include <algorithm>
 #include <cmath>
+#include <limits>
 #include <tuple>
 #include <numeric>
 #include <stdexcept>
 
 #include "device.h"
+#include "../host/parallel.h"
 
 namespace skelfmm {
+
+// Geometry for the expanded |d|^2 of the pair kernel.  With coordinates taken
+// relative to an origin o, |t - s|^2 = |t'|^2 + |s'|^2 - 2 t'.s' evaluated in
+// float64 has an absolute error below 20 u R^2 (u = 2^-53, R bounding |t'| and
+// |s'|), i.e. a relative error below 20 u (R / d)^2 for a pair at distance
+// >= d.  For R <= 1024 d that is below 2.4e-9, far under the float32 rounding
+// that follows; the build marks an item expanded only then, with d a lower
+// bound of the distance between any two distinct entries of its boxes.
+//
+// Lower bound of the nearest-neighbor distance of every point: a leaf's points
+// are compared with the points of the leaf itself, its colleague leaves, its
+// coarse and its fine neighbor leaves; any other point lies at least half the
+// leaf's side away (under strong balance every box touching a leaf is at most
+// one level finer, and those are leaves on its fine list).
+static void box_geometry(const Plan& p, Layout& L) {
+    const int nb = p.n_boxes;
+    const int dim = p.dim;
+    std::vector<double> nn(static_cast<size_t>(p.n), std::numeric_limits<double>::infinity());
+    std::vector<int32_t> leaves;
+    for (int b = 0; b < nb; ++b)
+        if (p.is_leaf[b] && p.idx_ptr[b + 1] > p.idx_ptr[b]) leaves.push_back(b);
+    auto dist2 = [&](int64_t a, int64_t c) {
+        double s2 = 0.0;
+        for (int d = 0; d < dim; ++d) {
+            const double t = p.pts[a * dim + d] - p.pts[c * dim + d];
+            s2 += t * t;
+        }
+        return s2;
+    };
+    parallel_for(static_cast<int64_t>(leaves.size()), host_threads(p.opt.num_threads), [&](int64_t li) {
+        const int b = leaves[li];
+        const double half = 0.5 * std::ldexp(p.root_side, -p.level[b]);
+        std::vector<int32_t> cand;
+        for (int x = p.coll_ptr[b]; x < p.coll_ptr[b + 1]; ++x)
+            if (p.is_leaf[p.coll_idx[x]]) cand.push_back(p.coll_idx[x]);
+        for (int x = p.coarse_ptr[b]; x < p.coarse_ptr[b + 1]; ++x) cand.push_back(p.coarse_idx[x]);
+        for (int x = p.fine_ptr[b]; x < p.fine_ptr[b + 1]; ++x) cand.push_back(p.fine_idx[x]);
+        for (int64_t i = p.idx_ptr[b]; i < p.idx_ptr[b + 1]; ++i) {
+            const int64_t a = p.idx[i];
+            double m = half * half;
+            for (int c : cand)
+                for (int64_t j = p.idx_ptr[c]; j < p.idx_ptr[c + 1]; ++j)
+                    if (p.idx[j] != a) m = std::min(m, dist2(a, p.idx[j]));
+            nn[a] = std::sqrt(m);
+        }
+    }, 16);
+    L.dmin.assign(nb, 0.0);
+    L.bcenter.assign(static_cast<size_t>(nb) * 3, 0.0);
+    L.brad.assign(nb, 0.0);
+    for (int b = 0; b < nb; ++b) {
+        const double side = std::ldexp(p.root_side, -p.level[b]);
+        double c[3] = {0, 0, 0};
+        for (int d = 0; d < dim; ++d) c[d] = p.root_lo[d] + (p.coord[3 * b + d] + 0.5) * side - L.center[d];
+        double dm = std::numeric_limits<double>::infinity(), r2 = 0.0;
+        for (int64_t i = p.idx_ptr[b]; i < p.idx_ptr[b + 1]; ++i) {
+            const int64_t a = p.idx[i];
+            dm = std::min(dm, nn[a]);
+            double s2 = 0.0;
+            for (int d = 0; d < dim; ++d) {
+                const double t = (p.pts[a * dim + d] - L.center[d]) - c[d];
+                s2 += t * t;
+            }
+            r2 = std::max(r2, s2);
+        }
+        L.dmin[b] = dm;
+        for (int d = 0; d < 3; ++d) L.bcenter[3 * b + d] = c[d];
+        L.brad[b] = std::sqrt(r2);
+    }
+}
+
+// An item of boxes i != j may use the expanded |d|^2 (origin: the first entry of i).
+static bool expanded_ok(const Layout& L, int bi, int bj) {
+    if (L.nb[bi] == 0 || L.dmin.empty()) return false;
+    const double* o = &L.X[static_cast<size_t>(L.voff[bi]) * 4];
+    auto reach = [&](int b) {
+        double s2 = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            const double t = L.bcenter[3 * b + d] - o[d];
+            s2 += t * t;
+        }
+        return std::sqrt(s2) + L.brad[b];
+    };
+    const double R = std::max(reach(bi), reach(bj));
+    const double d = std::min(L.dmin[bi], L.dmin[bj]);
+    return d > 0.0 && R <= 1024.0 * d;
+}
 
 Layout make_layout(const Plan& p, bool keep_transparent, int tile) {
     Layout L;
@@ -154,6 +242,7 @@ Layout make_layout(const Plan& p, bool keep_transparent, int tile) {
     }
 
     pad_transfer_offsets(L);
+    box_geometry(p, L);
 
     // work list and pair counts
     L.tasks = make_tasks(L, tile);
@@ -256,7 +345,8 @@ void make_symmetric(Layout& L, int group) {
         const int bi = pr.bi, bj = pr.bj;
         const int ni = L.nb[bi], nj = L.nb[bj], ki = L.kb[bi], kj = L.kb[bj];
         if (bi == bj) {
-            SymTask st{bi, bi, 0, ni, base_u[bi] + int64_t(nu[bi]) * ni, -1, base_u[bi] + int64_t(nu[bi] + 1) * ni, -1};
+            SymTask st{bi, bi, 0, ni, 0, 0, base_u[bi] + int64_t(nu[bi]) * ni, -1,
+                       base_u[bi] + int64_t(nu[bi] + 1) * ni, -1};
             nu[bi] += 2;
             if (ki > 0) {
                 st.fwd_h = base_h[bi] + int64_t(nh[bi]) * ki;
@@ -271,7 +361,8 @@ void make_symmetric(Layout& L, int group) {
         const int64_t row_h = ki > 0 ? base_h[bi] + int64_t(nh[bi]++) * ki : -1;
         for (int t0 = 0; t0 < ni; t0 += group) {
             const int t1 = std::min(ni, t0 + group);
-            SymTask st{bi, bj, t0, t1, row_u + t0, -1, base_u[bj] + int64_t(nu[bj]++) * nj, -1};
+            SymTask st{bi, bj, t0, t1, expanded_ok(L, bi, bj) ? SYM_EXPANDED : 0, 0, row_u + t0, -1,
+                       base_u[bj] + int64_t(nu[bj]++) * nj, -1};
             if (t0 < ki) st.fwd_h = row_h + t0;
             if (t0 < ki && kj > 0) st.rev_h = base_h[bj] + int64_t(nh[bj]++) * kj;
             items.push_back({int64_t(t1 - t0) * nj, st});
@@ -384,6 +475,7 @@ Layout merge_layouts(const std::vector<const Layout*>& ls, std::vector<int64_t>&
         for (int l = 0; l <= M.max_level; ++l) M.level_ptr[l + 1] += M.level_ptr[l];
     }
     M.voff.resize(M.n_boxes); M.hoff.resize(M.n_boxes); M.toff.resize(M.n_boxes);
+    M.dmin.resize(M.n_boxes); M.brad.resize(M.n_boxes); M.bcenter.resize(static_cast<size_t>(M.n_boxes) * 3);
     M.nb.resize(M.n_boxes); M.kb.resize(M.n_boxes); M.level.resize(M.n_boxes);
     M.parent.resize(M.n_boxes); M.is_leaf.resize(M.n_boxes);
     M.seg_ptr.assign(M.n_boxes + 1, 0);
@@ -395,6 +487,10 @@ Layout merge_layouts(const std::vector<const Layout*>& ls, std::vector<int64_t>&
         M.toff[g] = L.toff[b] + tbase[i];
         M.nb[g] = L.nb[b];
         M.kb[g] = L.kb[b];
+        M.dmin[g] = L.dmin.empty() ? 0.0 : L.dmin[b];
+        M.brad[g] = L.brad.empty() ? 0.0 : L.brad[b];
+        // centres stay in the operator's own frame, like its entry coordinates
+        for (int d = 0; d < 3; ++d) M.bcenter[3 * g + d] = L.bcenter.empty() ? 0.0 : L.bcenter[3 * b + d];
         M.level[g] = L.level[b];
         M.parent[g] = L.parent[b] < 0 ? -1 : newid[i][L.parent[b]];
         M.is_leaf[g] = L.is_leaf[b];

@@ -61,6 +61,10 @@ def test_cube_1m_f64_and_f32(cube_1m):
         say(w.name, dt, "vs O1", e1, "vs O2 (sampled leaves)", e2)
         assert e1 <= 1e-6
         if dt == torch.float64:
+            e64 = e1
+        else:
+            assert e1 <= 1.5 * e64 + 1e-7
+        if dt == torch.float64:
             assert e2 <= 1e-12
     # the adjoint (Laplace: Atilde^T = Atilde) on the benchmark's second input
     v = w.weights()
@@ -83,9 +87,13 @@ def test_ellipsoid_4m_f32():
     u1 = oracle.direct(x, q, targets=tg)
     u = op.apply(torch.from_numpy(q).to("cuda:0", torch.float32)).double().cpu().numpy()
     e1 = relerr(u[tg], u1)
-    say(w.name, "f32 vs O1", e1)
-    assert e1 <= 10 * w.tol
     ud = op.apply(torch.from_numpy(q).to("cuda:0", torch.float64)).cpu().numpy()
+    ed = relerr(ud[tg], u1)
+    say(w.name, "f32 vs O1", e1, "f64 vs O1", ed, "expanded items", st["n_sym_expanded"], "of", st["n_sym_tasks"])
+    assert e1 <= 10 * w.tol
+    # the float32 evaluation (expanded |d|^2 where the build allows it) adds
+    # little to the skeleton approximation error on this clustered surface
+    assert e1 <= 1.5 * ed + 1e-7
     pts, u2 = sampled_o2(op, q, n_leaves=4)
     e2 = relerr(ud[pts], u2)
     say(w.name, "f64 vs O2 (sampled leaves)", e2)
