@@ -48,8 +48,8 @@ FLOPS_PER_SYM_SKEL_PAIR = 4
 # workload (scaled by a plain 512 MiB copy: x2.000 fetch, x1.000 write), valid only for
 # the kernel, targets-per-lane variant and kernel source they were measured on (first
 # 16 hex digits of the source's sha256).
-NEAR_TRAFFIC = {"f32": {"kernel": "k_near_sym", "targets_per_lane": 4, "kernels_sha256": "707a54e4768dfec5",
-                         "bytes": 1.5905e9 + 0.6966e9}}
+NEAR_TRAFFIC = {"f32": {"kernel": "k_near_sym", "targets_per_lane": 3, "kernels_sha256": "cc5494f47e3da477",
+                         "bytes": 2.8428e9 + 1.0499e9}}
 
 
 def log(*a):
@@ -118,7 +118,7 @@ def cpu_baseline(P, q, v, budget_s: float, nrhs: int = 1):
     t0 = time.perf_counter()
     oracle.apply(P, q, box_mask=mask0)
     t_base = time.perf_counter() - t0
-    frac = 2e-3
+    frac = 5e-2
     mask = (rng.random(P["n_boxes"]) < frac).astype(np.uint8)
     t0 = time.perf_counter()
     oracle.apply(P, q, box_mask=mask)
