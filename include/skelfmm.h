@@ -81,7 +81,10 @@ typedef struct {
     int32_t nonsymmetric;    /* 1: evaluate both orders of every colleague pair separately (default 0:
                                 for the real Laplace kernels one evaluation of G(B_i, B_j) serves
                                 the ifo terms i <- j and j <- i; single-RHS applies only) */
-    int32_t reserved[7];
+    int32_t no_expansion;    /* 1: the float32 pair kernel always forms |d|^2 from coordinate
+                                differences (default 0: pairs whose distance bound allows it use
+                                the expanded form |t'|^2 + |s'|^2 - 2 t'.s', see skelfmm_stats) */
+    int32_t reserved[6];
 } skelfmm_options;
 
 /* Build-time and layout statistics (section 5 / table "Notation for reported results"). */

@@ -46,7 +46,8 @@ class Options(ctypes.Structure):
     _fields_ = [("proxy_shape", ctypes.c_int32), ("proxy_points", ctypes.c_int32),
                 ("proxy_scale", ctypes.c_double), ("no_compression", ctypes.c_int32),
                 ("num_threads", ctypes.c_int32), ("keep_transparent", ctypes.c_int32),
-                ("f64_leaf", ctypes.c_int32), ("nonsymmetric", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+                ("f64_leaf", ctypes.c_int32), ("nonsymmetric", ctypes.c_int32), ("no_expansion", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
 
 
 class Stats(ctypes.Structure):
@@ -248,11 +249,12 @@ class Operator:
 def build(points, kind: str = "laplace", tol: float = 1e-6, leaf_size: int = 64, kappa: float = 0.0,
           proxy_shape: int = 0, proxy_points: int = 0, proxy_scale: float = 0.0, no_compression: bool = False,
           num_threads: int = 0, keep_transparent: bool = False, f64_leaf: bool = False,
-          symmetric: bool = True) -> Operator:
+          symmetric: bool = True, expansion: bool = True) -> Operator:
     """Build the skeleton operator for ``points`` (n x dim, host, float64).
 
     ``symmetric=False`` evaluates both orders of every colleague pair separately
-    (the pairing applies to the real Laplace kernels with one right-hand side)."""
+    (the pairing applies to the real Laplace kernels with one right-hand side);
+    ``expansion=False`` keeps the float32 pair kernel on coordinate differences."""
     pts = np.ascontiguousarray(points, dtype=np.float64)
     if pts.ndim != 2:
         raise ValueError("points must be n x dim")
@@ -263,6 +265,7 @@ def build(points, kind: str = "laplace", tol: float = 1e-6, leaf_size: int = 64,
     o.no_compression, o.num_threads = int(no_compression), num_threads
     o.keep_transparent, o.f64_leaf = int(keep_transparent), int(f64_leaf)
     o.nonsymmetric = int(not symmetric)
+    o.no_expansion = int(not expansion)
     h = _vp()
     _check(_lib.skelfmm_build(pts.ctypes.data_as(_P(ctypes.c_double)), n, k, tol, leaf_size,
                               ctypes.byref(o), ctypes.byref(h)))

@@ -116,7 +116,7 @@ skelfmm_status skelfmm_build(const double* points, int64_t n, skelfmm_kernel ker
             if (p.opt.proxy_shape == 2 && p.dim == 3) throw std::invalid_argument("the proxy circle is 2D only");
             skelfmm::build_plan(p);
             op->dev = skelfmm::device_create(p, op->opt.keep_transparent != 0, op->opt.f64_leaf != 0,
-                                             op->opt.nonsymmetric == 0);
+                                             op->opt.nonsymmetric == 0, op->opt.no_expansion == 0);
         } catch (...) {
             delete op;
             throw;

@@ -87,6 +87,7 @@ struct Layout {
     // symmetric pairs (real kernels, one RHS): the colleague pairs they cover are
     // removed from the *_ns segment lists, which serve the one-RHS near field
     bool sym = false;
+    bool allow_expanded = true;     // pair items may use the expanded |d|^2 where the bound allows
     std::vector<int32_t> seg_ptr_ns, seg_src_ns, seg_mode_ns;
     std::vector<SymTask> sym_tasks;
     std::vector<SymRows> sym_rows;               // boxes receiving slot rows
@@ -116,7 +117,7 @@ Layout merge_layouts(const std::vector<const Layout*>& ls, std::vector<int64_t>&
 struct DeviceOp;
 struct DeviceBatch;
 
-DeviceOp* device_create(const Plan& p, bool keep_transparent, bool f64_leaf, bool symmetric);
+DeviceOp* device_create(const Plan& p, bool keep_transparent, bool f64_leaf, bool symmetric, bool expanded);
 void device_prepare(DeviceOp* d, int64_t nrhs_max, int dtype);
 void device_apply(DeviceOp* d, const void* q, void* u, int64_t nrhs, int dtype, void* stream, bool adjoint);
 void device_fill_stats(const DeviceOp* d, skelfmm_stats* out);

@@ -142,9 +142,10 @@ static void check_ranks(const Layout& L) {
 // for every tpl in 1 .. 4).
 constexpr int kSymGroup = 768;
 
-DeviceOp* device_create(const Plan& p, bool keep_transparent, bool f64_leaf, bool symmetric) {
+DeviceOp* device_create(const Plan& p, bool keep_transparent, bool f64_leaf, bool symmetric, bool expanded) {
     auto d = std::make_unique<DeviceOp>();
     d->L = make_layout(p, keep_transparent, 64 * kDefaultTPL);
+    d->L.allow_expanded = expanded;
     // the pairing needs G(x, y) = G(y, x) with real values
     if (symmetric && p.kind == 0) make_symmetric(d->L, kSymGroup);
     d->f64_leaf = f64_leaf;
@@ -610,7 +611,9 @@ DeviceBatch* batch_create(const std::vector<DeviceOp*>& ops) {
     b->merged = std::make_unique<DeviceOp>();
     b->merged->L = merge_layouts(ls, ebase);
     for (auto* o : ops)
-        if (o->L.sym != ops[0]->L.sym) throw std::invalid_argument("batched operators must share the pairing option");
+        if (o->L.sym != ops[0]->L.sym || o->L.allow_expanded != ops[0]->L.allow_expanded)
+            throw std::invalid_argument("batched operators must share the pairing options");
+    b->merged->L.allow_expanded = ops[0]->L.allow_expanded;
     if (ops[0]->L.sym) make_symmetric(b->merged->L, kSymGroup);
     b->merged->f64_leaf = ops[0]->f64_leaf;
     check_ranks(b->merged->L);

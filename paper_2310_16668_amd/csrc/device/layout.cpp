@@ -361,7 +361,7 @@ void make_symmetric(Layout& L, int group) {
         const int64_t row_h = ki > 0 ? base_h[bi] + int64_t(nh[bi]++) * ki : -1;
         for (int t0 = 0; t0 < ni; t0 += group) {
             const int t1 = std::min(ni, t0 + group);
-            SymTask st{bi, bj, t0, t1, expanded_ok(L, bi, bj) ? SYM_EXPANDED : 0, 0, row_u + t0, -1,
+            SymTask st{bi, bj, t0, t1, (L.allow_expanded && expanded_ok(L, bi, bj)) ? SYM_EXPANDED : 0, 0, row_u + t0, -1,
                        base_u[bj] + int64_t(nu[bj]++) * nj, -1};
             if (t0 < ki) st.fwd_h = row_h + t0;
             if (t0 < ki && kj > 0) st.rev_h = base_h[bj] + int64_t(nh[bj]++) * kj;
