@@ -80,12 +80,19 @@ constexpr int kChunkReals = 8;   // right-hand-side reals per multi-RHS near-fie
 
 int tpl_slot(int tpl) { return tpl - 1; }
 
+// Several right-hand sides of a real kernel in the float32 policy run the near
+// field on the matrix cores (k_near_mfma) from 8 columns on.
+constexpr int kMfmaMinRhs = 8;
+constexpr int kMfmaCols = 32;     // columns per accumulator tile
+
 // Values per entry inside the workspace: nv for one RHS; several RHS are padded
-// to a multiple of the near-field chunk.
-int64_t padded_width(int64_t nrhs, int dtype) {
+// to a multiple of the near-field chunk (of the accumulator tile on the matrix
+// core path).
+int64_t padded_width(int64_t nrhs, int dtype, bool mfma) {
     const int64_t w = nrhs * (dtype_is_complex(dtype) ? 2 : 1);
     if (nrhs == 1) return w;
-    return (w + kChunkReals - 1) / kChunkReals * kChunkReals;
+    const int64_t m = mfma ? kMfmaCols : kChunkReals;
+    return (w + m - 1) / m * m;
 }
 
 inline unsigned blocks_for(int64_t n, int bs) { return static_cast<unsigned>((n + bs - 1) / bs); }
@@ -112,6 +119,8 @@ struct DeviceOp {
     // terms, their work lists, the pair items, the slot reduction lists
     DevMem seg_ptr_ns, segs_ns, tasks_ns[SKELFMM_NTPL], symtasks, symrows, slots;
     int ntasks_ns[SKELFMM_NTPL] = {};
+    DevMem tasks32;                               // 32-target work list of the matrix-core near field
+    int ntasks32 = 0;
     int nsym = 0, nred = 0;
     // workspace
     DevMem Q, Qh, U, Uh;
@@ -125,6 +134,12 @@ struct DeviceOp {
             for (auto e : ev) (void)hipEventDestroy(e);
     }
 };
+
+// The matrix-core near field serves several RHS of a real kernel in the
+// float32 policy.
+static bool use_mfma(const DeviceOp* d, int64_t nrhs, int dtype) {
+    return d->L.kind == 0 && dtype == SKELFMM_F32 && !d->f64_leaf && nrhs >= kMfmaMinRhs;
+}
 
 struct DeviceBatch {
     std::vector<DeviceOp*> ops;
@@ -239,6 +254,11 @@ static void upload(DeviceOp* d, int dtype) {
             d->tasks[tpl_slot(t)].upload(tl);
             d->ntasks[tpl_slot(t)] = static_cast<int>(tl.size());
         }
+        {
+            const std::vector<Task> tl = make_tasks(L, 32);
+            d->tasks32.upload(tl);
+            d->ntasks32 = static_cast<int>(tl.size());
+        }
         if (L.sym) {
             d->seg_ptr_ns.upload(L.seg_ptr_ns);
             std::vector<int2> sn(L.seg_src_ns.size());
@@ -278,7 +298,7 @@ void device_prepare(DeviceOp* d, int64_t nrhs, int dtype) {
     upload(d, dtype);
     upload_transposes(d, dtype_is_single(dtype));
     const size_t vb = dtype_is_single(dtype) ? 4 : 8;
-    const size_t wp = static_cast<size_t>(padded_width(nrhs, dtype));
+    const size_t wp = static_cast<size_t>(padded_width(nrhs, dtype, use_mfma(d, nrhs, dtype)));
     const size_t need_e = static_cast<size_t>(d->L.n_entries) * wp * vb;
     const size_t need_h = static_cast<size_t>(d->L.n_hentries) * wp * vb;
     if (d->Q.bytes < need_e) { d->Q.alloc(need_e); d->U.alloc(need_e); }
@@ -376,6 +396,18 @@ void launch_near_mr(const DeviceOp* d, hipStream_t s, int Wp, void* Q, void* Qh,
     SKF_HIP(hipGetLastError());
 }
 
+template <class P>
+void launch_near_mfma(const DeviceOp* d, hipStream_t s, int Wp, void* Q, void* Qh, void* U, void* Uh) {
+    const int ntasks = d->ntasks32;
+    if (ntasks == 0) return;
+    const int ntiles = Wp / kMfmaCols;
+    hipLaunchKernelGGL((kern::k_near_mfma<P>), dim3(blocks_for(int64_t(ntasks) * ntiles, 4)), dim3(256), 0, s,
+                       d->tasks32.as<Task>(), ntasks, ntiles, Wp, d->seg_ptr.as<int32_t>(), d->segs.as<int2>(),
+                       d->boxrec.as<kern::BoxRec>(), d->X64.as<kern::Rec4<double>>(), static_cast<const float*>(Q),
+                       static_cast<const float*>(Qh), static_cast<float*>(U), static_cast<float*>(Uh), kern::kInv4Pi);
+    SKF_HIP(hipGetLastError());
+}
+
 // One sweep.  V: stored values; TT: transfer matrices; P: near-field policy;
 // Am: accumulator of one source box's partial sums in the multi-RHS near field.
 template <typename V, typename TT, class P, typename Am>
@@ -384,7 +416,8 @@ void sweep(DeviceOp* d, const std::vector<IO>& io, int64_t nrhs, int dtype, hipS
     const Layout& L = d->L;
     const bool multi = nrhs > 1;
     const int Win = static_cast<int>(nrhs * P::nv);
-    const int Wp = static_cast<int>(padded_width(nrhs, dtype));
+    const bool mfma = use_mfma(d, nrhs, dtype);
+    const int Wp = static_cast<int>(padded_width(nrhs, dtype, mfma));
     V* Q = d->Q.as<V>();
     V* Qh = d->Qh.as<V>();
     V* U = d->U.as<V>();
@@ -427,8 +460,13 @@ void sweep(DeviceOp* d, const std::vector<IO>& io, int64_t nrhs, int dtype, hipS
     }
     pm.mark(2);
     if (multi) {
-        if (adjoint && P::kind == 1) launch_near_mr<P, true, Am>(d, s, Wp, Q, Qh, U, Uh);
-        else launch_near_mr<P, false, Am>(d, s, Wp, Q, Qh, U, Uh);
+        if constexpr (P::kind == 0 && sizeof(typename P::Rt) == 4) {
+            if (mfma) launch_near_mfma<P>(d, s, Wp, Q, Qh, U, Uh);
+            else launch_near_mr<P, false, Am>(d, s, Wp, Q, Qh, U, Uh);
+        } else {
+            if (adjoint && P::kind == 1) launch_near_mr<P, true, Am>(d, s, Wp, Q, Qh, U, Uh);
+            else launch_near_mr<P, false, Am>(d, s, Wp, Q, Qh, U, Uh);
+        }
         pm.mark(3);
         pm.mark(4);
     } else {

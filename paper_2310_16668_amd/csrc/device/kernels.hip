@@ -851,6 +851,122 @@ __global__ void __launch_bounds__(256) k_sym_reduce(const SymRows* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
+// many right-hand sides on the matrix cores (real kernels, float32 policy)
+// ---------------------------------------------------------------------------
+// With several right-hand sides the near field of a target tile is a product
+// U[t, r] += sum_s G(t, s) Q[s, r] whose left factor is generated on the fly.
+// A work item is one wavefront holding 32 targets x 32 RHS columns in a 32 x 32
+// float32 accumulator tile of v_mfma_f32_32x32x2f32: each step takes two
+// sources, every lane evaluates one kernel value G(target lane % 32, source
+// lane / 32) -- exactly the A operand's layout (row lane % 32, k lane / 32) --
+// and supplies Q[source lane / 32, column lane % 32] as the B operand.  The
+// float32 tile of one source box is added to float64 totals (the accumulator
+// layout: register v of lane l holds row 8 (v / 4) + 4 (l / 32) + v % 4,
+// column l % 32), as the other float32 kernels do per source box.
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+// Sources [s0, s1) of one box.  MODE as in near_loop_mr: 0 u += G q;
+// 1 u += G q, uh -= G qh; 2 u += G q, uh -= G q; 3 u += G (q - qh).
+template <class P, bool MASK, int MODE>
+__device__ __forceinline__ void mfma_range(const Rec4<double>* __restrict__ Xs, const float* __restrict__ Qs,
+                                           const float* __restrict__ Qhs, int Wp, int s0, int s1, double xt,
+                                           double yt, double zt, int row, int half, floatx16& cu, floatx16& ch) {
+#pragma unroll 8
+    for (int s2 = s0; s2 < s1; s2 += 2) {
+        const int s = s2 + half;
+        const bool ok = s < s1;
+        const int sc = ok ? s : s1 - 1;
+        const Rec4<double> xs = Xs[sc];
+        float g, gi;
+        green<P, false, MASK>(xt - xs.x, yt - xs.y, zt - xs.z, 0.0f, g, gi);
+        g = ok ? g : 0.0f;
+        const int64_t o = static_cast<int64_t>(sc) * Wp + row;
+        const float q = Qs[o];
+        float qh = 0.0f;
+        if constexpr (MODE == 1 || MODE == 3) qh = Qhs[o];
+        const float bu = MODE == 3 ? q - qh : q;
+        cu = __builtin_amdgcn_mfma_f32_32x32x2f32(g, bu, cu, 0, 0, 0);
+        if constexpr (MODE == 1) ch = __builtin_amdgcn_mfma_f32_32x32x2f32(g, -qh, ch, 0, 0, 0);
+        if constexpr (MODE == 2) ch = __builtin_amdgcn_mfma_f32_32x32x2f32(g, -q, ch, 0, 0, 0);
+    }
+}
+
+template <class P, bool MASK>
+__device__ __forceinline__ void mfma_segment(int mode, bool has_h, const Rec4<double>* __restrict__ Xs,
+                                             const float* __restrict__ Qs, const float* __restrict__ Qhs, int Wp,
+                                             int sn, int sk, double xt, double yt, double zt, int row, int half,
+                                             floatx16& cu, floatx16& ch) {
+    if (mode == SEG_IFO) {
+        if (has_h) {
+            mfma_range<P, MASK, 1>(Xs, Qs, Qhs, Wp, 0, sk, xt, yt, zt, row, half, cu, ch);
+            mfma_range<P, MASK, 0>(Xs, Qs, Qhs, Wp, sk, sn, xt, yt, zt, row, half, cu, ch);
+        } else {
+            mfma_range<P, MASK, 0>(Xs, Qs, Qhs, Wp, 0, sn, xt, yt, zt, row, half, cu, ch);
+        }
+    } else if (mode == SEG_IFS) {
+        if (has_h) mfma_range<P, MASK, 2>(Xs, Qs, Qhs, Wp, 0, sn, xt, yt, zt, row, half, cu, ch);
+        else mfma_range<P, MASK, 0>(Xs, Qs, Qhs, Wp, 0, sn, xt, yt, zt, row, half, cu, ch);
+    } else if (mode == SEG_TFO) {
+        mfma_range<P, MASK, 3>(Xs, Qs, Qhs, Wp, 0, sk, xt, yt, zt, row, half, cu, ch);
+        mfma_range<P, MASK, 0>(Xs, Qs, Qhs, Wp, sk, sn, xt, yt, zt, row, half, cu, ch);
+    } else {
+        mfma_range<P, MASK, 0>(Xs, Qs, Qhs, Wp, 0, sn, xt, yt, zt, row, half, cu, ch);
+    }
+}
+
+// Work item: (task of 32 targets, tile of 32 columns); Wp is a multiple of 32.
+template <class P>
+__global__ void __launch_bounds__(256) k_near_mfma(const Task* __restrict__ tasks, int ntasks, int ntiles, int Wp,
+                                                   const int32_t* __restrict__ seg_ptr,
+                                                   const int2* __restrict__ segs, const BoxRec* __restrict__ box,
+                                                   const Rec4<double>* __restrict__ X, const float* __restrict__ Q,
+                                                   const float* __restrict__ Qh, float* __restrict__ U,
+                                                   float* __restrict__ Uh, double scale) {
+    const int lane = threadIdx.x & 63;
+    const int wid = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (wid >= ntasks * ntiles) return;
+    const int c0 = 32 * (wid % ntiles);
+    const Task tk = tasks[wid / ntiles];
+    const BoxRec tb = box[tk.box];
+    const bool has_h = tk.t0 < tb.k;
+    const int row = lane & 31, half = lane >> 5;
+    const Rec4<double> xr = X[tb.voff + min(tk.t0 + row, tb.n - 1)];
+    double du[16], dh[16];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) { du[v] = 0.0; dh[v] = 0.0; }
+    const int e1 = seg_ptr[tk.box + 1];
+    for (int e = seg_ptr[tk.box]; e < e1; ++e) {
+        const int2 sg = segs[e];
+        const BoxRec sb = box[sg.x];
+        const Rec4<double>* Xs = X + sb.voff;
+        const float* Qs = Q + sb.voff * Wp + c0;
+        const float* Qhs = Qh + sb.hoff * Wp + c0;
+        floatx16 cu = {}, ch = {};
+        if (sg.y & SEG_SELF)
+            mfma_segment<P, true>(sg.y & SEG_MODE_MASK, has_h, Xs, Qs, Qhs, Wp, sb.n, sb.k, xr.x, xr.y, xr.z, row,
+                                  half, cu, ch);
+        else
+            mfma_segment<P, false>(sg.y & SEG_MODE_MASK, has_h, Xs, Qs, Qhs, Wp, sb.n, sb.k, xr.x, xr.y, xr.z,
+                                   row, half, cu, ch);
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            du[v] += static_cast<double>(cu[v]);
+            dh[v] += static_cast<double>(ch[v]);
+        }
+    }
+    const double sc = scale * P::gscale;
+    const int col = c0 + row;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int t = tk.t0 + 8 * (v / 4) + 4 * half + (v % 4);
+        if (t < tb.n) {
+            U[(tb.voff + t) * Wp + col] = static_cast<float>(du[v] * sc);
+            if (has_h && t < tb.k) Uh[(tb.hoff + t) * Wp + col] = static_cast<float>(dh[v] * sc);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // many right-hand sides
 // ---------------------------------------------------------------------------
 // Gather / scatter between the caller's n x Win vectors and the leaf entries of
