@@ -121,6 +121,7 @@ struct DeviceOp {
     int ntasks_ns[SKELFMM_NTPL] = {};
     DevMem tasks32;                               // 32-target work list of the matrix-core near field
     int ntasks32 = 0;
+    int ntasks32h = 0;                            // its first ntasks32h items hold uhat rows
     int nsym = 0, nred = 0;
     // workspace
     DevMem Q, Qh, U, Uh;
@@ -255,7 +256,12 @@ static void upload(DeviceOp* d, int dtype) {
             d->ntasks[tpl_slot(t)] = static_cast<int>(tl.size());
         }
         {
-            const std::vector<Task> tl = make_tasks(L, 32);
+            // items holding skeleton targets (uhat rows) first; the rest run two
+            // column tiles per wave
+            std::vector<Task> tl = make_tasks(L, 32);
+            std::stable_partition(tl.begin(), tl.end(), [&](const Task& t) { return t.t0 < L.kb[t.box]; });
+            d->ntasks32h = static_cast<int>(
+                std::count_if(tl.begin(), tl.end(), [&](const Task& t) { return t.t0 < L.kb[t.box]; }));
             d->tasks32.upload(tl);
             d->ntasks32 = static_cast<int>(tl.size());
         }
@@ -396,15 +402,35 @@ void launch_near_mr(const DeviceOp* d, hipStream_t s, int Wp, void* Q, void* Qh,
     SKF_HIP(hipGetLastError());
 }
 
+// Tasks with uhat rows come first in the list (nh of them).  One column tile:
+// k_near_mfma over every task; more: two tiles per wave, one launch per list.
 template <class P>
 void launch_near_mfma(const DeviceOp* d, hipStream_t s, int Wp, void* Q, void* Qh, void* U, void* Uh) {
-    const int ntasks = d->ntasks32;
-    if (ntasks == 0) return;
-    const int ntiles = Wp / kMfmaCols;
-    hipLaunchKernelGGL((kern::k_near_mfma<P>), dim3(blocks_for(int64_t(ntasks) * ntiles, 4)), dim3(256), 0, s,
-                       d->tasks32.as<Task>(), ntasks, ntiles, Wp, d->seg_ptr.as<int32_t>(), d->segs.as<int2>(),
-                       d->boxrec.as<kern::BoxRec>(), d->X64.as<kern::Rec4<double>>(), static_cast<const float*>(Q),
-                       static_cast<const float*>(Qh), static_cast<float*>(U), static_cast<float*>(Uh), kern::kInv4Pi);
+    static_assert(kMfmaCols == kern::kMfmaTile, "one accumulator tile width");
+    const int nt = d->ntasks32, nh = d->ntasks32h, nn = nt - nh;
+    const int ntiles = Wp / kMfmaCols, npairs = (ntiles + 1) / 2;
+    const Task* tl = d->tasks32.as<Task>();
+    const auto* X = d->X64.as<kern::Rec4<double>>();
+    const float* Qf = static_cast<const float*>(Q);
+    const float* Qhf = static_cast<const float*>(Qh);
+    float* Uf = static_cast<float*>(U);
+    float* Uhf = static_cast<float*>(Uh);
+    if (ntiles == 1) {
+        if (nt > 0)
+            hipLaunchKernelGGL((kern::k_near_mfma<P>), dim3(blocks_for(nt, 4)), dim3(256), 0, s, tl, nt, 1, Wp,
+                               d->seg_ptr.as<int32_t>(), d->segs.as<int2>(), d->boxrec.as<kern::BoxRec>(), X, Qf,
+                               Qhf, Uf, Uhf, kern::kInv4Pi);
+        SKF_HIP(hipGetLastError());
+        return;
+    }
+    if (nh > 0)
+        hipLaunchKernelGGL((kern::k_near_mfma2<P, true>), dim3(blocks_for(int64_t(nh) * npairs, 4)), dim3(256), 0,
+                           s, tl, nh, npairs, Wp, d->seg_ptr.as<int32_t>(), d->segs.as<int2>(),
+                           d->boxrec.as<kern::BoxRec>(), X, Qf, Qhf, Uf, Uhf, kern::kInv4Pi);
+    if (nn > 0)
+        hipLaunchKernelGGL((kern::k_near_mfma2<P, false>), dim3(blocks_for(int64_t(nn) * npairs, 4)), dim3(256), 0,
+                           s, tl + nh, nn, npairs, Wp, d->seg_ptr.as<int32_t>(), d->segs.as<int2>(),
+                           d->boxrec.as<kern::BoxRec>(), X, Qf, Qhf, Uf, Uhf, kern::kInv4Pi);
     SKF_HIP(hipGetLastError());
 }
 

@@ -864,6 +864,7 @@ __global__ void __launch_bounds__(256) k_sym_reduce(const SymRows* __restrict__ 
 // layout: register v of lane l holds row 8 (v / 4) + 4 (l / 32) + v % 4,
 // column l % 32), as the other float32 kernels do per source box.
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+constexpr int kMfmaTile = 32;   // columns of one accumulator tile
 
 // Sources [s0, s1) of one box.  MODE as in near_loop_mr: 0 u += G q;
 // 1 u += G q, uh -= G qh; 2 u += G q, uh -= G q; 3 u += G (q - qh).
@@ -962,6 +963,127 @@ __global__ void __launch_bounds__(256) k_near_mfma(const Task* __restrict__ task
         if (t < tb.n) {
             U[(tb.voff + t) * Wp + col] = static_cast<float>(du[v] * sc);
             if (has_h && t < tb.k) Uh[(tb.hoff + t) * Wp + col] = static_cast<float>(dh[v] * sc);
+        }
+    }
+}
+
+// Two column tiles per wave: each kernel value feeds the MFMAs of both tiles,
+// halving the evaluations per column.  `two` is false when the second tile
+// lies past the padded width (an odd tile count): its loads are skipped and
+// its MFMAs accumulate zeros that are never stored.  Each tile sees the same MFMA sequence as in k_near_mfma, so the
+// sums agree bit for bit with the one-tile kernel.  Modes as in mfma_range.
+template <class P, bool MASK, int MODE>
+__device__ __forceinline__ void mfma_range2(const Rec4<double>* __restrict__ Xs, const float* __restrict__ Qs,
+                                            const float* __restrict__ Qhs, int Wp, int s0, int s1, double xt,
+                                            double yt, double zt, int row, int half, bool two, floatx16 (&cu)[2],
+                                            floatx16 (&ch)[2]) {
+#pragma unroll 4
+    for (int s2 = s0; s2 < s1; s2 += 2) {
+        const int s = s2 + half;
+        const bool ok = s < s1;
+        const int sc = ok ? s : s1 - 1;
+        const Rec4<double> xs = Xs[sc];
+        float g, gi;
+        green<P, false, MASK>(xt - xs.x, yt - xs.y, zt - xs.z, 0.0f, g, gi);
+        g = ok ? g : 0.0f;
+        const int64_t o = static_cast<int64_t>(sc) * Wp + row;
+        float q0 = Qs[o], q1 = 0.0f, h0 = 0.0f, h1 = 0.0f;
+        if (two) q1 = Qs[o + kMfmaTile];
+        if constexpr (MODE == 1 || MODE == 3) {
+            h0 = Qhs[o];
+            if (two) h1 = Qhs[o + kMfmaTile];
+        }
+        const float b0 = MODE == 3 ? q0 - h0 : q0, b1 = MODE == 3 ? q1 - h1 : q1;
+        cu[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(g, b0, cu[0], 0, 0, 0);
+        cu[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(g, b1, cu[1], 0, 0, 0);
+        if constexpr (MODE == 1) {
+            ch[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(g, -h0, ch[0], 0, 0, 0);
+            ch[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(g, -h1, ch[1], 0, 0, 0);
+        }
+        if constexpr (MODE == 2) {
+            ch[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(g, -q0, ch[0], 0, 0, 0);
+            ch[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(g, -q1, ch[1], 0, 0, 0);
+        }
+    }
+}
+
+template <class P, bool MASK, bool H>
+__device__ __forceinline__ void mfma_segment2(int mode, const Rec4<double>* __restrict__ Xs,
+                                              const float* __restrict__ Qs, const float* __restrict__ Qhs, int Wp,
+                                              int sn, int sk, double xt, double yt, double zt, int row, int half,
+                                              bool two, floatx16 (&cu)[2], floatx16 (&ch)[2]) {
+    if (mode == SEG_IFO && H) {
+        mfma_range2<P, MASK, 1>(Xs, Qs, Qhs, Wp, 0, sk, xt, yt, zt, row, half, two, cu, ch);
+        mfma_range2<P, MASK, 0>(Xs, Qs, Qhs, Wp, sk, sn, xt, yt, zt, row, half, two, cu, ch);
+    } else if (mode == SEG_IFS && H) {
+        mfma_range2<P, MASK, 2>(Xs, Qs, Qhs, Wp, 0, sn, xt, yt, zt, row, half, two, cu, ch);
+    } else if (mode == SEG_TFO) {
+        mfma_range2<P, MASK, 3>(Xs, Qs, Qhs, Wp, 0, sk, xt, yt, zt, row, half, two, cu, ch);
+        mfma_range2<P, MASK, 0>(Xs, Qs, Qhs, Wp, sk, sn, xt, yt, zt, row, half, two, cu, ch);
+    } else {
+        mfma_range2<P, MASK, 0>(Xs, Qs, Qhs, Wp, 0, sn, xt, yt, zt, row, half, two, cu, ch);
+    }
+}
+
+// Work item: (task of 32 targets, pair of 32-column tiles).  H: the task's
+// targets lie in the box's skeleton (uhat rows); tasks are launched in two
+// lists, with and without.
+template <class P, bool H>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(H ? 2 : 1, 8))) k_near_mfma2(const Task* __restrict__ tasks, int ntasks, int npairs, int Wp,
+                                                    const int32_t* __restrict__ seg_ptr,
+                                                    const int2* __restrict__ segs, const BoxRec* __restrict__ box,
+                                                    const Rec4<double>* __restrict__ X, const float* __restrict__ Q,
+                                                    const float* __restrict__ Qh, float* __restrict__ U,
+                                                    float* __restrict__ Uh, double scale) {
+    const int lane = threadIdx.x & 63;
+    const int wid = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (wid >= ntasks * npairs) return;
+    const int c0 = 2 * kMfmaTile * (wid % npairs);
+    const bool two = c0 + kMfmaTile < Wp;
+    const Task tk = tasks[wid / npairs];
+    const BoxRec tb = box[tk.box];
+    const int row = lane & 31, half = lane >> 5;
+    const Rec4<double> xr = X[tb.voff + min(tk.t0 + row, tb.n - 1)];
+    double du[2][16], dh[2][16];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) { du[c][v] = 0.0; dh[c][v] = 0.0; }
+    const int e1 = seg_ptr[tk.box + 1];
+    for (int e = seg_ptr[tk.box]; e < e1; ++e) {
+        const int2 sg = segs[e];
+        const BoxRec sb = box[sg.x];
+        const Rec4<double>* Xs = X + sb.voff;
+        const float* Qs = Q + sb.voff * Wp + c0;
+        const float* Qhs = Qh + sb.hoff * Wp + c0;
+        floatx16 cu[2] = {{}, {}}, ch[2] = {{}, {}};
+        if (sg.y & SEG_SELF)
+            mfma_segment2<P, true, H>(sg.y & SEG_MODE_MASK, Xs, Qs, Qhs, Wp, sb.n, sb.k, xr.x, xr.y, xr.z, row, half,
+                                      two, cu, ch);
+        else
+            mfma_segment2<P, false, H>(sg.y & SEG_MODE_MASK, Xs, Qs, Qhs, Wp, sb.n, sb.k, xr.x, xr.y, xr.z, row,
+                                       half, two, cu, ch);
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                du[c][v] += static_cast<double>(cu[c][v]);
+                if constexpr (H) dh[c][v] += static_cast<double>(ch[c][v]);
+            }
+    }
+    const double sc = scale * P::gscale;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int t = tk.t0 + 8 * (v / 4) + 4 * half + (v % 4);
+        if (t < tb.n) {
+            float* u = U + (tb.voff + t) * Wp + c0 + row;
+            u[0] = static_cast<float>(du[0][v] * sc);
+            if (two) u[kMfmaTile] = static_cast<float>(du[1][v] * sc);
+            if (H && t < tb.k) {
+                float* uh = Uh + (tb.hoff + t) * Wp + c0 + row;
+                uh[0] = static_cast<float>(dh[0][v] * sc);
+                if (two) uh[kMfmaTile] = static_cast<float>(dh[1][v] * sc);
+            }
         }
     }
 }

@@ -234,6 +234,27 @@ def test_many_rhs_single_precision(name):
     assert e1 <= max(10 * tol, 1e-5)
 
 
+@pytest.mark.parametrize("nrhs", [40, 70])
+def test_many_rhs_single_precision_column_tiles(nrhs):
+    """float32 with many RHS runs on the matrix cores in 32-column tiles, two
+    tiles per wave where a work item has no uhat rows: 40 RHS pad to two tiles
+    (one pair), 70 to three (the last pair holds one tile).  Every column must
+    match O2 on the rounded charges and the one-column apply of the same column."""
+    x, op, P = _op("lap3d_uniform_64k")
+    n = x.shape[0]
+    Q = workloads.charges(n, nrhs, 23)
+    Qr = Q.astype(np.float32).astype(np.float64)
+    U = host(op.apply(dev(Q, torch.float32))).astype(np.float64)
+    W = host(op.apply_adjoint(dev(Q, torch.float32))).astype(np.float64)
+    e_u = relerr(U, oracle.apply(P, Qr))
+    e_w = relerr(W, oracle.apply(P, Qr, adjoint=True))
+    _say("lap3d_uniform_64k", f"{nrhs} rhs float32 vs O2", e_u, "adjoint", e_w)
+    assert e_u <= 2e-6 and e_w <= 2e-6
+    for c in sorted(c for c in {0, 31, 32, 33, 63, 64, nrhs - 1} if c < nrhs):
+        one = host(op.apply(dev(np.ascontiguousarray(Q[:, c]), torch.float32))).astype(np.float64)
+        assert relerr(U[:, c], one) <= 2e-6, c
+
+
 def _batch_ops(f64_leaf=False):
     geo = [workloads.uniform_points(20000, 3, 601), workloads.ellipsoid_points(30000, 602),
            workloads.uniform_points(15000, 3, 603)]
