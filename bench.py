@@ -29,11 +29,20 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Vector ALU peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz x 2 flops (multiply-add).
-# The near-field kernels issue non-packed float64 and float32 operations (the
-# packed float32 forms, which double the float32 figure to 157.3, are disabled in
-# this build), so both paths are priced against 78.6 TFLOP/s.
-PEAK_TFLOPS = {"f64": 78.6, "f32": 78.6}
+# Vector ALU peaks (published): float32 157.3 TFLOP/s = 256 CUs x 4 SIMDs x 32 lanes
+# x 2.4 GHz x 2 flops -- a plain (non-packed) float32 multiply-add issues in two
+# cycles per wave of 64 -- and float64 78.6 TFLOP/s (four cycles per wave).  Each
+# path is priced against the peak of its evaluation type.
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
+# Issue cycles per wave instruction (64 lanes) used for the instruction-mix bound of
+# the float32 pair kernel: float64 add / multiply-add and the float64 -> float32
+# conversion 4, float32 multiply-add 2, reciprocal square root 16.  The cheapest
+# evaluation of a symmetric pair (expanded |d|^2: one float64 add and three float64
+# multiply-adds; one conversion; one reciprocal square root; two float32
+# multiply-adds) therefore costs 40 cycles per wave of 64 pairs.
+CLOCK_GHZ = 2.4
+SIMDS = 1024
+MIX_CYCLES_PER_64_SYM_PAIRS = {"f32": 4 * 4 + 4 + 16 + 2 * 2}
 PEAK_HBM_GBS = 8000.0
 # algorithmic flops of one 3D Laplace pair in k_near: 3 subtractions, |d|^2
 # (3 mul + 2 add), one reciprocal square root, one multiply-add into u; a skeleton
@@ -307,6 +316,15 @@ def main():
     tpl = tuned.get(chosen, {}).get("targets_per_lane")
     traffic = (tr["bytes"] if tr and tr["kernels_sha256"] == digest and tr.get("kernel") == dom
                and tr.get("targets_per_lane") == tpl else None)
+    # the same launch against its instruction mix: every evaluation (a symmetric pair,
+    # or a one-direction tile pair) priced at the cheapest symmetric-pair cost
+    issue_bound = None
+    if dom == "k_near_sym" and chosen in MIX_CYCLES_PER_64_SYM_PAIRS:
+        evals = st["pairs_sym"] + st["pairs_tile"]
+        ideal_ms = evals / 64 * MIX_CYCLES_PER_64_SYM_PAIRS[chosen] / SIMDS / (CLOCK_GHZ * 1e9) * 1e3
+        issue_bound = {"cycles_per_64_pairs_ideal": MIX_CYCLES_PER_64_SYM_PAIRS[chosen],
+                       "cycles_per_64_pairs_achieved": near_ms * 1e-3 * CLOCK_GHZ * 1e9 * SIMDS / (evals / 64),
+                       "ideal_ms": ideal_ms, "frac": ideal_ms / near_ms}
     sT = 8 if chosen == "f64" else 4
     # upward and downward each read every T once, plus their vectors (n and k entries)
     t_bytes = st["m_proj_elems"] * sT
@@ -329,6 +347,7 @@ def main():
                    "tol": w.tol, "nrhs": 1, "step": "forward apply + adjoint apply"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS[chosen], "unit": "TFLOP/s",
                      "frac": achieved / PEAK_TFLOPS[chosen], "traffic": traffic,
+                     "issue_bound": issue_bound,
                      "kernel": dom, "ms_per_launch": near_ms,
                      "sym_pairs_per_launch": st["pairs_sym"], "sym_skel_pairs_per_launch": st["pairs_sym_skel"],
                      "tile_pairs_per_launch": st["pairs_tile"], "tile_skel_pairs_per_launch": st["pairs_tile_skel"],

@@ -750,8 +750,49 @@ __device__ __forceinline__ void sym_pass(const SymCtx& cx, int tp, const Rec4<do
     }
 }
 
-// A pair item: passes of 64 TPL targets; a last pass of at most 64 targets runs
-// with one target per lane, so a ragged end wastes at most one wave's lanes.
+// The last pass of an item when at most 64 TPL targets are left: it runs with
+// the fewest targets per lane that hold them, so a ragged end wastes less than
+// one wave's lanes.  The pass boundaries (and with them the diagonal tiles of a
+// self item) are those of TPL-wide passes.  Every pass width is inlined at one
+// call site (two copies of a wide pass cost the float32 variants spills).
+template <class P, int TPL, bool SELF, bool FAST>
+__device__ __forceinline__ void sym_tail(const SymCtx& cx, int tp, const Rec4<double>* __restrict__ X,
+                                         const typename P::Vt* __restrict__ Q, const typename P::Vt* __restrict__ Qh,
+                                         const Rec4<double>* __restrict__ Xs, const typename P::Vt* __restrict__ Qs,
+                                         const typename P::Vt* __restrict__ Qhs, typename P::Rt* tile,
+                                         SrcStage<typename P::Rt>* src, int lane) {
+    if constexpr (TPL == 1) {
+        sym_pass<P, 1, SELF, FAST>(cx, tp, X, Q, Qh, Xs, Qs, Qhs, tile, src, lane);
+    } else {
+        if (cx.t1 - tp > 64 * (TPL - 1))
+            sym_pass<P, TPL, SELF, FAST>(cx, tp, X, Q, Qh, Xs, Qs, Qhs, tile, src, lane);
+        else
+            sym_tail<P, TPL - 1, SELF, FAST>(cx, tp, X, Q, Qh, Xs, Qs, Qhs, tile, src, lane);
+    }
+}
+
+// All passes of an item: TPL-wide while more than 64 (TPL - 1) targets are
+// left (the last of them may be ragged), else the narrower tail.
+template <class P, int TPL, bool SELF, bool FAST>
+__device__ __forceinline__ void sym_passes(const SymCtx& cx, const Rec4<double>* __restrict__ X,
+                                           const typename P::Vt* __restrict__ Q,
+                                           const typename P::Vt* __restrict__ Qh,
+                                           const Rec4<double>* __restrict__ Xs,
+                                           const typename P::Vt* __restrict__ Qs,
+                                           const typename P::Vt* __restrict__ Qhs, typename P::Rt* tile,
+                                           SrcStage<typename P::Rt>* src, int lane) {
+    for (int tp = cx.t0; tp < cx.t1;) {
+        if (cx.t1 - tp > 64 * (TPL - 1)) {
+            sym_pass<P, TPL, SELF, FAST>(cx, tp, X, Q, Qh, Xs, Qs, Qhs, tile, src, lane);
+            tp += 64 * TPL;
+        } else {
+            if constexpr (TPL > 1) sym_tail<P, TPL - 1, SELF, FAST>(cx, tp, X, Q, Qh, Xs, Qs, Qhs, tile, src, lane);
+            break;
+        }
+    }
+}
+
+// A pair item: its passes (sym_passes).
 // A box paired with itself (bi == bj, one item over all its targets) evaluates
 // each unordered pair of distinct entries once, except inside the diagonal
 // tiles, which run in one direction with the zero distances masked.
@@ -776,21 +817,13 @@ __device__ __forceinline__ void sym_item(const SymTask it, const BoxRec* __restr
     const Rec4<double>* Xs = X + cx.bj.voff;
     const V* Qs = Q + cx.bj.voff;
     const V* Qhs = Qh + cx.bj.hoff;
-    int tp = it.t0;
     // the expanded |d|^2 serves the float32 evaluation of items the build marked safe for it
-    if (sizeof(typename P::Rt) == 4 && (it.flags & SYM_EXPANDED)) {
-        for (; it.t1 - tp > 64; tp += 64 * TPL)
-            sym_pass<P, TPL, false, true>(cx, tp, X, Q, Qh, Xs, Qs, Qhs, tile, src, lane);
-        if (tp < it.t1) sym_pass<P, 1, false, true>(cx, tp, X, Q, Qh, Xs, Qs, Qhs, tile, src, lane);
-    } else if (it.bi != it.bj) {
-        for (; it.t1 - tp > 64; tp += 64 * TPL)
-            sym_pass<P, TPL, false, false>(cx, tp, X, Q, Qh, Xs, Qs, Qhs, tile, src, lane);
-        if (tp < it.t1) sym_pass<P, 1, false, false>(cx, tp, X, Q, Qh, Xs, Qs, Qhs, tile, src, lane);
-    } else {
-        for (; it.t1 - tp > 64; tp += 64 * TPL)
-            sym_pass<P, TPL, true, false>(cx, tp, X, Q, Qh, Xs, Qs, Qhs, tile, src, lane);
-        if (tp < it.t1) sym_pass<P, 1, true, false>(cx, tp, X, Q, Qh, Xs, Qs, Qhs, tile, src, lane);
-    }
+    if (sizeof(typename P::Rt) == 4 && (it.flags & SYM_EXPANDED))
+        sym_passes<P, TPL, false, true>(cx, X, Q, Qh, Xs, Qs, Qhs, tile, src, lane);
+    else if (it.bi != it.bj)
+        sym_passes<P, TPL, false, false>(cx, X, Q, Qh, Xs, Qs, Qhs, tile, src, lane);
+    else
+        sym_passes<P, TPL, true, false>(cx, X, Q, Qh, Xs, Qs, Qhs, tile, src, lane);
 }
 
 // Waves per SIMD the pair kernel is compiled for: the float32 evaluation fits
@@ -866,30 +899,70 @@ __global__ void __launch_bounds__(256) k_sym_reduce(const SymRows* __restrict__ 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 constexpr int kMfmaTile = 32;   // columns of one accumulator tile
 
-// Sources [s0, s1) of one box.  MODE as in near_loop_mr: 0 u += G q;
-// 1 u += G q, uh -= G qh; 2 u += G q, uh -= G q; 3 u += G (q - qh).
+// Sources [s0, s1) of one box, two per step, into NT column tiles.  MODE as in
+// near_loop_mr: 0 u += G q; 1 u += G q, uh -= G qh; 2 u += G q, uh -= G q;
+// 3 u += G (q - qh).  Steps run in groups of GS: the group's loads are issued
+// together, then its kernel values and MFMAs, so one memory latency covers GS
+// steps; steps past s1 repeat the last source with a zero kernel value.  With
+// NT = 2, `two` is false when the second tile lies past the padded width (an
+// odd tile count): its loads are skipped and its MFMAs accumulate zeros that
+// are never stored.
+template <class P, bool MASK, int MODE, int NT, int GS>
+__device__ __forceinline__ void mfma_steps(const Rec4<double>* __restrict__ Xs, const float* __restrict__ Qs,
+                                           const float* __restrict__ Qhs, int Wp, int s0, int s1, double xt,
+                                           double yt, double zt, int row, int half, bool two, floatx16 (&cu)[NT],
+                                           floatx16 (&ch)[NT]) {
+    for (int sg = s0; sg < s1; sg += 2 * GS) {
+        double sx[GS], sy[GS], sz[GS];
+        float q[GS][NT], qh[GS][NT];
+        bool ok[GS];
+#pragma unroll
+        for (int u = 0; u < GS; ++u) {
+            const int s = sg + 2 * u + half;
+            ok[u] = s < s1;
+            const int sc = ok[u] ? s : s1 - 1;
+            const Rec4<double> xs = Xs[sc];
+            sx[u] = xs.x;
+            sy[u] = xs.y;
+            sz[u] = xs.z;
+            const int64_t o = static_cast<int64_t>(sc) * Wp + row;
+#pragma unroll
+            for (int c = 0; c < NT; ++c) {
+                q[u][c] = 0.0f;
+                qh[u][c] = 0.0f;
+                if (c == 0 || two) {
+                    q[u][c] = Qs[o + c * kMfmaTile];
+                    if constexpr (MODE == 1 || MODE == 3) qh[u][c] = Qhs[o + c * kMfmaTile];
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < GS; ++u) {
+            float g, gi;
+            green<P, false, MASK>(xt - sx[u], yt - sy[u], zt - sz[u], 0.0f, g, gi);
+            g = ok[u] ? g : 0.0f;
+#pragma unroll
+            for (int c = 0; c < NT; ++c) {
+                const float bu = MODE == 3 ? q[u][c] - qh[u][c] : q[u][c];
+                cu[c] = __builtin_amdgcn_mfma_f32_32x32x2f32(g, bu, cu[c], 0, 0, 0);
+                if constexpr (MODE == 1) ch[c] = __builtin_amdgcn_mfma_f32_32x32x2f32(g, -qh[u][c], ch[c], 0, 0, 0);
+                if constexpr (MODE == 2) ch[c] = __builtin_amdgcn_mfma_f32_32x32x2f32(g, -q[u][c], ch[c], 0, 0, 0);
+            }
+        }
+    }
+}
+
+// Steps per group of the one-tile kernel
+constexpr int kMfmaGroup1 = 4;
+
 template <class P, bool MASK, int MODE>
 __device__ __forceinline__ void mfma_range(const Rec4<double>* __restrict__ Xs, const float* __restrict__ Qs,
                                            const float* __restrict__ Qhs, int Wp, int s0, int s1, double xt,
                                            double yt, double zt, int row, int half, floatx16& cu, floatx16& ch) {
-#pragma unroll 8
-    for (int s2 = s0; s2 < s1; s2 += 2) {
-        const int s = s2 + half;
-        const bool ok = s < s1;
-        const int sc = ok ? s : s1 - 1;
-        const Rec4<double> xs = Xs[sc];
-        float g, gi;
-        green<P, false, MASK>(xt - xs.x, yt - xs.y, zt - xs.z, 0.0f, g, gi);
-        g = ok ? g : 0.0f;
-        const int64_t o = static_cast<int64_t>(sc) * Wp + row;
-        const float q = Qs[o];
-        float qh = 0.0f;
-        if constexpr (MODE == 1 || MODE == 3) qh = Qhs[o];
-        const float bu = MODE == 3 ? q - qh : q;
-        cu = __builtin_amdgcn_mfma_f32_32x32x2f32(g, bu, cu, 0, 0, 0);
-        if constexpr (MODE == 1) ch = __builtin_amdgcn_mfma_f32_32x32x2f32(g, -qh, ch, 0, 0, 0);
-        if constexpr (MODE == 2) ch = __builtin_amdgcn_mfma_f32_32x32x2f32(g, -q, ch, 0, 0, 0);
-    }
+    floatx16 u[1] = {cu}, h[1] = {ch};
+    mfma_steps<P, MASK, MODE, 1, kMfmaGroup1>(Xs, Qs, Qhs, Wp, s0, s1, xt, yt, zt, row, half, false, u, h);
+    cu = u[0];
+    ch = h[0];
 }
 
 template <class P, bool MASK>
@@ -968,43 +1041,16 @@ __global__ void __launch_bounds__(256) k_near_mfma(const Task* __restrict__ task
 }
 
 // Two column tiles per wave: each kernel value feeds the MFMAs of both tiles,
-// halving the evaluations per column.  `two` is false when the second tile
-// lies past the padded width (an odd tile count): its loads are skipped and
-// its MFMAs accumulate zeros that are never stored.  Each tile sees the same MFMA sequence as in k_near_mfma, so the
-// sums agree bit for bit with the one-tile kernel.  Modes as in mfma_range.
+// halving the evaluations per column.  Per tile the MFMA sequence is that of
+// the one-tile kernel, so the sums agree bit for bit.  Steps per group: the
+// uhat modes hold four accumulator tiles and take smaller groups.
 template <class P, bool MASK, int MODE>
 __device__ __forceinline__ void mfma_range2(const Rec4<double>* __restrict__ Xs, const float* __restrict__ Qs,
                                             const float* __restrict__ Qhs, int Wp, int s0, int s1, double xt,
                                             double yt, double zt, int row, int half, bool two, floatx16 (&cu)[2],
                                             floatx16 (&ch)[2]) {
-#pragma unroll 4
-    for (int s2 = s0; s2 < s1; s2 += 2) {
-        const int s = s2 + half;
-        const bool ok = s < s1;
-        const int sc = ok ? s : s1 - 1;
-        const Rec4<double> xs = Xs[sc];
-        float g, gi;
-        green<P, false, MASK>(xt - xs.x, yt - xs.y, zt - xs.z, 0.0f, g, gi);
-        g = ok ? g : 0.0f;
-        const int64_t o = static_cast<int64_t>(sc) * Wp + row;
-        float q0 = Qs[o], q1 = 0.0f, h0 = 0.0f, h1 = 0.0f;
-        if (two) q1 = Qs[o + kMfmaTile];
-        if constexpr (MODE == 1 || MODE == 3) {
-            h0 = Qhs[o];
-            if (two) h1 = Qhs[o + kMfmaTile];
-        }
-        const float b0 = MODE == 3 ? q0 - h0 : q0, b1 = MODE == 3 ? q1 - h1 : q1;
-        cu[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(g, b0, cu[0], 0, 0, 0);
-        cu[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(g, b1, cu[1], 0, 0, 0);
-        if constexpr (MODE == 1) {
-            ch[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(g, -h0, ch[0], 0, 0, 0);
-            ch[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(g, -h1, ch[1], 0, 0, 0);
-        }
-        if constexpr (MODE == 2) {
-            ch[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(g, -q0, ch[0], 0, 0, 0);
-            ch[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(g, -q1, ch[1], 0, 0, 0);
-        }
-    }
+    mfma_steps<P, MASK, MODE, 2, (MODE == 1 || MODE == 2) ? 2 : 4>(Xs, Qs, Qhs, Wp, s0, s1, xt, yt, zt, row, half,
+                                                                    two, cu, ch);
 }
 
 template <class P, bool MASK, bool H>

@@ -298,12 +298,11 @@ void make_symmetric(Layout& L, int group) {
             }
             if (c < b) continue;   // the pair was handled from the smaller id
             // i = the box on the lanes: the side whose targets fill the passes
-            // (128 lanes, a last pass of 64) with fewer idle lanes per source
-            // pair; on a tie the box with more entries
-            auto lanes = [](int64_t m) {
-                const int64_t full = m / 128, r = m % 128;
-                return 128 * full + (r == 0 ? 0 : (r <= 64 ? 64 : 128));
-            };
+            // with fewer idle lane slots per source pair; on a tie the box with
+            // more entries.  Full passes hold 64 TPL targets and the last pass
+            // the fewest targets per lane that hold the rest, so m targets take
+            // 64 ceil(m / 64) lane slots at any TPL.
+            auto lanes = [](int64_t m) { return (m + 63) / 64 * 64; };
             const int64_t cost_b = lanes(L.nb[b]) * L.nb[c], cost_c = lanes(L.nb[c]) * L.nb[b];
             int bi = b, bj = c;
             if (cost_c < cost_b || (cost_c == cost_b && L.nb[c] > L.nb[b])) { bi = c; bj = b; }
@@ -407,12 +406,12 @@ void sym_pair_counts(const Layout& L, int tpl, int64_t out[4]) {
             out[1] += std::max<int64_t>(0, std::min<int64_t>(ki, st.t1) - st.t0) * kj;
             continue;
         }
-        // passes of 64 tpl targets, a last one of at most 64; the diagonal tiles
-        // run in one direction, the rest of the block in both
+        // passes of 64 tpl targets while more remain, then one pass over the
+        // rest; the diagonal tiles run in one direction, the rest of the block
+        // in both
         int64_t d = 0, dk = 0;
         for (int64_t tp = 0; tp < ni;) {
-            const int64_t w = ni - tp > 64 ? 64 * tpl : 64;
-            const int64_t e = std::min(ni, tp + w);
+            const int64_t e = ni - tp > 64 * tpl ? tp + 64 * tpl : ni;
             d += (e - tp) * (e - tp);
             const int64_t ek = std::max<int64_t>(0, std::min(e, ki) - tp);
             dk += ek * ek;
