@@ -212,8 +212,7 @@ def batched_run(steps: int, warmup: int):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU; --gpus must be 1 "
-                          "(the sharded design is described in DESIGN.md)"}))
+        print(json.dumps({"error": "one GPU per run: --gpus must be 1 (the apply does not shard across GPUs)"}))
         return 2
     if args.batched_only:
         print(json.dumps({"batched": batched_run(args.steps, args.warmup)}))

@@ -49,7 +49,7 @@ typedef enum {
     SKELFMM_EINVAL = -1,     /* invalid argument */
     SKELFMM_ENOMEM = -2,     /* host or device allocation failed */
     SKELFMM_EDEVICE = -3,    /* HIP runtime error (no device, launch failure, ...) */
-    SKELFMM_ENOTSUP = -4,    /* valid request this build does not support */
+    SKELFMM_ENOTSUP = -4,    /* valid request the library does not support */
     SKELFMM_EINTERNAL = -5
 } skelfmm_status;
 
