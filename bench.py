@@ -54,11 +54,15 @@ FLOPS_PER_SKEL_PAIR = 2
 FLOPS_PER_SYM_PAIR = 13
 FLOPS_PER_SYM_SKEL_PAIR = 4
 # HBM bytes per near-field launch from rocprofv3 FETCH_SIZE + WRITE_SIZE runs of this
-# workload (scaled by a plain 512 MiB copy: x2.000 fetch, x1.000 write), valid only for
-# the kernel, targets-per-lane variant and kernel source they were measured on (first
-# 16 hex digits of the source's sha256).
-NEAR_TRAFFIC = {"f32": {"kernel": "k_near_sym", "targets_per_lane": 3, "kernels_sha256": "4454541f7387769f",
-                         "bytes": 2.8285e9 + 1.0113e9}}
+# workload (scaled by a plain 512 MiB copy: x2.000 fetch, x1.000 write), per
+# targets-per-lane variant, valid only for the kernel and kernel source they were
+# measured on (first 16 hex digits of the source's sha256).
+NEAR_TRAFFIC = {"f32": {"kernel": "k_near_sym", "kernels_sha256": "542e57b9110cce95",
+                        "bytes_by_tpl": {
+                          1: 6.4410e+09 + 2.0518e+09,
+                          2: 3.9893e+09 + 1.5460e+09,
+                          3: 2.8289e+09 + 1.0113e+09,
+                          4: 1.9410e+09 + 7.4405e+08}}}
 
 
 def log(*a):
@@ -318,8 +322,8 @@ def main():
     digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     tr = NEAR_TRAFFIC.get(chosen)
     tpl = tuned.get(chosen, {}).get("targets_per_lane")
-    traffic = (tr["bytes"] if tr and tr["kernels_sha256"] == digest and tr.get("kernel") == dom
-               and tr.get("targets_per_lane") == tpl else None)
+    traffic = (tr["bytes_by_tpl"].get(tpl) if tr and tr["kernels_sha256"] == digest and tr.get("kernel") == dom
+               else None)
     # the same launch against its instruction mix: every evaluation (a symmetric pair,
     # or a one-direction tile pair) priced at the cheapest symmetric-pair cost
     issue_bound = None

@@ -112,6 +112,7 @@ struct DeviceOp {
     DevMem upwork[2], downwork[2];                // [0]: float64 T row groups, [1]: float32
     std::vector<int64_t> up_ptr[2], down_ptr[2];
     std::vector<int> up_nw, down_nw;
+    std::vector<int> up_rows, down_rows;          // per level: most output rows of a box (k up, n - k down)
     int tpl = kDefaultTPL;
     DevMem tasks[SKELFMM_NTPL];                   // work lists for 1 .. 4 targets per lane
     int ntasks[SKELFMM_NTPL] = {};
@@ -177,6 +178,13 @@ static void build_transfer_work(DeviceOp* d) {
     const Layout& L = d->L;
     d->up_nw.assign(L.max_level + 1, 1);
     d->down_nw.assign(L.max_level + 1, 1);
+    d->up_rows.assign(L.max_level + 1, 0);
+    d->down_rows.assign(L.max_level + 1, 0);
+    for (int l = 0; l <= L.max_level; ++l)
+        for (int b = L.level_ptr[l]; b < L.level_ptr[l + 1]; ++b) {
+            d->up_rows[l] = std::max(d->up_rows[l], L.kb[b]);
+            d->down_rows[l] = std::max(d->down_rows[l], L.nb[b] - L.kb[b]);
+        }
     for (int g = 0; g < 2; ++g) {
         // row groups: 64 rows of float64 T, 128 rows of float32 T (one 8-byte load per lane)
         const int G = g == 0 ? kern::RowMap<double>::group : kern::RowMap<float>::group;
@@ -467,8 +475,10 @@ void sweep(DeviceOp* d, const std::vector<IO>& io, int64_t nrhs, int dtype, hipS
         const int b0 = L.level_ptr[l], nbx = L.level_ptr[l + 1] - b0;
         if (nbx <= 0) continue;
         if (multi) {
-            hipLaunchKernelGGL((kern::k_upward_mr<V, TT>), dim3(nbx), dim3(256), 0, s, br, toff, pmap, b0, Wp, T, Q,
-                               Qh);
+            // row chunks of a box spread over the grid's second dimension (4 per block)
+            const int gy = std::max(1, (d->up_rows[l] + 4 * kern::kRB - 1) / (4 * kern::kRB));
+            hipLaunchKernelGGL((kern::k_upward_mr<V, TT>), dim3(nbx, gy), dim3(256), 0, s, br, toff, pmap, b0, Wp,
+                               T, Q, Qh);
         } else {
             const int wg = sizeof(TT) == 4 ? 1 : 0;
             const int64_t w0 = d->up_ptr[wg][l], nwk = d->up_ptr[wg][l + 1] - w0;
@@ -504,8 +514,9 @@ void sweep(DeviceOp* d, const std::vector<IO>& io, int64_t nrhs, int dtype, hipS
         const int b0 = L.level_ptr[l], nbx = L.level_ptr[l + 1] - b0;
         if (nbx <= 0) continue;
         if (multi) {
-            hipLaunchKernelGGL((kern::k_downward_mr<V, TT>), dim3(nbx), dim3(256), 0, s, br, ttoff, pmap, b0, Wp, Tt,
-                               Uh, U);
+            const int gy = std::max(1, (d->down_rows[l] + 4 * kern::kRB - 1) / (4 * kern::kRB));
+            hipLaunchKernelGGL((kern::k_downward_mr<V, TT>), dim3(nbx, gy), dim3(256), 0, s, br, ttoff, pmap, b0, Wp,
+                               Tt, Uh, U);
         } else {
             const int wg = sizeof(TT) == 4 ? 1 : 0;
             const int64_t w0 = d->down_ptr[wg][l], nwk = d->down_ptr[wg][l + 1] - w0;

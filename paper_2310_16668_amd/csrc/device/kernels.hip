@@ -1181,7 +1181,7 @@ __global__ void __launch_bounds__(256) k_upward_mr(const BoxRec* __restrict__ bo
     for (int c0 = 0; c0 < Wp; c0 += 64) {
         const int c = c0 + lane;
         const bool act = c < Wp;
-        for (int r0 = wave * kRB; r0 < k; r0 += 4 * kRB) {
+        for (int r0 = (blockIdx.y * 4 + wave) * kRB; r0 < k; r0 += gridDim.y * 4 * kRB) {
             double acc[kRB];
 #pragma unroll
             for (int rr = 0; rr < kRB; ++rr) acc[rr] = 0.0;
@@ -1232,7 +1232,7 @@ __global__ void __launch_bounds__(256) k_downward_mr(const BoxRec* __restrict__ 
         const bool act = c < Wp;
         // redundant rows (reads uhat inputs: this box's Uh and the parent's U,
         // never this box's own skeleton entries, which the loop after updates)
-        for (int r0 = wave * kRB; r0 < m; r0 += 4 * kRB) {
+        for (int r0 = (blockIdx.y * 4 + wave) * kRB; r0 < m; r0 += gridDim.y * 4 * kRB) {
             double acc[kRB];
 #pragma unroll
             for (int rr = 0; rr < kRB; ++rr) acc[rr] = 0.0;
@@ -1260,8 +1260,8 @@ __global__ void __launch_bounds__(256) k_downward_mr(const BoxRec* __restrict__ 
                 }
             }
         }
-        // skeleton rows
-        for (int i = wave; i < k && act; i += 4) {
+        // skeleton rows (once per box: the blocks of row 0 of the grid)
+        for (int i = wave; i < k && act && blockIdx.y == 0; i += 4) {
             const double uh = static_cast<double>(Uh[(tb.hoff + i) * Wp + c]) +
                               static_cast<double>(U[static_cast<int64_t>(pmap[tb.hoff + i]) * Wp + c]);
             U[(tb.voff + i) * Wp + c] = static_cast<V>(static_cast<double>(U[(tb.voff + i) * Wp + c]) + uh);
