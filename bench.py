@@ -5,22 +5,31 @@
 A step is one forward apply u = Atilde q followed by one adjoint apply
 w = Atilde^H v (the whole GPU sweep each: gather, upward pass, near field,
 downward pass, output), inputs resident in HBM.  value = N * nrhs / (time of
-one step).  The run also reports each path's error against the float64 dense
-sum on 2,048 random targets, the near-field kernel's arithmetic roofline (HIP
-events around that pass, on the apply's stream), the transfer passes' HBM
-rate, and the CPU oracle timed on a bounded sample of the same workload.
+one step).  The timed region holds the K steps only; per-kernel durations (the
+roofline) come from a second, separate run of the same steps with the
+library's HIP events around every pass on the apply's stream.
 
-It also times the eight-geometry, 64-RHS float32 batch (one captured hipGraph
-holding a batched forward and a batched adjoint sweep) and reports it beside
-the float64 single-RHS rate of the 1M cube.
+Beside the headline the run reports, each with its error against the float64
+dense sum on random targets (relative l2 and max|e| / max|u|):
+  * both precision paths of the 1M cube (float64, float32);
+  * the float32 apply of 64 right-hand sides on the same 1M operator (the
+    matrix-core path), against the float64 single-RHS apply at that accuracy;
+  * the 4M-point ellipsoid (float32, compensated leaf sums);
+  * the 1M-point Helmholtz cube (complex64 with float64 leaf sums, forward and
+    conjugated adjoint);
+  * the eight-geometry, 64-RHS float32 batch (one captured hipGraph holding a
+    batched forward and a batched adjoint sweep);
+  * the CPU oracle timed on a bounded sample of the headline workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--only f32|f64]
+       [--headline-only] [--batched-only]
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -34,6 +43,8 @@ sys.path.insert(0, ROOT)
 # cycles per wave of 64 -- and float64 78.6 TFLOP/s (four cycles per wave).  Each
 # path is priced against the peak of its evaluation type.
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
+# Dense float32 matrix-core peak (published), for the many-RHS kernels.
+PEAK_MFMA_F32_TFLOPS = 157.3
 # Issue cycles per wave instruction (64 lanes) used for the instruction-mix bound of
 # the float32 pair kernel: float64 add / multiply-add and the float64 -> float32
 # conversion 4, float32 multiply-add 2, reciprocal square root 16.  The cheapest
@@ -53,16 +64,46 @@ FLOPS_PER_PAIR = 11
 FLOPS_PER_SKEL_PAIR = 2
 FLOPS_PER_SYM_PAIR = 13
 FLOPS_PER_SYM_SKEL_PAIR = 4
+# One 3D Helmholtz pair: 3 subtractions, |d|^2 (5), reciprocal square root with one
+# Newton step (5), r and kappa r (2), sincos (1), the kernel's real and imaginary
+# parts (2), one complex multiply-add into u (8); a skeleton pair adds a complex
+# multiply-add into uhat (8).  Transcendentals count one flop each.
+FLOPS_PER_HELM_PAIR = 26
+FLOPS_PER_HELM_SKEL_PAIR = 8
 # HBM bytes per near-field launch from rocprofv3 FETCH_SIZE + WRITE_SIZE runs of this
 # workload (scaled by a plain 512 MiB copy: x2.000 fetch, x1.000 write), per
 # targets-per-lane variant, valid only for the kernel and kernel source they were
-# measured on (first 16 hex digits of the source's sha256).
+# measured on (first 16 hex digits of the sha256 of the pair kernel's section of
+# kernels.hip, pair_kernel_digest).
 NEAR_TRAFFIC = {"f32": {"kernel": "k_near_sym", "kernels_sha256": "542e57b9110cce95",
                         "bytes_by_tpl": {
                           1: 6.4410e+09 + 2.0518e+09,
                           2: 3.9893e+09 + 1.5460e+09,
                           3: 2.8289e+09 + 1.0113e+09,
                           4: 1.9410e+09 + 7.4405e+08}}}
+
+
+PAIR_KERNEL_BEGIN = "// symmetric near field (real kernels, one right-hand side)"
+PAIR_KERNEL_END = "// many right-hand sides on the matrix cores (real kernels, float32 policy)"
+
+
+def pair_kernel_digest() -> str:
+    """sha256 (16 hex digits) of the pair kernel's section of kernels.hip (k_near_sym and
+    k_sym_reduce, between the two section banners)."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_2310_16668_amd", "csrc", "device", "kernels.hip")
+    text = open(src, encoding="utf-8").read()
+    i, j = text.index(PAIR_KERNEL_BEGIN), text.index(PAIR_KERNEL_END)
+    return hashlib.sha256(text[i:j].encode()).hexdigest()[:16]
+
+
+def near_traffic(path: str, kernel: str, tpl):
+    """HBM bytes per launch carried in NEAR_TRAFFIC, or None when they were taken on
+    another kernel, another launch shape or another source of the pair kernel."""
+    tr = NEAR_TRAFFIC.get(path)
+    if not tr or tr.get("kernel") != kernel or tr["kernels_sha256"] != pair_kernel_digest():
+        return None
+    return tr["bytes_by_tpl"].get(tpl)
 
 
 def log(*a):
@@ -81,11 +122,117 @@ def parse():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run one plain device-to-device copy of MIB MiB (counter calibration)")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="time the 1M cube only (no 64-RHS, ellipsoid, Helmholtz or batched legs)")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the eight-geometry, 64-RHS float32 batched measurement")
     ap.add_argument("--batched-only", action="store_true",
                     help="run only the batched measurement and print its object (for profiling)")
     return ap.parse_args()
+
+
+# ---------------------------------------------------------------------------
+# measurement helpers
+# ---------------------------------------------------------------------------
+def errors(u, ref) -> dict:
+    """relative l2 and max|e| / max|u| (the paper's measure) of u against ref."""
+    u, ref = np.asarray(u), np.asarray(ref)
+    return {"rel_l2": float(np.linalg.norm(u - ref) / np.linalg.norm(ref)),
+            "max_rel": float(np.max(np.abs(u - ref)) / np.max(np.abs(ref)))}
+
+
+def clocks() -> dict | None:
+    """Current shader and memory clocks of GPU 0 as rocm-smi reports them (None if it cannot)."""
+    try:
+        r = subprocess.run(["rocm-smi", "--showclocks", "--json"], capture_output=True, text=True, timeout=20)
+        d = json.loads(r.stdout)
+        card = d[sorted(d)[0]]
+        out = {}
+        for k, v in card.items():
+            kl = k.lower()
+            if "sclk" in kl and "sclk" not in out:
+                out["sclk"] = v
+            if "mclk" in kl and "mclk" not in out:
+                out["mclk"] = v
+        return out or None
+    except Exception:
+        return None
+
+
+def timed_steps(step, steps: int, warmup: int) -> float:
+    """ms per step over `steps` calls of step() between device synchronisations
+    (after `warmup` untimed calls)."""
+    import torch
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def pass_times(obj, step, steps: int) -> dict:
+    """ms per sweep of every pass, from the library's HIP events over `steps`
+    further calls of step() (a separate run from the timed region)."""
+    import torch
+    obj.timing(True)
+    torch.cuda.synchronize()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    t = obj.timing_read()
+    obj.timing(False)
+    n = max(t.pop("sweeps"), 1)
+    return {k: v / n for k, v in t.items()}
+
+
+def near_kernels(st: dict, pm: dict, helm: bool = False) -> dict:
+    """(ms per launch, algorithmic flops per launch) of the near-field kernels."""
+    pairs_ns = st["pairs_near"] - 2 * st["pairs_sym"] - st["pairs_tile"]
+    skel_ns = st["pairs_skel"] - 2 * st["pairs_sym_skel"] - st["pairs_tile_skel"]
+    if helm:
+        return {"k_near": (pm["near_field"], FLOPS_PER_HELM_PAIR * pairs_ns + FLOPS_PER_HELM_SKEL_PAIR * skel_ns)}
+    return {
+        "k_near": (pm["near_field"], FLOPS_PER_PAIR * pairs_ns + FLOPS_PER_SKEL_PAIR * skel_ns),
+        "k_near_sym": (pm["near_pairs"], FLOPS_PER_SYM_PAIR * st["pairs_sym"]
+                       + FLOPS_PER_SYM_SKEL_PAIR * st["pairs_sym_skel"]
+                       + FLOPS_PER_PAIR * st["pairs_tile"] + FLOPS_PER_SKEL_PAIR * st["pairs_tile_skel"]),
+    }
+
+
+def transfer_figures(st: dict, pm: dict, s_bytes: int, width: int = 1, mfma: bool = False) -> dict:
+    """HBM (and, on the matrix cores, MFMA) rate of the upward + downward passes: each
+    reads every T once (sum k (n - k) entries) and the vectors of its entries
+    (width reals per entry)."""
+    t_bytes = st["m_proj_elems"] * s_bytes
+    vec_bytes = st["n_entries"] * s_bytes * 4 * width
+    ms = pm["upward"] + pm["downward"]
+    out = {"bound": "mfma" if mfma else "hbm", "bytes_per_sweep": 2 * (t_bytes + vec_bytes),
+           "ms_per_sweep": ms, "achieved_GBs": 2 * (t_bytes + vec_bytes) / (ms * 1e-3) / 1e9,
+           "peak_GBs": PEAK_HBM_GBS}
+    out["hbm_frac"] = out["achieved_GBs"] / PEAK_HBM_GBS
+    if mfma:
+        flops = 2 * 2 * st["m_proj_elems"] * width
+        out["flops_per_sweep"] = flops
+        out["achieved_TFLOPs"] = flops / (ms * 1e-3) / 1e12
+        out["peak_TFLOPs"] = PEAK_MFMA_F32_TFLOPS
+        out["mfma_frac"] = out["achieved_TFLOPs"] / PEAK_MFMA_F32_TFLOPS
+    return out
+
+
+def mfma_near_figures(st: dict, pm: dict, nrhs: int) -> dict:
+    """Matrix-core rate of the many-RHS near field: 2 flops per (pair evaluation, column)."""
+    ms = pm["near_field"]
+    flops = 2 * st["pairs_near"] * nrhs
+    out = {"bound": "mfma", "ms_per_sweep": ms, "mfma_flops_per_sweep": flops,
+           "achieved_TFLOPs": flops / (ms * 1e-3) / 1e12, "peak_TFLOPs": PEAK_MFMA_F32_TFLOPS}
+    out["frac"] = out["achieved_TFLOPs"] / PEAK_MFMA_F32_TFLOPS
+    return out
 
 
 def pair_counts(P) -> np.ndarray:
@@ -117,11 +264,13 @@ def pair_counts(P) -> np.ndarray:
 
 
 def cpu_baseline(P, q, v, budget_s: float, nrhs: int = 1):
-    """Time the oracle's float64 apply (O2) of the same skeleton operators on the
-    host cores: the full forward apply, then the full adjoint apply when both fit
-    the budget.  A forward apply longer than the budget is instead timed on a
-    random sample of target boxes (upward and downward passes in full) and
-    scaled by the pair counts, with the adjoint taken equal to it."""
+    """The oracle's float64 apply (O2) of the same skeleton operators on the host
+    cores, on a bounded sample: the translations of a random sample of target
+    boxes (sized so one sampled apply takes about a tenth of the budget) with the
+    upward and downward passes in full; one warm-up run, then the median of
+    three, scaled to the whole workload by the pair counts.  The oracle samples
+    the forward apply only (its adjoint visits the same pairs), so a step
+    (forward + adjoint) is taken as twice the forward."""
     import oracle
 
     n = P["points"].shape[0]
@@ -129,88 +278,204 @@ def cpu_baseline(P, q, v, budget_s: float, nrhs: int = 1):
     cnt = pair_counts(P)
     total = cnt.sum()
     rng = np.random.default_rng(77)
+    # calibration: the passes alone, then a 2% sample
     mask0 = np.zeros(P["n_boxes"], dtype=np.uint8)
     t0 = time.perf_counter()
     oracle.apply(P, q, box_mask=mask0)
     t_base = time.perf_counter() - t0
-    frac = 5e-2
-    mask = (rng.random(P["n_boxes"]) < frac).astype(np.uint8)
+    mask = (rng.random(P["n_boxes"]) < 0.02).astype(np.uint8)
     t0 = time.perf_counter()
     oracle.apply(P, q, box_mask=mask)
     t_cal = max(time.perf_counter() - t0 - t_base, 1e-3)
-    est_full = t_base + t_cal * total / max(cnt[mask == 1].sum(), 1.0)
-    if est_full <= budget_s:
-        t0 = time.perf_counter()
-        oracle.apply(P, q)
-        t_f = time.perf_counter() - t0
-        if 2 * t_f <= 1.5 * budget_s:
-            t0 = time.perf_counter()
-            oracle.apply(P, v, adjoint=True)
-            t_a = time.perf_counter() - t0
-            return {"value": n * nrhs / (t_f + t_a), "unit": "points/s", "cores": cores, "kind": "oracle",
-                    "sample": (f"CPU float64 apply (oracle O2) of the same skeleton operators, whole workload: "
-                               f"forward {t_f:.1f}s + adjoint {t_a:.1f}s")}
-        return {"value": n * nrhs / (2 * t_f), "unit": "points/s", "cores": cores, "kind": "oracle",
-                "sample": (f"CPU float64 apply (oracle O2) of the same skeleton operators: full forward "
-                           f"{t_f:.1f}s, adjoint taken equal")}
-    frac = min(1.0, budget_s * (total / max(est_full - t_base, 1e-3)) / total)
+    per_pair = t_cal / max(cnt[mask == 1].sum(), 1.0)
+    target = max(budget_s / 10 - t_base, 0.2)
+    frac = min(1.0, target / max(per_pair * total, 1e-9))
     mask = (rng.random(P["n_boxes"]) < frac).astype(np.uint8)
-    t0 = time.perf_counter()
-    oracle.apply(P, q, box_mask=mask)
-    t_s = time.perf_counter() - t0
     sampled = cnt[mask == 1].sum()
-    t_full = t_base + (t_s - t_base) * total / max(sampled, 1.0)
+    runs = []
+    for rep in range(4):
+        t0 = time.perf_counter()
+        oracle.apply(P, q, box_mask=mask)
+        if rep > 0:
+            runs.append(time.perf_counter() - t0)
+    t_s = sorted(runs)[1]
+    t_fwd = t_base + (t_s - t_base) * total / max(sampled, 1.0)
     return {
-        "value": n * nrhs / (2.0 * t_full),
+        "value": n * nrhs / (2.0 * t_fwd),
         "unit": "points/s",
         "cores": cores,
         "kind": "oracle",
         "sample": (f"CPU float64 apply (oracle O2) of the same skeleton operators; translations for "
                    f"{int(mask.sum())} of {P['n_boxes']} target boxes ({100 * sampled / total:.2f}% of "
-                   f"{total:.3e} pair evaluations) in {t_s:.1f}s, upward/downward passes in full "
-                   f"({t_base:.1f}s); forward+adjoint time extrapolated as 2 x {t_full:.1f}s"),
+                   f"{total:.3e} pair evaluations), upward/downward passes in full ({t_base:.2f}s); 1 warm-up "
+                   f"then the median of 3 runs ({t_s:.2f}s), scaled by pair counts to a {t_fwd:.1f}s forward "
+                   f"apply; forward + adjoint taken as twice that"),
     }
 
 
-def batched_run(steps: int, warmup: int):
+# ---------------------------------------------------------------------------
+# legs
+# ---------------------------------------------------------------------------
+def many_rhs_same_operator(op, w, x, steps, warmup, f64_rate):
+    """64 float32 right-hand sides on the 1M cube's operator (matrix-core near field
+    and transfers): forward + adjoint points x RHS/s against the float64 single-RHS
+    rate of the same operator, errors against the dense sum on 4 columns at 2,048
+    targets."""
+    import torch
+
+    import oracle
+    nrhs = 64
+    dev = torch.device("cuda:0")
+    Qh = w.charges(nrhs)
+    Vh = w.weights(nrhs)
+    Q = torch.from_numpy(Qh).to(dev, torch.float32)
+    V = torch.from_numpy(Vh).to(dev, torch.float32)
+    op.prepare(nrhs, torch.float32)
+    xfer = op.autotune_transfers(nrhs)
+    holder = {}
+
+    def step():
+        holder["u"] = op.apply(Q)
+        holder["w"] = op.apply_adjoint(V)
+
+    ms = timed_steps(step, steps, warmup)
+    pm = pass_times(op, step, max(3, steps // 2))
+    st = op.stats()
+    rate = w.n * nrhs / (ms * 1e-3)
+    res = {"value": rate, "unit": "points x RHS/s (fwd+adjoint)", "ms_per_step": ms, "nrhs": nrhs, "dtype": "f32",
+           "transfer_shape": xfer, "passes_ms_per_sweep": pm, "f64_single_rhs_points_per_s": f64_rate,
+           "ratio_to_f64_single_rhs": rate / f64_rate,
+           "roofline": {"transfers": transfer_figures(st, pm, 4, nrhs, mfma=True),
+                        "near_field": mfma_near_figures(st, pm, nrhs)}}
+    tg = w.targets()
+    cols = [0, 21, 42, 63]
+    U = holder["u"].double().cpu().numpy()
+    W = holder["w"].double().cpu().numpy()
+    Qr = Qh.astype(np.float32).astype(np.float64)
+    Vr = Vh.astype(np.float32).astype(np.float64)
+    ref_u = np.stack([oracle.direct(x, np.ascontiguousarray(Qr[:, c]), targets=tg) for c in cols], axis=1)
+    ref_w = np.stack([oracle.direct(x, np.ascontiguousarray(Vr[:, c]), targets=tg) for c in cols], axis=1)
+    res["error_vs_direct"] = errors(U[np.ix_(tg, cols)], ref_u)
+    res["adjoint_error_vs_direct"] = errors(W[np.ix_(tg, cols)], ref_w)
+    return res
+
+
+def single_leg(name, op, q_h, v_h, x, kind, kappa, tdt, targets, steps, warmup, helm=False):
+    """One operator, one RHS: forward + adjoint timed, per-pass figures, errors vs O1."""
+    import torch
+
+    import oracle
+    dev = torch.device("cuda:0")
+    op.prepare(1, tdt)
+    tuned = op.autotune(tdt)
+    q = torch.from_numpy(q_h).to(dev, tdt)
+    v = torch.from_numpy(v_h).to(dev, tdt)
+    holder = {}
+
+    def step():
+        holder["u"] = op.apply(q)
+        holder["w"] = op.apply_adjoint(v)
+
+    ms = timed_steps(step, steps, warmup)
+    pm = pass_times(op, step, max(3, steps // 2))
+    st = op.stats()
+    ker = near_kernels(st, pm, helm)
+    dom = max(ker, key=lambda k: ker[k][0])
+    f64_eval = tdt in (torch.float64, torch.complex128) or helm
+    peak = PEAK_TFLOPS["f64" if f64_eval else "f32"]
+    n = x.shape[0]
+    s_bytes = 8 if tdt in (torch.float64, torch.complex128) else 4
+    res = {"value": n / (ms * 1e-3), "unit": "points/s (fwd+adjoint)", "ms_per_step": ms, "autotune": tuned,
+           "passes_ms_per_sweep": pm,
+           "roofline": {"bound": "alu", "kernel": dom, "ms_per_launch": ker[dom][0],
+                        "achieved": ker[dom][1] / (ker[dom][0] * 1e-3) / 1e12, "peak": peak, "unit": "TFLOP/s",
+                        "pair_evaluations_per_launch": st["pairs_near"] - st["pairs_sym"]},
+           "transfers": transfer_figures(st, pm, s_bytes, 2 if helm else 1)}
+    res["roofline"]["frac"] = res["roofline"]["achieved"] / peak
+    up = np.complex128 if helm else np.float64
+    u = holder["u"].cpu().numpy().astype(up)
+    wv = holder["w"].cpu().numpy().astype(up)
+    cast = {torch.float32: np.float32, torch.complex64: np.complex64}.get(tdt)
+    qr = q_h.astype(cast).astype(q_h.dtype) if cast else q_h
+    vr = v_h.astype(cast).astype(v_h.dtype) if cast else v_h
+    res["error_vs_direct"] = errors(u[targets], oracle.direct(x, qr, kind, kappa, targets=targets))
+    # A^H v = conj(A conj v) for the complex-symmetric kernel (A for Laplace)
+    ref_w = (np.conj(oracle.direct(x, np.conj(vr), kind, kappa, targets=targets)) if helm
+             else oracle.direct(x, vr, kind, kappa, targets=targets))
+    res["adjoint_error_vs_direct"] = errors(wv[targets], ref_w)
+    log(f"[bench] {name}: {ms:.3f} ms/step err {res['error_vs_direct']} adj {res['adjoint_error_vs_direct']}")
+    return res
+
+
+def batched_run(steps: int, warmup: int, check: bool = True):
     """Eight 3D Laplace geometries (65,536 .. 2,097,152 points, cube / ellipsoid,
     tol 1e-6, leaf 128), 64 float32 right-hand sides each: one captured hipGraph
     holds a batched forward sweep and a batched adjoint sweep; value = total
-    points x RHS per second of that step."""
+    points x RHS per second of that step.  Per-pass figures come from separate
+    eager batched sweeps with the library's events; the adjoint sweep's output
+    (the gradient A^T w of L = sum(w u)) and the forward are checked against the
+    dense sum on 4 columns at 256 targets per geometry."""
     import torch
 
+    import oracle
     import workloads
     import paper_2310_16668_amd as sk
 
     wls = workloads.batch_workloads()
     t0 = time.perf_counter()
-    ops = [sk.build(w.points(), "laplace", tol=w.tol, leaf_size=w.leaf_size) for w in wls]
+    xs = [w.points() for w in wls]
+    ops = [sk.build(x, "laplace", tol=w.tol, leaf_size=w.leaf_size) for x, w in zip(xs, wls)]
     t_build = time.perf_counter() - t0
     batch = sk.Batch(ops)
     dev = torch.device("cuda:0")
-    q = [torch.from_numpy(w.charges()).to(dev, torch.float32) for w in wls]
-    v = [torch.from_numpy(w.weights()).to(dev, torch.float32) for w in wls]
-    batch.apply(q)
-    batch.apply(v, adjoint=True)
+    q_h = [w.charges() for w in wls]
+    v_h = [w.weights() for w in wls]
+    q = [torch.from_numpy(a).to(dev, torch.float32) for a in q_h]
+    v = [torch.from_numpy(a).to(dev, torch.float32) for a in v_h]
+    xfer = batch.autotune_transfers(64)
+    log(f"[bench] batched transfer shapes (ms per up + down pass pair): {xfer}")
+    outs = {}
+
+    def eager():
+        outs["u"] = batch.apply(q)
+        outs["w"] = batch.apply(v, adjoint=True)
+
+    eager()
     torch.cuda.synchronize()
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
-        batch.apply(q)
-        batch.apply(v, adjoint=True)
-    for _ in range(warmup):
-        graph.replay()
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(steps):
-        graph.replay()
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / steps
+        gu = batch.apply(q)
+        gw = batch.apply(v, adjoint=True)
+    ms = timed_steps(graph.replay, steps, warmup)
+    pm = pass_times(batch, eager, max(3, steps // 2))
     n_total = sum(w.n for w in wls)
-    return {"value": n_total * 64 / (ms * 1e-3), "unit": "points x RHS/s (fwd+adjoint)", "ms_per_step": ms,
-            "n_total": n_total, "sizes": [w.n for w in wls], "nrhs": 64, "dtype": "f32", "graph": True,
-            "build_s": t_build}
+    sts = [o.stats() for o in ops]
+    st = {k: sum(s[k] for s in sts) for k in ("m_proj_elems", "n_entries", "pairs_near", "pairs_skel")}
+    res = {"value": n_total * 64 / (ms * 1e-3), "unit": "points x RHS/s (fwd+adjoint)", "ms_per_step": ms,
+           "n_total": n_total, "sizes": [w.n for w in wls], "nrhs": 64, "dtype": "f32", "graph": True,
+           "build_s": t_build, "transfer_shape": xfer, "passes_ms_per_sweep": pm,
+           "roofline": {"transfers": transfer_figures(st, pm, 4, 64, mfma=True),
+                        "near_field": mfma_near_figures(st, pm, 64)}}
+    if check:
+        graph.replay()
+        torch.cuda.synchronize()
+        e_u, e_w = [], []
+        cols = [0, 21, 42, 63]
+        for g, w in enumerate(wls):
+            tg = w.targets(256)
+            qr = q_h[g].astype(np.float32).astype(np.float64)
+            vr = v_h[g].astype(np.float32).astype(np.float64)
+            U = gu[g].double().cpu().numpy()[np.ix_(tg, cols)]
+            W = gw[g].double().cpu().numpy()[np.ix_(tg, cols)]
+            ru = np.stack([oracle.direct(xs[g], np.ascontiguousarray(qr[:, c]), targets=tg) for c in cols], axis=1)
+            rw = np.stack([oracle.direct(xs[g], np.ascontiguousarray(vr[:, c]), targets=tg) for c in cols], axis=1)
+            e_u.append(errors(U, ru))
+            e_w.append(errors(W, rw))
+        res["error_vs_direct"] = {"rel_l2_max_over_geometries": max(e["rel_l2"] for e in e_u),
+                                  "max_rel_max_over_geometries": max(e["max_rel"] for e in e_u)}
+        res["gradient_error_vs_dense_ATw"] = {"rel_l2_max_over_geometries": max(e["rel_l2"] for e in e_w),
+                                              "max_rel_max_over_geometries": max(e["max_rel"] for e in e_w)}
+    return res
 
 
 def main():
@@ -219,7 +484,7 @@ def main():
         print(json.dumps({"error": "one GPU per run: --gpus must be 1 (the apply does not shard across GPUs)"}))
         return 2
     if args.batched_only:
-        print(json.dumps({"batched": batched_run(args.steps, args.warmup)}))
+        print(json.dumps({"batched": batched_run(args.steps, args.warmup, check=False)}))
         return 0
     import torch
 
@@ -239,7 +504,6 @@ def main():
         f"pairs={st['pairs_near']:.3e} skel_pairs={st['pairs_skel']:.3e}")
 
     dev = torch.device("cuda:0")
-    stream = torch.cuda.current_stream(dev)
     results = {}
     if args.calibrate_copy:
         nb = args.calibrate_copy << 20
@@ -254,6 +518,7 @@ def main():
     if args.only:
         paths = [p for p in paths if p[0] == args.only]
     tuned = {}
+    clk = {"before": clocks()}
     for dt_name, tdt in paths:
         op.prepare(1, tdt)
         if not args.no_autotune:
@@ -261,33 +526,28 @@ def main():
             log(f"[bench] {dt_name} autotune {tuned[dt_name]}")
         q = torch.from_numpy(q_h).to(dev, tdt)
         v = torch.from_numpy(v_h).to(dev, tdt)
-        for _ in range(args.warmup):
-            op.apply(q)
-            op.apply_adjoint(v)
-        # the timed region: K steps; the library records HIP events around each
-        # pass on the apply's stream (the per-kernel durations of the roofline)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        op.timing(True)
-        torch.cuda.synchronize()
-        e0.record(stream)
-        for _ in range(args.steps):
-            u = op.apply(q)
-            wv = op.apply_adjoint(v)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ms_step = e0.elapsed_time(e1) / args.steps
-        passes = op.timing_read()
-        op.timing(False)
-        res = {"ms_per_step": ms_step, "passes_ms_per_sweep": {k: passes[k] / passes["sweeps"] for k in sk.PASSES}}
+        holder = {}
+
+        def step():
+            holder["u"] = op.apply(q)
+            holder["w"] = op.apply_adjoint(v)
+
+        # the timed region: K steps and nothing else
+        ms_step = timed_steps(step, args.steps, args.warmup)
+        clk["after_" + dt_name] = clocks()
+        # per-pass durations: a separate run of the same steps with HIP events
+        pm = pass_times(op, step, args.steps)
+        res = {"ms_per_step": ms_step, "passes_ms_per_sweep": pm}
         if not args.profile_only:
             import oracle
             tg = w.targets()
-            u1 = oracle.direct(x, q_h, targets=tg)
-            uu = u.double().cpu().numpy()
-            res["relerr_vs_direct"] = float(np.linalg.norm(uu[tg] - u1) / np.linalg.norm(u1))
-            ww = wv.double().cpu().numpy()
-            w1 = oracle.direct(x, v_h, targets=tg)   # Laplace: A^H = A
-            res["relerr_adjoint_vs_direct"] = float(np.linalg.norm(ww[tg] - w1) / np.linalg.norm(w1))
+            cast = np.float32 if tdt == torch.float32 else np.float64
+            qr = q_h.astype(cast).astype(np.float64)
+            vr = v_h.astype(cast).astype(np.float64)
+            e = errors(holder["u"].double().cpu().numpy()[tg], oracle.direct(x, qr, targets=tg))
+            ea = errors(holder["w"].double().cpu().numpy()[tg], oracle.direct(x, vr, targets=tg))  # A^H = A
+            res["relerr_vs_direct"], res["maxrel_vs_direct"] = e["rel_l2"], e["max_rel"]
+            res["relerr_adjoint_vs_direct"], res["maxrel_adjoint_vs_direct"] = ea["rel_l2"], ea["max_rel"]
         results[dt_name] = res
         log(f"[bench] {dt_name}: {ms_step:.3f} ms/step {res}")
 
@@ -304,26 +564,12 @@ def main():
     if chosen in tuned:
         op.set_targets_per_lane(tuned[chosen]["targets_per_lane"])
     st = op.stats()
-    # pairs left to k_near after symmetric pairing (each paired evaluation covers two)
-    pairs_ns = st["pairs_near"] - 2 * st["pairs_sym"] - st["pairs_tile"]
-    skel_ns = st["pairs_skel"] - 2 * st["pairs_sym_skel"] - st["pairs_tile_skel"]
-    # per near-field kernel: (ms per launch, algorithmic flops per launch)
-    kernels = {
-        "k_near": (pm["near_field"], FLOPS_PER_PAIR * pairs_ns + FLOPS_PER_SKEL_PAIR * skel_ns),
-        "k_near_sym": (pm["near_pairs"], FLOPS_PER_SYM_PAIR * st["pairs_sym"]
-                       + FLOPS_PER_SYM_SKEL_PAIR * st["pairs_sym_skel"]
-                       + FLOPS_PER_PAIR * st["pairs_tile"] + FLOPS_PER_SKEL_PAIR * st["pairs_tile_skel"]),
-    }
+    kernels = near_kernels(st, pm)
     dom = max(kernels, key=lambda k: kernels[k][0])
     near_ms, flops = kernels[dom]
     achieved = flops / (near_ms * 1e-3) / 1e12
-    import hashlib
-    src = os.path.join(ROOT, "paper_2310_16668_amd", "csrc", "device", "kernels.hip")
-    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    tr = NEAR_TRAFFIC.get(chosen)
     tpl = tuned.get(chosen, {}).get("targets_per_lane")
-    traffic = (tr["bytes_by_tpl"].get(tpl) if tr and tr["kernels_sha256"] == digest and tr.get("kernel") == dom
-               else None)
+    traffic = near_traffic(chosen, dom, tpl)
     # the same launch against its instruction mix: every evaluation (a symmetric pair,
     # or a one-direction tile pair) priced at the cheapest symmetric-pair cost
     issue_bound = None
@@ -333,11 +579,8 @@ def main():
         issue_bound = {"cycles_per_64_pairs_ideal": MIX_CYCLES_PER_64_SYM_PAIRS[chosen],
                        "cycles_per_64_pairs_achieved": near_ms * 1e-3 * CLOCK_GHZ * 1e9 * SIMDS / (evals / 64),
                        "ideal_ms": ideal_ms, "frac": ideal_ms / near_ms}
-    sT = 8 if chosen == "f64" else 4
-    # upward and downward each read every T once, plus their vectors (n and k entries)
-    t_bytes = st["m_proj_elems"] * sT
-    vec_bytes = st["n_entries"] * sT * 4
-    trans_ms = r["passes_ms_per_sweep"]["upward"] + r["passes_ms_per_sweep"]["downward"]
+    pairs_ns = st["pairs_near"] - 2 * st["pairs_sym"] - st["pairs_tile"]
+    skel_ns = st["pairs_skel"] - 2 * st["pairs_sym_skel"] - st["pairs_tile_skel"]
     out = {
         "metric": "apply points/s (fwd+adjoint), 3D Laplace N=1M @1e-6 rel err; % HBM/VALU roofline",
         "value": w.n / (r["ms_per_step"] * 1e-3),
@@ -363,22 +606,49 @@ def main():
                      "near_kernels": {k: {"ms": v[0], "tflops": v[1] / (v[0] * 1e-3) / 1e12 if v[0] > 0 else None}
                                       for k, v in kernels.items()},
                      "near_reduce_ms": pm["near_reduce"]},
-        "transfer_passes": {"bound": "hbm", "bytes_per_sweep": 2 * (t_bytes + vec_bytes),
-                            "ms_per_sweep": trans_ms,
-                            "achieved_GBs": 2 * (t_bytes + vec_bytes) / (trans_ms * 1e-3) / 1e9,
-                            "peak_GBs": PEAK_HBM_GBS},
+        "transfer_passes": transfer_figures(st, pm, 8 if chosen == "f64" else 4),
         "paths": results,
         "autotune": tuned,
+        "clocks": clk,
         "build_s": t_build,
     }
-    if not args.no_batched and not args.profile_only:
+    f64_rate = w.n / (results["f64"]["ms_per_step"] * 1e-3) if "f64" in results else None
+    legs = not (args.headline_only or args.profile_only)
+    if legs and f64_rate:
+        log("[bench] 64 float32 RHS on the same operator")
+        out["many_rhs_same_operator"] = many_rhs_same_operator(op, w, x, args.steps, args.warmup, f64_rate)
+        log(f"[bench] many RHS: {out['many_rhs_same_operator']}")
+    if legs:
+        we = workloads.LAPLACE3D_ELLIPSOID_4M
+        log(f"[bench] building {we.name}")
+        xe = we.points()
+        t0 = time.perf_counter()
+        ope = sk.build(xe, "laplace", tol=we.tol, leaf_size=we.leaf_size, compensated_leaf=True)
+        tb = time.perf_counter() - t0
+        leg = single_leg(we.name, ope, we.charges(), we.weights(), xe, "laplace", 0.0, torch.float32,
+                         we.targets(), args.steps, args.warmup)
+        leg.update({"config": {"workload": we.name, "n": we.n, "tol": we.tol, "leaf_size": we.leaf_size,
+                               "dtype": "f32", "compensated_leaf": True}, "build_s": tb})
+        out["ellipsoid_4m"] = leg
+        del ope
+        wh = workloads.HELMHOLTZ3D_1M
+        log(f"[bench] building {wh.name}")
+        xh = wh.points()
+        t0 = time.perf_counter()
+        oph = sk.build(xh, "helmholtz", tol=wh.tol, leaf_size=wh.leaf_size, kappa=wh.kappa, f64_leaf=True)
+        tb = time.perf_counter() - t0
+        vh = workloads.charges(wh.n, 1, 1300 + wh.number, complex_=True)
+        leg = single_leg(wh.name, oph, wh.charges(), vh, xh, "helmholtz", wh.kappa, torch.complex64, wh.targets(),
+                         args.steps, args.warmup, helm=True)
+        leg.update({"config": {"workload": wh.name, "n": wh.n, "tol": wh.tol, "leaf_size": wh.leaf_size,
+                               "kappa": wh.kappa, "dtype": "c64", "f64_leaf": True}, "build_s": tb})
+        out["helmholtz_1m"] = leg
+        del oph
+    if legs and not args.no_batched:
         log("[bench] eight-geometry batched run")
         bt = batched_run(args.steps, args.warmup)
-        if "f64" in results:
-            # the float64 single-RHS apply (fwd + adjoint) of the 1M cube, for comparison
-            f64_rate = w.n / (results["f64"]["ms_per_step"] * 1e-3)
-            bt["f64_single_rhs_points_per_s"] = f64_rate
-            bt["ratio_to_f64_single_rhs"] = bt["value"] / f64_rate
+        if f64_rate:
+            bt["f64_single_rhs_points_per_s_1m_cube"] = f64_rate
         out["batched"] = bt
         log(f"[bench] batched: {bt}")
     if not args.no_cpu_baseline and not args.profile_only:

@@ -58,9 +58,11 @@ typedef enum { SKELFMM_LAPLACE = 0, SKELFMM_HELMHOLTZ = 1 } skelfmm_kind;
 /* Arithmetic of an apply.  Laplace takes F64 or F32, Helmholtz C128 or C64. */
 typedef enum { SKELFMM_F64 = 0, SKELFMM_F32 = 1, SKELFMM_C128 = 2, SKELFMM_C64 = 3 } skelfmm_dtype;
 
-/* Kernel G (section 2):
- *   2D Laplace    -log(r) / (2 pi)         (dim = 2)
- *   3D Laplace    1 / (4 pi r)             (dim = 3)
+/* Kernel G (section 2, equations for the Laplace and Helmholtz kernels):
+ *   2D Laplace    -log(r) / (2 pi)          (dim = 2)
+ *   3D Laplace    1 / (4 pi r)              (dim = 3)
+ *   2D Helmholtz  (i/4) H0^(1)(kappa r)     (dim = 2, kappa >= 0; H0^(1) = J0 + i Y0,
+ *                                            evaluated in float64 in every dtype)
  *   3D Helmholtz  exp(i kappa r) / (4 pi r) (dim = 3, kappa >= 0)           */
 typedef struct {
     int32_t kind;            /* skelfmm_kind */
@@ -84,7 +86,12 @@ typedef struct {
     int32_t no_expansion;    /* 1: the float32 pair kernel always forms |d|^2 from coordinate
                                 differences (default 0: pairs whose distance bound allows it use
                                 the expanded form |t'|^2 + |s'|^2 - 2 t'.s', see skelfmm_stats) */
-    int32_t reserved[6];
+    int32_t compensated_leaf;/* F32 applies with one right-hand side: the symmetric pair kernel keeps
+                                its float32 partial sums to at most four products per target and
+                                forms its per-source column sums in float64 before everything is
+                                accumulated in float64 (default 0: float32 partials over blocks of 16
+                                sources and float32 column sums over the 64 x tpl targets of a pass) */
+    int32_t reserved[5];
 } skelfmm_options;
 
 /* Build-time and layout statistics (section 5 / table "Notation for reported results"). */
@@ -145,8 +152,8 @@ skelfmm_status skelfmm_build(const double* points, int64_t n, skelfmm_kernel ker
                              int32_t leaf_size, const skelfmm_options* opt, skelfmm_op** out);
 
 /* Upload the operator to the current HIP device and size its workspace for up to
- * nrhs_max right-hand sides of `dtype`.  Synchronous; may allocate.  Calling apply
- * with a larger nrhs (or a new dtype) prepares implicitly, which then allocates. */
+ * nrhs_max right-hand sides of `dtype` (nrhs_max = 0: upload only, no workspace).  Synchronous; may allocate.  Calling apply with a
+ * larger nrhs (or a new dtype) prepares implicitly, which then allocates. */
 skelfmm_status skelfmm_prepare(skelfmm_op* op, int64_t nrhs_max, skelfmm_dtype dtype);
 
 /* u = Atilde q on the GPU.  q, u: device buffers, n x nrhs (x2 for complex). */
@@ -170,6 +177,23 @@ skelfmm_status skelfmm_stats_get(const skelfmm_op* op, skelfmm_stats* out);
 skelfmm_status skelfmm_autotune(skelfmm_op* op, skelfmm_dtype dtype, void* hip_stream, int32_t* chosen, float* ms);
 skelfmm_status skelfmm_set_targets_per_lane(skelfmm_op* op, int32_t tpl);
 
+/* Launch shape of the many-RHS transfers on the matrix cores (float32 Laplace
+ * applies with at least 8 right-hand sides; section 3, "FMM apply", equations
+ * (15)-(20): per box qhat = q_S + T q_R upward and u_R += T^* uhat downward,
+ * here one GEMM per box against all right-hand sides).  Shapes 0 .. SKELFMM_NXFER-1
+ * are blocks of 4 or 2 wavefronts (128 or 64 rows of the result) with 64 or 32
+ * columns per wavefront: {4, 64}, {4, 32}, {2, 64}, {2, 32}.  No shape changes the
+ * arithmetic of an output tile, so all give identical results.
+ * skelfmm_autotune_transfers prepares the operator for nrhs float32 columns, times
+ * both passes in every shape on `hip_stream` (synchronously; it overwrites the
+ * workspace), keeps the fastest, returns it in *chosen and the timings in
+ * ms[SKELFMM_NXFER] (may be NULL).  Errors: EINVAL for a Helmholtz operator or
+ * NULL chosen, ENOTSUP when nrhs < 8 (those applies do not use the matrix cores). */
+#define SKELFMM_NXFER 4
+skelfmm_status skelfmm_autotune_transfers(skelfmm_op* op, int64_t nrhs, void* hip_stream, int32_t* chosen,
+                                         float* ms);
+skelfmm_status skelfmm_set_transfer_shape(skelfmm_op* op, int32_t shape);
+
 /* Per-pass GPU timing.  When enabled, each apply records HIP events on its stream
  * around its passes: [0] gather, [1] upward pass, [2] near field over the segment
  * lists (ifo, ifs, tfo, top level; with symmetric pairing, what is left after
@@ -191,6 +215,13 @@ skelfmm_status skelfmm_batch_create(skelfmm_op* const* ops, int32_t nops, skelfm
 skelfmm_status skelfmm_batch_apply(skelfmm_batch* b, const void* const* q, void* const* u,
                                    int64_t nrhs, skelfmm_dtype dtype, int32_t adjoint,
                                    void* hip_stream);
+/* skelfmm_timing / skelfmm_timing_read for the batch's sweeps (eager applies;
+ * a captured graph records no events). */
+skelfmm_status skelfmm_batch_timing(skelfmm_batch* b, int32_t enable);
+skelfmm_status skelfmm_batch_timing_read(skelfmm_batch* b, double* ms, int64_t* sweeps);
+/* skelfmm_autotune_transfers for the batch's merged sweep. */
+skelfmm_status skelfmm_batch_autotune_transfers(skelfmm_batch* b, int64_t nrhs, void* hip_stream,
+                                               int32_t* chosen, float* ms);
 void skelfmm_batch_destroy(skelfmm_batch* b);   /* NULL-safe */
 
 void skelfmm_destroy(skelfmm_op* op);           /* NULL-safe; frees host and device state */

@@ -26,7 +26,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
-_SOURCES = [os.path.join(_HERE, "direct.c"), os.path.join(_HERE, "apply.c")]
+_SOURCES = [os.path.join(_HERE, "direct.c"), os.path.join(_HERE, "apply.c"), os.path.join(_HERE, "hankel.c")]
 
 KIND = {"laplace": 0, "helmholtz": 1}
 
@@ -54,6 +54,7 @@ def _load():
         _lib.oracle_direct.restype = ctypes.c_int
         _lib.oracle_apply.restype = ctypes.c_int
         _lib.oracle_num_threads.restype = ctypes.c_int
+        _lib.oracle_h0_many.restype = None
     return _lib
 
 
@@ -102,6 +103,16 @@ def direct(points, q, kind="laplace", kappa=0.0, targets=None):
     return _from_values(out, kind, squeeze)
 
 
+def h0(x) -> np.ndarray:
+    """H0^(1)(x) = J0(x) + i Y0(x) for x > 0, as the oracle's C code evaluates it
+    (the 2D Helmholtz kernel is (i/4) H0^(1)(kappa r))."""
+    x = np.ascontiguousarray(x, dtype=np.float64).ravel()
+    j = np.zeros_like(x)
+    y = np.zeros_like(x)
+    _load().oracle_h0_many(ctypes.c_int64(x.size), _ptr(x), _ptr(j), _ptr(y))
+    return j + 1j * y
+
+
 def kernel(points_t, points_s, kind="laplace", kappa=0.0, same=None):
     """Dense kernel block G(x_t, x_s) by its definition (section 2), numpy.
 
@@ -119,6 +130,9 @@ def kernel(points_t, points_s, kind="laplace", kappa=0.0, same=None):
     rs = np.where(zero, 1.0, r)
     if kind == "laplace":
         g = -np.log(rs) / (2 * np.pi) if dim == 2 else 1.0 / (4 * np.pi * rs)
+    elif dim == 2:
+        from scipy.special import hankel1   # an independent evaluation of H0^(1)
+        g = 0.25j * hankel1(0, kappa * rs)
     else:
         g = np.exp(1j * kappa * rs) / (4 * np.pi * rs)
     return np.where(zero, 0.0, g)

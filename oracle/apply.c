@@ -37,6 +37,8 @@
 
 #define O_PI 3.14159265358979323846
 
+void oracle_h0(double x, double* j0, double* y0);   /* hankel.c */
+
 typedef struct {
     int32_t dim, kind;          /* kind 0 Laplace, 1 Helmholtz */
     double kappa;
@@ -75,8 +77,16 @@ static inline void kernel_value(const o2_plan* P, int64_t i, int64_t j, int conj
     if (P->kind == 0) {
         *gr = (P->dim == 2) ? -log(r) / (2.0 * O_PI) : 1.0 / (4.0 * O_PI * r);
     } else {
-        *gr = cos(P->kappa * r) / (4.0 * O_PI * r);
-        *gi = sin(P->kappa * r) / (4.0 * O_PI * r);
+        if (P->dim == 3) {
+            *gr = cos(P->kappa * r) / (4.0 * O_PI * r);
+            *gi = sin(P->kappa * r) / (4.0 * O_PI * r);
+        } else {
+            /* (i/4) H0^(1)(kappa r) = (i/4)(J0 + i Y0) */
+            double j0, y0;
+            oracle_h0(P->kappa * r, &j0, &y0);
+            *gr = -0.25 * y0;
+            *gi = 0.25 * j0;
+        }
         if (conj) *gi = -*gi;
     }
 }

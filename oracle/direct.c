@@ -12,6 +12,7 @@
  * Kernels (section 2, the Laplace and Helmholtz fundamental solutions):
  *   2D Laplace    G = -log(r) / (2 pi)
  *   3D Laplace    G = 1 / (4 pi r)
+ *   2D Helmholtz  G = (i/4) H0^(1)(kappa r)   (H0^(1) from hankel.c)
  *   3D Helmholtz  G = exp(i kappa r) / (4 pi r)
  * A pair with the same index is the excluded diagonal.  A pair of distinct
  * points at distance zero contributes zero (the paper does not define it).
@@ -22,6 +23,8 @@
 #include <omp.h>
 
 #define O_PI 3.14159265358979323846
+
+void oracle_h0(double x, double* j0, double* y0);   /* hankel.c */
 
 typedef struct { double s, c; } neu_t;   /* Neumaier running sum + correction */
 
@@ -40,7 +43,7 @@ static inline double dist(int dim, const double* a, const double* b) {
 
 /*
  * oracle_direct: u[t, :] = sum_{j != targ[t]} G(x_targ[t], x_j) q[j, :]
- *   dim    2 or 3;  kind 0 = Laplace, 1 = Helmholtz (3D only)
+ *   dim    2 or 3;  kind 0 = Laplace, 1 = Helmholtz
  *   pts    n x dim row-major
  *   q      n x nrhs row-major; complex values interleaved (re, im) when kind == 1
  *   targ   ntarg target indices into pts
@@ -51,7 +54,7 @@ int oracle_direct(int dim, int kind, double kappa, int64_t n, const double* pts,
                   int nrhs, const double* q, int64_t ntarg, const int64_t* targ,
                   double* out)
 {
-    if ((dim != 2 && dim != 3) || (kind != 0 && kind != 1) || (kind == 1 && dim != 3))
+    if ((dim != 2 && dim != 3) || (kind != 0 && kind != 1))
         return -1;
     const int cplx = (kind == 1);
     const int w = cplx ? 2 * nrhs : nrhs;
@@ -72,8 +75,17 @@ int oracle_direct(int dim, int kind, double kappa, int64_t n, const double* pts,
                     const double g = (dim == 2) ? -log(r) / (2.0 * O_PI) : 1.0 / (4.0 * O_PI * r);
                     for (int c = 0; c < nrhs; ++c) neu_add(&acc[c], g * qj[c]);
                 } else {
-                    const double gr = cos(kappa * r) / (4.0 * O_PI * r);
-                    const double gi = sin(kappa * r) / (4.0 * O_PI * r);
+                    double gr, gi;
+                    if (dim == 3) {
+                        gr = cos(kappa * r) / (4.0 * O_PI * r);
+                        gi = sin(kappa * r) / (4.0 * O_PI * r);
+                    } else {
+                        /* (i/4)(J0 + i Y0) */
+                        double j0, y0;
+                        oracle_h0(kappa * r, &j0, &y0);
+                        gr = -0.25 * y0;
+                        gi = 0.25 * j0;
+                    }
                     for (int c = 0; c < nrhs; ++c) {
                         const double a = qj[2 * c], b = qj[2 * c + 1];
                         neu_add(&acc[2 * c], gr * a);

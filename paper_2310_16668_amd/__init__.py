@@ -47,7 +47,7 @@ class Options(ctypes.Structure):
                 ("proxy_scale", ctypes.c_double), ("no_compression", ctypes.c_int32),
                 ("num_threads", ctypes.c_int32), ("keep_transparent", ctypes.c_int32),
                 ("f64_leaf", ctypes.c_int32), ("nonsymmetric", ctypes.c_int32), ("no_expansion", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("compensated_leaf", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
 
 
 class Stats(ctypes.Structure):
@@ -95,17 +95,28 @@ _lib.skelfmm_destroy.argtypes = [_vp]
 _lib.skelfmm_timing.argtypes = [_vp, ctypes.c_int32]
 _lib.skelfmm_autotune.argtypes = [_vp, ctypes.c_int, _vp, _P(ctypes.c_int32), _P(ctypes.c_float)]
 _lib.skelfmm_set_targets_per_lane.argtypes = [_vp, ctypes.c_int32]
+_lib.skelfmm_autotune_transfers.argtypes = [_vp, ctypes.c_int64, _vp, _P(ctypes.c_int32), _P(ctypes.c_float)]
+_lib.skelfmm_set_transfer_shape.argtypes = [_vp, ctypes.c_int32]
+_lib.skelfmm_batch_autotune_transfers.argtypes = [_vp, ctypes.c_int64, _vp, _P(ctypes.c_int32), _P(ctypes.c_float)]
 _lib.skelfmm_timing_read.argtypes = [_vp, _P(ctypes.c_double), _P(ctypes.c_int64)]
+_lib.skelfmm_batch_timing.argtypes = [_vp, ctypes.c_int32]
+_lib.skelfmm_batch_timing.restype = ctypes.c_int
+_lib.skelfmm_batch_timing_read.argtypes = [_vp, _P(ctypes.c_double), _P(ctypes.c_int64)]
+_lib.skelfmm_batch_timing_read.restype = ctypes.c_int
 _lib.skelfmm_last_error.restype = ctypes.c_char_p
 for _f in ("skelfmm_build", "skelfmm_prepare", "skelfmm_apply", "skelfmm_apply_adjoint", "skelfmm_stats_get",
            "skelfmm_export", "skelfmm_batch_create", "skelfmm_batch_apply", "skelfmm_timing",
-           "skelfmm_timing_read", "skelfmm_autotune", "skelfmm_set_targets_per_lane"):
+           "skelfmm_timing_read", "skelfmm_autotune", "skelfmm_set_targets_per_lane", "skelfmm_autotune_transfers",
+           "skelfmm_set_transfer_shape", "skelfmm_batch_autotune_transfers"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTED = ("skelfmm_build", "skelfmm_prepare", "skelfmm_apply", "skelfmm_apply_adjoint", "skelfmm_stats_get",
             "skelfmm_export", "skelfmm_batch_create", "skelfmm_batch_apply", "skelfmm_batch_destroy",
             "skelfmm_destroy", "skelfmm_last_error", "skelfmm_timing", "skelfmm_timing_read",
-            "skelfmm_autotune", "skelfmm_set_targets_per_lane")
+            "skelfmm_autotune", "skelfmm_set_targets_per_lane", "skelfmm_autotune_transfers",
+            "skelfmm_set_transfer_shape", "skelfmm_batch_autotune_transfers", "skelfmm_batch_timing",
+            "skelfmm_batch_timing_read")
+NXFER = 4
 PASSES = ("gather", "upward", "near_field", "near_pairs", "near_reduce", "downward", "output")
 
 
@@ -203,6 +214,18 @@ class Operator:
     def set_targets_per_lane(self, tpl: int):
         _check(_lib.skelfmm_set_targets_per_lane(self._h, tpl))
 
+    def autotune_transfers(self, nrhs: int) -> dict:
+        """Time the float32 many-RHS matrix-core transfers in every launch shape; keep the fastest."""
+        torch = _torch()
+        chosen = ctypes.c_int32()
+        ms = (ctypes.c_float * NXFER)()
+        _check(_lib.skelfmm_autotune_transfers(self._h, nrhs, torch.cuda.current_stream().cuda_stream,
+                                               ctypes.byref(chosen), ms))
+        return {"shape": chosen.value, "ms": [ms[i] for i in range(NXFER)]}
+
+    def set_transfer_shape(self, shape: int):
+        _check(_lib.skelfmm_set_transfer_shape(self._h, shape))
+
     def timing(self, enable: bool = True):
         """Enable (and zero) or disable per-pass HIP-event timing of applies."""
         _check(_lib.skelfmm_timing(self._h, int(enable)))
@@ -249,12 +272,14 @@ class Operator:
 def build(points, kind: str = "laplace", tol: float = 1e-6, leaf_size: int = 64, kappa: float = 0.0,
           proxy_shape: int = 0, proxy_points: int = 0, proxy_scale: float = 0.0, no_compression: bool = False,
           num_threads: int = 0, keep_transparent: bool = False, f64_leaf: bool = False,
-          symmetric: bool = True, expansion: bool = True) -> Operator:
+          symmetric: bool = True, expansion: bool = True, compensated_leaf: bool = False) -> Operator:
     """Build the skeleton operator for ``points`` (n x dim, host, float64).
 
     ``symmetric=False`` evaluates both orders of every colleague pair separately
     (the pairing applies to the real Laplace kernels with one right-hand side);
-    ``expansion=False`` keeps the float32 pair kernel on coordinate differences."""
+    ``expansion=False`` keeps the float32 pair kernel on coordinate differences;
+    ``compensated_leaf=True`` keeps its float32 partial sums to four products and
+    forms its column sums in float64."""
     pts = np.ascontiguousarray(points, dtype=np.float64)
     if pts.ndim != 2:
         raise ValueError("points must be n x dim")
@@ -266,6 +291,7 @@ def build(points, kind: str = "laplace", tol: float = 1e-6, leaf_size: int = 64,
     o.keep_transparent, o.f64_leaf = int(keep_transparent), int(f64_leaf)
     o.nonsymmetric = int(not symmetric)
     o.no_expansion = int(not expansion)
+    o.compensated_leaf = int(compensated_leaf)
     h = _vp()
     _check(_lib.skelfmm_build(pts.ctypes.data_as(_P(ctypes.c_double)), n, k, tol, leaf_size,
                               ctypes.byref(o), ctypes.byref(h)))
@@ -288,6 +314,27 @@ class Batch:
         if h:
             self._destroy(h)
             self._h = None
+
+    def timing(self, enable: bool = True):
+        """Enable (and zero) or disable per-pass HIP-event timing of eager batched sweeps."""
+        _check(_lib.skelfmm_batch_timing(self._h, int(enable)))
+
+    def timing_read(self) -> dict:
+        ms = (ctypes.c_double * len(PASSES))()
+        n = ctypes.c_int64()
+        _check(_lib.skelfmm_batch_timing_read(self._h, ms, ctypes.byref(n)))
+        out = {p: ms[i] for i, p in enumerate(PASSES)}
+        out["sweeps"] = n.value
+        return out
+
+    def autotune_transfers(self, nrhs: int) -> dict:
+        """Time the float32 many-RHS matrix-core transfers of the merged sweep; keep the fastest."""
+        torch = _torch()
+        chosen = ctypes.c_int32()
+        ms = (ctypes.c_float * NXFER)()
+        _check(_lib.skelfmm_batch_autotune_transfers(self._h, nrhs, torch.cuda.current_stream().cuda_stream,
+                                                     ctypes.byref(chosen), ms))
+        return {"shape": chosen.value, "ms": [ms[i] for i in range(NXFER)]}
 
     def apply(self, qs, adjoint: bool = False):
         """Outputs for every operator, each shaped like its input ([n] or [n, nrhs])."""

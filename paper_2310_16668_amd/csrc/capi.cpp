@@ -86,8 +86,6 @@ skelfmm_status skelfmm_build(const double* points, int64_t n, skelfmm_kernel ker
     if (kernel.dim != 2 && kernel.dim != 3) return fail(SKELFMM_EINVAL, "dim must be 2 or 3");
     if (kernel.kind != SKELFMM_LAPLACE && kernel.kind != SKELFMM_HELMHOLTZ)
         return fail(SKELFMM_EINVAL, "unknown kernel kind");
-    if (kernel.kind == SKELFMM_HELMHOLTZ && kernel.dim != 3)
-        return fail(SKELFMM_ENOTSUP, "Helmholtz is supported in 3D only");
     if (kernel.kind == SKELFMM_HELMHOLTZ && !(kernel.kappa >= 0.0 && std::isfinite(kernel.kappa)))
         return fail(SKELFMM_EINVAL, "kappa must be finite and >= 0");
     if (!(tol > 0.0 && tol < 1.0)) return fail(SKELFMM_EINVAL, "tol must be in (0, 1)");
@@ -116,7 +114,8 @@ skelfmm_status skelfmm_build(const double* points, int64_t n, skelfmm_kernel ker
             if (p.opt.proxy_shape == 2 && p.dim == 3) throw std::invalid_argument("the proxy circle is 2D only");
             skelfmm::build_plan(p);
             op->dev = skelfmm::device_create(p, op->opt.keep_transparent != 0, op->opt.f64_leaf != 0,
-                                             op->opt.nonsymmetric == 0, op->opt.no_expansion == 0);
+                                             op->opt.nonsymmetric == 0, op->opt.no_expansion == 0,
+                                             op->opt.compensated_leaf != 0);
         } catch (...) {
             delete op;
             throw;
@@ -128,7 +127,7 @@ skelfmm_status skelfmm_build(const double* points, int64_t n, skelfmm_kernel ker
 
 skelfmm_status skelfmm_prepare(skelfmm_op* op, int64_t nrhs_max, skelfmm_dtype dtype) {
     if (!alive(op)) return fail(SKELFMM_EINVAL, "invalid operator");
-    if (nrhs_max < 1) return fail(SKELFMM_EINVAL, "nrhs must be >= 1");
+    if (nrhs_max < 0) return fail(SKELFMM_EINVAL, "nrhs_max must be >= 0");
     if (skelfmm_status s = check_dtype(op, dtype)) return s;
     return guarded([&]() -> skelfmm_status {
         skelfmm::device_prepare(op->dev, nrhs_max, static_cast<int>(dtype));
@@ -199,6 +198,29 @@ skelfmm_status skelfmm_set_targets_per_lane(skelfmm_op* op, int32_t tpl) {
     if (tpl < 1 || tpl > SKELFMM_NTPL) return fail(SKELFMM_EINVAL, "targets per lane must be 1 .. 4");
     return guarded([&]() -> skelfmm_status {
         skelfmm::device_set_tpl(op->dev, tpl);
+        return SKELFMM_OK;
+    });
+}
+
+skelfmm_status skelfmm_autotune_transfers(skelfmm_op* op, int64_t nrhs, void* hip_stream, int32_t* chosen,
+                                         float* ms) {
+    if (!alive(op)) return fail(SKELFMM_EINVAL, "invalid operator");
+    if (!chosen) return fail(SKELFMM_EINVAL, "chosen is NULL");
+    if (nrhs < 1) return fail(SKELFMM_EINVAL, "nrhs must be >= 1");
+    if (skelfmm_status s = check_dtype(op, SKELFMM_F32)) return s;
+    return guarded([&]() -> skelfmm_status {
+        float t[SKELFMM_NXFER] = {};
+        *chosen = skelfmm::device_autotune_xfer(op->dev, nrhs, hip_stream, t);
+        if (ms) for (int i = 0; i < SKELFMM_NXFER; ++i) ms[i] = t[i];
+        return SKELFMM_OK;
+    });
+}
+
+skelfmm_status skelfmm_set_transfer_shape(skelfmm_op* op, int32_t shape) {
+    if (!alive(op)) return fail(SKELFMM_EINVAL, "invalid operator");
+    if (shape < 0 || shape >= SKELFMM_NXFER) return fail(SKELFMM_EINVAL, "transfer launch shape out of range");
+    return guarded([&]() -> skelfmm_status {
+        skelfmm::device_set_xfer(op->dev, shape);
         return SKELFMM_OK;
     });
 }
@@ -294,6 +316,37 @@ skelfmm_status skelfmm_batch_apply(skelfmm_batch* b, const void* const* q, void*
     }
     return guarded([&]() -> skelfmm_status {
         skelfmm::batch_apply(b->dev, q, u, nrhs, static_cast<int>(dtype), hip_stream, adjoint != 0);
+        return SKELFMM_OK;
+    });
+}
+
+skelfmm_status skelfmm_batch_autotune_transfers(skelfmm_batch* b, int64_t nrhs, void* hip_stream, int32_t* chosen,
+                                               float* ms) {
+    if (!b || b->magic != kMagic) return fail(SKELFMM_EINVAL, "invalid batch");
+    if (!chosen) return fail(SKELFMM_EINVAL, "chosen is NULL");
+    if (nrhs < 1) return fail(SKELFMM_EINVAL, "nrhs must be >= 1");
+    if (b->kind != SKELFMM_LAPLACE) return fail(SKELFMM_EINVAL, "the matrix-core transfers serve Laplace batches");
+    return guarded([&]() -> skelfmm_status {
+        float t[SKELFMM_NXFER] = {};
+        *chosen = skelfmm::batch_autotune_xfer(b->dev, nrhs, hip_stream, t);
+        if (ms) for (int i = 0; i < SKELFMM_NXFER; ++i) ms[i] = t[i];
+        return SKELFMM_OK;
+    });
+}
+
+skelfmm_status skelfmm_batch_timing(skelfmm_batch* b, int32_t enable) {
+    if (!b || b->magic != kMagic) return fail(SKELFMM_EINVAL, "invalid batch");
+    return guarded([&]() -> skelfmm_status {
+        skelfmm::device_timing(skelfmm::batch_merged(b->dev), enable != 0);
+        return SKELFMM_OK;
+    });
+}
+
+skelfmm_status skelfmm_batch_timing_read(skelfmm_batch* b, double* ms, int64_t* sweeps) {
+    if (!b || b->magic != kMagic) return fail(SKELFMM_EINVAL, "invalid batch");
+    if (!ms || !sweeps) return fail(SKELFMM_EINVAL, "NULL output");
+    return guarded([&]() -> skelfmm_status {
+        skelfmm::device_timing_read(skelfmm::batch_merged(b->dev), ms, sweeps);
         return SKELFMM_OK;
     });
 }

@@ -117,7 +117,8 @@ Layout merge_layouts(const std::vector<const Layout*>& ls, std::vector<int64_t>&
 struct DeviceOp;
 struct DeviceBatch;
 
-DeviceOp* device_create(const Plan& p, bool keep_transparent, bool f64_leaf, bool symmetric, bool expanded);
+DeviceOp* device_create(const Plan& p, bool keep_transparent, bool f64_leaf, bool symmetric, bool expanded,
+                        bool compensated);
 void device_prepare(DeviceOp* d, int64_t nrhs_max, int dtype);
 void device_apply(DeviceOp* d, const void* q, void* u, int64_t nrhs, int dtype, void* stream, bool adjoint);
 void device_fill_stats(const DeviceOp* d, skelfmm_stats* out);
@@ -125,11 +126,15 @@ void device_destroy(DeviceOp* d);
 void device_timing(DeviceOp* d, bool enable);
 int device_autotune(DeviceOp* d, int dtype, void* stream, float* ms_out);
 void device_set_tpl(DeviceOp* d, int tpl);
+int device_autotune_xfer(DeviceOp* d, int64_t nrhs, void* stream, float* ms_out);
+void device_set_xfer(DeviceOp* d, int shape);
 void device_timing_read(DeviceOp* d, double* ms, int64_t* sweeps);
 
 DeviceBatch* batch_create(const std::vector<DeviceOp*>& ops);
 void batch_apply(DeviceBatch* b, const void* const* q, void* const* u, int64_t nrhs, int dtype,
                  void* stream, bool adjoint);
 void batch_destroy(DeviceBatch* b);
+int batch_autotune_xfer(DeviceBatch* b, int64_t nrhs, void* stream, float* ms_out);
+DeviceOp* batch_merged(DeviceBatch* b);   // the merged operator the batch's sweeps run on
 
 }  // namespace skelfmm

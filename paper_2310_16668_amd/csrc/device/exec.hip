@@ -20,134 +20,9 @@
 // versa, so the segment lists are reused unchanged; the upward pass becomes a
 // top-down pass of the downward form; the gather becomes the output scatter.
 // The adjoint therefore runs the forward launches with the kernel conjugated.
-#include <hip/hip_runtime.h>
-
-#include <algorithm>
-#include <array>
-#include <cstring>
-#include <memory>
-#include <string>
-#include <vector>
-
-#include "device.h"
-#include "kernels.hip"
+#include "sweep.h"
 
 namespace skelfmm {
-
-#define SKF_HIP(x)                                                                                 \
-    do {                                                                                           \
-        hipError_t e_ = (x);                                                                       \
-        if (e_ != hipSuccess) {                                                                    \
-            if (e_ == hipErrorOutOfMemory) throw OutOfMemory(std::string(#x) + ": out of memory"); \
-            throw DeviceError(std::string(#x) + ": " + hipGetErrorString(e_));                    \
-        }                                                                                          \
-    } while (0)
-
-namespace {
-
-struct DevMem {
-    void* p = nullptr;
-    size_t bytes = 0;
-    DevMem() = default;
-    DevMem(const DevMem&) = delete;
-    DevMem& operator=(const DevMem&) = delete;
-    ~DevMem() { release(); }
-    void release() {
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        bytes = 0;
-    }
-    // 256 spare bytes keep merged wave-uniform loads at the end of an array in bounds
-    void alloc(size_t b) {
-        release();
-        SKF_HIP(hipMalloc(&p, b + 256));
-        bytes = b;
-    }
-    template <class T>
-    void upload(const std::vector<T>& v) {
-        alloc(v.size() * sizeof(T));
-        if (!v.empty()) SKF_HIP(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
-    }
-    template <class T>
-    T* as() const { return static_cast<T*>(p); }
-};
-
-int dtype_is_complex(int dt) { return dt == SKELFMM_C128 || dt == SKELFMM_C64; }
-int dtype_is_single(int dt) { return dt == SKELFMM_F32 || dt == SKELFMM_C64; }
-
-constexpr int kDefaultTPL = 2;   // targets per lane in the single-RHS near-field kernels (1 .. 4)
-constexpr int kChunkReals = 8;   // right-hand-side reals per multi-RHS near-field work item
-
-int tpl_slot(int tpl) { return tpl - 1; }
-
-// Several right-hand sides of a real kernel in the float32 policy run the near
-// field on the matrix cores (k_near_mfma) from 8 columns on.
-constexpr int kMfmaMinRhs = 8;
-constexpr int kMfmaCols = 32;     // columns per accumulator tile
-
-// Values per entry inside the workspace: nv for one RHS; several RHS are padded
-// to a multiple of the near-field chunk (of the accumulator tile on the matrix
-// core path).
-int64_t padded_width(int64_t nrhs, int dtype, bool mfma) {
-    const int64_t w = nrhs * (dtype_is_complex(dtype) ? 2 : 1);
-    if (nrhs == 1) return w;
-    const int64_t m = mfma ? kMfmaCols : kChunkReals;
-    return (w + m - 1) / m * m;
-}
-
-inline unsigned blocks_for(int64_t n, int bs) { return static_cast<unsigned>((n + bs - 1) / bs); }
-
-}  // namespace
-
-struct DeviceOp {
-    Layout L;
-    bool f64_leaf = false;
-    int device = -1;
-    bool uploaded = false;
-    // static arrays
-    DevMem voff, hoff, toff, ttoff, nb, kb, pmap, gather_e, gather_p;
-    DevMem X64, T64, T32, Tt64, Tt32;             // T and its per-box transposes, columns padded
-    DevMem seg_ptr, segs, boxrec;
-    // one-RHS transfer work: (box, first row) items per level, and waves per item
-    DevMem upwork[2], downwork[2];                // [0]: float64 T row groups, [1]: float32
-    std::vector<int64_t> up_ptr[2], down_ptr[2];
-    std::vector<int> up_nw, down_nw;
-    std::vector<int> up_rows, down_rows;          // per level: most output rows of a box (k up, n - k down)
-    int tpl = kDefaultTPL;
-    DevMem tasks[SKELFMM_NTPL];                   // work lists for 1 .. 4 targets per lane
-    int ntasks[SKELFMM_NTPL] = {};
-    // symmetric near field (one RHS): segment lists without the paired ifo
-    // terms, their work lists, the pair items, the slot reduction lists
-    DevMem seg_ptr_ns, segs_ns, tasks_ns[SKELFMM_NTPL], symtasks, symrows, slots;
-    int ntasks_ns[SKELFMM_NTPL] = {};
-    DevMem tasks32;                               // 32-target work list of the matrix-core near field
-    int ntasks32 = 0;
-    int ntasks32h = 0;                            // its first ntasks32h items hold uhat rows
-    int nsym = 0, nred = 0;
-    // workspace
-    DevMem Q, Qh, U, Uh;
-    // per-pass timing
-    bool timing = false;
-    std::vector<std::array<hipEvent_t, SKELFMM_NPASS + 1>> pending;
-    double pass_ms[SKELFMM_NPASS] = {};
-    int64_t sweeps = 0;
-    ~DeviceOp() {
-        for (auto& ev : pending)
-            for (auto e : ev) (void)hipEventDestroy(e);
-    }
-};
-
-// The matrix-core near field serves several RHS of a real kernel in the
-// float32 policy.
-static bool use_mfma(const DeviceOp* d, int64_t nrhs, int dtype) {
-    return d->L.kind == 0 && dtype == SKELFMM_F32 && !d->f64_leaf && nrhs >= kMfmaMinRhs;
-}
-
-struct DeviceBatch {
-    std::vector<DeviceOp*> ops;
-    std::unique_ptr<DeviceOp> merged;
-    std::vector<int64_t> gbase;                   // first gather-list index of each operator
-};
 
 static void check_ranks(const Layout& L) {
     int kmax = 0;
@@ -159,13 +34,15 @@ static void check_ranks(const Layout& L) {
 // for every tpl in 1 .. 4).
 constexpr int kSymGroup = 768;
 
-DeviceOp* device_create(const Plan& p, bool keep_transparent, bool f64_leaf, bool symmetric, bool expanded) {
+DeviceOp* device_create(const Plan& p, bool keep_transparent, bool f64_leaf, bool symmetric, bool expanded,
+                        bool compensated) {
     auto d = std::make_unique<DeviceOp>();
     d->L = make_layout(p, keep_transparent, 64 * kDefaultTPL);
     d->L.allow_expanded = expanded;
     // the pairing needs G(x, y) = G(y, x) with real values
     if (symmetric && p.kind == 0) make_symmetric(d->L, kSymGroup);
     d->f64_leaf = f64_leaf;
+    d->compensated = compensated;
     check_ranks(d->L);
     return d.release();
 }
@@ -185,9 +62,11 @@ static void build_transfer_work(DeviceOp* d) {
             d->up_rows[l] = std::max(d->up_rows[l], L.kb[b]);
             d->down_rows[l] = std::max(d->down_rows[l], L.nb[b] - L.kb[b]);
         }
-    for (int g = 0; g < 2; ++g) {
-        // row groups: 64 rows of float64 T, 128 rows of float32 T (one 8-byte load per lane)
-        const int G = g == 0 ? kern::RowMap<double>::group : kern::RowMap<float>::group;
+    for (int g = 0; g < 4; ++g) {
+        // row groups: 64 rows of float64 T, 128 rows of float32 T (one 8-byte load
+        // per lane); blocks of 64 / 128 rows of the matrix-core transfers
+        const int G = g == 0 ? kern::RowMap<double>::group
+                             : (g == 1 ? kern::RowMap<float>::group : kern::kXferRowsPerWave * (g == 2 ? 2 : 4));
         std::vector<int2> up, down;
         d->up_ptr[g].assign(L.max_level + 2, 0);
         d->down_ptr[g].assign(L.max_level + 2, 0);
@@ -202,8 +81,8 @@ static void build_transfer_work(DeviceOp* d) {
                 ++nbk;
                 cu += m;
                 cd += k;
-                for (int r = 0; r * G < k; ++r) up.push_back(make_int2(b, r));
-                for (int r = 0; r * G < std::max(m, 1); ++r) down.push_back(make_int2(b, r));
+                for (int r = 0; r * G < k; ++r) up.push_back(make_int2(b, r * (g >= 2 ? G : 1)));
+                for (int r = 0; r * G < std::max(m, 1); ++r) down.push_back(make_int2(b, r * (g >= 2 ? G : 1)));
             }
             if (g == 0 && nbk > 0) {
                 d->up_nw[l] = std::min(16, std::max(1, static_cast<int>(cu / nbk / 32.0 + 0.5)));
@@ -287,7 +166,6 @@ static void upload(DeviceOp* d, int dtype) {
             }
             d->symrows.upload(L.sym_rows);
             d->nred = static_cast<int>(L.sym_rows.size());
-            d->slots.alloc(static_cast<size_t>(L.slot_size) * sizeof(double));
         }
         std::vector<kern::BoxRec> br(L.n_boxes);
         for (int b = 0; b < L.n_boxes; ++b)
@@ -308,253 +186,38 @@ static void upload_transposes(DeviceOp* d, bool single) {
     else d->Tt64.upload(padded_t<double>(d->L, true));
 }
 
+// Bytes of the workspace one sweep of nrhs columns of dtype needs: entry
+// vectors q and u, skeleton vectors qhat and uhat, the pair kernel's slots.
+struct WorkBytes {
+    size_t e, h, slots;
+};
+static WorkBytes work_bytes(const DeviceOp* d, int64_t nrhs, int dtype) {
+    const size_t vb = dtype_is_single(dtype) ? 4 : 8;
+    const size_t wp = static_cast<size_t>(padded_width(nrhs, dtype, use_mfma(d, nrhs, dtype)));
+    return WorkBytes{static_cast<size_t>(d->L.n_entries) * wp * vb, static_cast<size_t>(d->L.n_hentries) * wp * vb,
+                     d->L.sym ? static_cast<size_t>(d->L.slot_size) * sizeof(double) : 0};
+}
+
+// Uploads the operator for dtype; nrhs >= 1 also sizes its own workspace.
 void device_prepare(DeviceOp* d, int64_t nrhs, int dtype) {
     upload(d, dtype);
     upload_transposes(d, dtype_is_single(dtype));
-    const size_t vb = dtype_is_single(dtype) ? 4 : 8;
-    const size_t wp = static_cast<size_t>(padded_width(nrhs, dtype, use_mfma(d, nrhs, dtype)));
-    const size_t need_e = static_cast<size_t>(d->L.n_entries) * wp * vb;
-    const size_t need_h = static_cast<size_t>(d->L.n_hentries) * wp * vb;
-    if (d->Q.bytes < need_e) { d->Q.alloc(need_e); d->U.alloc(need_e); }
-    if (d->Qh.bytes < need_h) { d->Qh.alloc(need_h); d->Uh.alloc(need_h); }
+    if (nrhs < 1) return;
+    const WorkBytes wb = work_bytes(d, nrhs, dtype);
+    if (d->Q.bytes < wb.e || !d->Q.p) { d->Q.alloc(wb.e); d->U.alloc(wb.e); }
+    if (d->Qh.bytes < wb.h || !d->Qh.p) { d->Qh.alloc(wb.h); d->Uh.alloc(wb.h); }
+    if (!d->slots.p) d->slots.alloc(wb.slots);
 }
 
 namespace {
 
-// The caller's buffers of one operator and its range of leaf entries.
-struct IO {
-    const void* q;
-    void* u;
-    int64_t g0;     // first index into the gather lists
-    int64_t cnt;    // number of points
-};
-
-// Events bracketing the passes of one sweep (only when timing is on).
-struct PassMarks {
-    DeviceOp* d;
-    hipStream_t s;
-    std::array<hipEvent_t, SKELFMM_NPASS + 1> ev{};
-    PassMarks(DeviceOp* d_, hipStream_t s_) : d(d_), s(s_) {
-        if (!d->timing) return;
-        for (auto& e : ev) SKF_HIP(hipEventCreate(&e));
-    }
-    void mark(int i) {
-        if (d->timing) SKF_HIP(hipEventRecord(ev[i], s));
-    }
-    void done() {
-        if (d->timing) d->pending.push_back(ev);
-    }
-};
-
-// The one-RHS near field: k_near over the segment lists; with symmetric pairing
-// it covers what is left after pairing, then k_near_sym evaluates the pairs
-// into slots and k_sym_reduce adds the slots to u and uhat.
-template <class P, int TPL, bool CONJ>
-void launch_near_t(const DeviceOp* d, hipStream_t s, void* Q, void* Qh, void* U, void* Uh, PassMarks* pm) {
-    using R = typename P::Rt;
-    using V = typename P::Vt;
-    const int ts = tpl_slot(TPL);
-    const bool sym = d->L.sym;
-    const int ntasks = sym ? d->ntasks_ns[ts] : d->ntasks[ts];
-    if (ntasks > 0) {
-        hipLaunchKernelGGL((kern::k_near<P, TPL, CONJ>), dim3(blocks_for(ntasks, 4)), dim3(256), 0, s,
-                           (sym ? d->tasks_ns[ts] : d->tasks[ts]).as<Task>(), ntasks,
-                           (sym ? d->seg_ptr_ns : d->seg_ptr).as<int32_t>(), (sym ? d->segs_ns : d->segs).as<int2>(),
-                           d->boxrec.as<kern::BoxRec>(), d->X64.as<kern::Rec4<double>>(), static_cast<const V*>(Q),
-                           static_cast<const V*>(Qh), static_cast<V*>(U), static_cast<V*>(Uh),
-                           static_cast<R>(d->L.kappa), kern::kInv4Pi);
-        SKF_HIP(hipGetLastError());
-    }
-    if (pm) pm->mark(3);
-    if constexpr (P::kind == 0) {
-        if (sym && d->nsym > 0) {
-            hipLaunchKernelGGL((kern::k_near_sym<P, TPL>), dim3(blocks_for(d->nsym, 4)), dim3(256), 0, s,
-                               d->symtasks.as<SymTask>(), d->nsym, d->boxrec.as<kern::BoxRec>(),
-                               d->X64.as<kern::Rec4<double>>(), static_cast<const V*>(Q), static_cast<const V*>(Qh),
-                               d->slots.as<double>(), kern::kInv4Pi);
-            SKF_HIP(hipGetLastError());
-        }
-    }
-    if (pm) pm->mark(4);
-    if constexpr (P::kind == 0) {
-        if (sym && d->nred > 0) {
-            hipLaunchKernelGGL((kern::k_sym_reduce<V>), dim3(d->nred), dim3(256), 0, s, d->symrows.as<SymRows>(),
-                               d->boxrec.as<kern::BoxRec>(), d->slots.as<double>(), static_cast<V*>(U),
-                               static_cast<V*>(Uh));
-            SKF_HIP(hipGetLastError());
-        }
-    }
-}
-
-template <class P, bool CONJ>
-void launch_near(const DeviceOp* d, hipStream_t s, void* Q, void* Qh, void* U, void* Uh, PassMarks* pm = nullptr) {
-    if (d->tpl == 1) launch_near_t<P, 1, CONJ>(d, s, Q, Qh, U, Uh, pm);
-    else if (d->tpl == 3) launch_near_t<P, 3, CONJ>(d, s, Q, Qh, U, Uh, pm);
-    else if (d->tpl == 4) launch_near_t<P, 4, CONJ>(d, s, Q, Qh, U, Uh, pm);
-    else launch_near_t<P, 2, CONJ>(d, s, Q, Qh, U, Uh, pm);
-}
-
-template <class P, bool CONJ, typename Am>
-void launch_near_mr(const DeviceOp* d, hipStream_t s, int Wp, void* Q, void* Qh, void* U, void* Uh) {
-    const int ntasks = d->ntasks[tpl_slot(1)];
-    if (ntasks == 0) return;
-    using R = typename P::Rt;
-    using V = typename P::Vt;
-    constexpr int NR = kChunkReals / P::nv;
-    const int nchunks = Wp / kChunkReals;
-    hipLaunchKernelGGL((kern::k_near_mr<P, NR, CONJ, Am>), dim3(blocks_for(int64_t(ntasks) * nchunks, 4)),
-                       dim3(256), 0, s, d->tasks[tpl_slot(1)].as<Task>(), ntasks, nchunks, Wp,
-                       d->seg_ptr.as<int32_t>(), d->segs.as<int2>(), d->boxrec.as<kern::BoxRec>(),
-                       d->X64.as<kern::Rec4<double>>(), static_cast<const V*>(Q), static_cast<const V*>(Qh), static_cast<V*>(U), static_cast<V*>(Uh),
-                       static_cast<R>(d->L.kappa), kern::kInv4Pi);
-    SKF_HIP(hipGetLastError());
-}
-
-// Tasks with uhat rows come first in the list (nh of them).  One column tile:
-// k_near_mfma over every task; more: two tiles per wave, one launch per list.
-template <class P>
-void launch_near_mfma(const DeviceOp* d, hipStream_t s, int Wp, void* Q, void* Qh, void* U, void* Uh) {
-    static_assert(kMfmaCols == kern::kMfmaTile, "one accumulator tile width");
-    const int nt = d->ntasks32, nh = d->ntasks32h, nn = nt - nh;
-    const int ntiles = Wp / kMfmaCols, npairs = (ntiles + 1) / 2;
-    const Task* tl = d->tasks32.as<Task>();
-    const auto* X = d->X64.as<kern::Rec4<double>>();
-    const float* Qf = static_cast<const float*>(Q);
-    const float* Qhf = static_cast<const float*>(Qh);
-    float* Uf = static_cast<float*>(U);
-    float* Uhf = static_cast<float*>(Uh);
-    if (ntiles == 1) {
-        if (nt > 0)
-            hipLaunchKernelGGL((kern::k_near_mfma<P>), dim3(blocks_for(nt, 4)), dim3(256), 0, s, tl, nt, 1, Wp,
-                               d->seg_ptr.as<int32_t>(), d->segs.as<int2>(), d->boxrec.as<kern::BoxRec>(), X, Qf,
-                               Qhf, Uf, Uhf, kern::kInv4Pi);
-        SKF_HIP(hipGetLastError());
-        return;
-    }
-    if (nh > 0)
-        hipLaunchKernelGGL((kern::k_near_mfma2<P, true>), dim3(blocks_for(int64_t(nh) * npairs, 4)), dim3(256), 0,
-                           s, tl, nh, npairs, Wp, d->seg_ptr.as<int32_t>(), d->segs.as<int2>(),
-                           d->boxrec.as<kern::BoxRec>(), X, Qf, Qhf, Uf, Uhf, kern::kInv4Pi);
-    if (nn > 0)
-        hipLaunchKernelGGL((kern::k_near_mfma2<P, false>), dim3(blocks_for(int64_t(nn) * npairs, 4)), dim3(256), 0,
-                           s, tl + nh, nn, npairs, Wp, d->seg_ptr.as<int32_t>(), d->segs.as<int2>(),
-                           d->boxrec.as<kern::BoxRec>(), X, Qf, Qhf, Uf, Uhf, kern::kInv4Pi);
-    SKF_HIP(hipGetLastError());
-}
-
-// One sweep.  V: stored values; TT: transfer matrices; P: near-field policy;
-// Am: accumulator of one source box's partial sums in the multi-RHS near field.
-template <typename V, typename TT, class P, typename Am>
-void sweep(DeviceOp* d, const std::vector<IO>& io, int64_t nrhs, int dtype, hipStream_t s, bool adjoint,
-           const TT* T, const TT* Tt) {
+void sweep_any(DeviceOp* d, const std::vector<IO>& io, int64_t nrhs, int dtype, hipStream_t s, bool adjoint,
+               const Work& w) {
     const Layout& L = d->L;
-    const bool multi = nrhs > 1;
-    const int Win = static_cast<int>(nrhs * P::nv);
-    const bool mfma = use_mfma(d, nrhs, dtype);
-    const int Wp = static_cast<int>(padded_width(nrhs, dtype, mfma));
-    V* Q = d->Q.as<V>();
-    V* Qh = d->Qh.as<V>();
-    V* U = d->U.as<V>();
-    V* Uh = d->Uh.as<V>();
-    const kern::BoxRec* br = d->boxrec.as<kern::BoxRec>();
-    const int64_t* toff = d->toff.as<int64_t>();
-    const int64_t* ttoff = d->ttoff.as<int64_t>();
-    const int32_t* pmap = d->pmap.as<int32_t>();
-    const int32_t* ge = d->gather_e.as<int32_t>();
-    const int32_t* gp = d->gather_p.as<int32_t>();
-    PassMarks pm(d, s);
-    pm.mark(0);
-    for (const IO& x : io) {
-        if (x.cnt <= 0) continue;
-        hipLaunchKernelGGL((kern::k_gather_pad<V, V>), dim3(blocks_for(x.cnt * Wp, 256)), dim3(256), 0, s,
-                           ge + x.g0, gp + x.g0, x.cnt, Win, Wp, static_cast<const V*>(x.q), Q);
-        SKF_HIP(hipGetLastError());
-    }
-    pm.mark(1);
-    for (int l = L.max_level; l >= 2; --l) {
-        const int b0 = L.level_ptr[l], nbx = L.level_ptr[l + 1] - b0;
-        if (nbx <= 0) continue;
-        if (multi) {
-            // row chunks of a box spread over the grid's second dimension (4 per block)
-            const int gy = std::max(1, (d->up_rows[l] + 4 * kern::kRB - 1) / (4 * kern::kRB));
-            hipLaunchKernelGGL((kern::k_upward_mr<V, TT>), dim3(nbx, gy), dim3(256), 0, s, br, toff, pmap, b0, Wp,
-                               T, Q, Qh);
-        } else {
-            const int wg = sizeof(TT) == 4 ? 1 : 0;
-            const int64_t w0 = d->up_ptr[wg][l], nwk = d->up_ptr[wg][l + 1] - w0;
-            if (nwk <= 0) continue;
-            const int nw = d->up_nw[l];
-            const int2* wk = d->upwork[wg].as<int2>() + w0;
-            if (P::nv == 1)
-                hipLaunchKernelGGL((kern::k_up_gemv<V, TT, 1>), dim3(nwk), dim3(64 * nw), 0, s, wk, br, toff, pmap, T,
-                                   Q, Q, Qh, nw);
-            else
-                hipLaunchKernelGGL((kern::k_up_gemv<V, TT, 2>), dim3(nwk), dim3(64 * nw), 0, s, wk, br, toff, pmap, T,
-                                   Q, Q, Qh, nw);
-        }
-        SKF_HIP(hipGetLastError());
-    }
-    pm.mark(2);
-    if (multi) {
-        if constexpr (P::kind == 0 && sizeof(typename P::Rt) == 4) {
-            if (mfma) launch_near_mfma<P>(d, s, Wp, Q, Qh, U, Uh);
-            else launch_near_mr<P, false, Am>(d, s, Wp, Q, Qh, U, Uh);
-        } else {
-            if (adjoint && P::kind == 1) launch_near_mr<P, true, Am>(d, s, Wp, Q, Qh, U, Uh);
-            else launch_near_mr<P, false, Am>(d, s, Wp, Q, Qh, U, Uh);
-        }
-        pm.mark(3);
-        pm.mark(4);
-    } else {
-        if (adjoint && P::kind == 1) launch_near<P, true>(d, s, Q, Qh, U, Uh, &pm);
-        else launch_near<P, false>(d, s, Q, Qh, U, Uh, &pm);
-    }
-    pm.mark(5);
-    for (int l = 2; l <= L.max_level; ++l) {
-        const int b0 = L.level_ptr[l], nbx = L.level_ptr[l + 1] - b0;
-        if (nbx <= 0) continue;
-        if (multi) {
-            const int gy = std::max(1, (d->down_rows[l] + 4 * kern::kRB - 1) / (4 * kern::kRB));
-            hipLaunchKernelGGL((kern::k_downward_mr<V, TT>), dim3(nbx, gy), dim3(256), 0, s, br, ttoff, pmap, b0, Wp,
-                               Tt, Uh, U);
-        } else {
-            const int wg = sizeof(TT) == 4 ? 1 : 0;
-            const int64_t w0 = d->down_ptr[wg][l], nwk = d->down_ptr[wg][l + 1] - w0;
-            if (nwk <= 0) continue;
-            const int nw = d->down_nw[l];
-            const int2* wk = d->downwork[wg].as<int2>() + w0;
-            if (P::nv == 1)
-                hipLaunchKernelGGL((kern::k_down_gemv<V, TT, 1>), dim3(nwk), dim3(64 * nw), 0, s, wk, br, ttoff, pmap,
-                                   Tt, Uh, U, U, nw);
-            else
-                hipLaunchKernelGGL((kern::k_down_gemv<V, TT, 2>), dim3(nwk), dim3(64 * nw), 0, s, wk, br, ttoff, pmap,
-                                   Tt, Uh, U, U, nw);
-        }
-        SKF_HIP(hipGetLastError());
-    }
-    pm.mark(6);
-    for (const IO& x : io) {
-        if (x.cnt <= 0) continue;
-        hipLaunchKernelGGL((kern::k_scatter_pad<V, V>), dim3(blocks_for(x.cnt * Win, 256)), dim3(256), 0, s,
-                           ge + x.g0, gp + x.g0, x.cnt, Win, Wp, U, static_cast<V*>(x.u));
-        SKF_HIP(hipGetLastError());
-    }
-    pm.mark(7);
-    pm.done();
-}
-
-template <int DIM, int KIND>
-void dispatch(DeviceOp* d, const std::vector<IO>& io, int64_t nrhs, int dtype, hipStream_t s, bool adjoint) {
-    if (dtype == SKELFMM_F64 || dtype == SKELFMM_C128) {
-        using P = kern::Pol<double, double, double, DIM, KIND>;
-        sweep<double, double, P, double>(d, io, nrhs, dtype, s, adjoint, d->T64.as<double>(), d->Tt64.as<double>());
-    } else if (d->f64_leaf) {
-        using P = kern::Pol<double, double, float, DIM, KIND>;
-        sweep<float, float, P, double>(d, io, nrhs, dtype, s, adjoint, d->T32.as<float>(), d->Tt32.as<float>());
-    } else {
-        using P = kern::Pol<float, double, float, DIM, KIND>;
-        sweep<float, float, P, float>(d, io, nrhs, dtype, s, adjoint, d->T32.as<float>(), d->Tt32.as<float>());
-    }
+    if (L.kind == 1 && L.dim == 2) sweep_helm2(d, io, nrhs, dtype, s, adjoint, w);
+    else if (L.kind == 1) sweep_helm3(d, io, nrhs, dtype, s, adjoint, w);
+    else if (L.dim == 3) sweep_lap3(d, io, nrhs, dtype, s, adjoint, w);
+    else sweep_lap2(d, io, nrhs, dtype, s, adjoint, w);
 }
 
 void run(DeviceOp* d, const std::vector<IO>& io, int64_t nrhs, int dtype, void* stream, bool adjoint) {
@@ -564,10 +227,7 @@ void run(DeviceOp* d, const std::vector<IO>& io, int64_t nrhs, int dtype, void* 
     if (d->uploaded && dev != d->device) throw std::invalid_argument("operator was prepared on another device");
     device_prepare(d, nrhs, dtype);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const Layout& L = d->L;
-    if (L.kind == 1) dispatch<3, 1>(d, io, nrhs, dtype, s, adjoint);
-    else if (L.dim == 3) dispatch<3, 0>(d, io, nrhs, dtype, s, adjoint);
-    else dispatch<2, 0>(d, io, nrhs, dtype, s, adjoint);
+    sweep_any(d, io, nrhs, dtype, s, adjoint, d->own_work());
 }
 
 }  // namespace
@@ -576,52 +236,67 @@ void device_apply(DeviceOp* d, const void* q, void* u, int64_t nrhs, int dtype, 
     run(d, {IO{q, u, 0, d->L.n_points}}, nrhs, dtype, stream, adjoint);
 }
 
-// Time the near-field launches for 1 .. 4 targets per lane on this operator
-// (workspace contents are whatever the last apply left; timing does not depend
-// on values) and keep the fastest.
-template <int DIM, int KIND>
-static void tune_near(DeviceOp* d, int dtype, hipStream_t s, float* ms_out) {
-    const bool single = dtype_is_single(dtype);
-    for (int t : {1, 2, 3, 4}) {
-        d->tpl = t;
-        hipEvent_t a, b;
-        SKF_HIP(hipEventCreate(&a));
-        SKF_HIP(hipEventCreate(&b));
+int device_autotune(DeviceOp* d, int dtype, void* stream, float* ms_out) {
+    device_prepare(d, 1, dtype);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const Layout& L = d->L;
+    if (L.kind == 1 && L.dim == 2) tune_helm2(d, dtype, s, ms_out);
+    else if (L.kind == 1) tune_helm3(d, dtype, s, ms_out);
+    else if (L.dim == 3) tune_lap3(d, dtype, s, ms_out);
+    else tune_lap2(d, dtype, s, ms_out);
+    return d->tpl;
+}
+
+// Time the matrix-core transfers (every level, upward then downward) in each
+// launch shape on this operator's workspace and keep the fastest.  Values do
+// not matter for the timing, and no shape changes the results.
+int device_autotune_xfer(DeviceOp* d, int64_t nrhs, void* stream, float* ms_out) {
+    if (!use_mfma(d, nrhs, SKELFMM_F32))
+        throw NotSupported("the matrix-core transfers serve float32 Laplace applies with at least 8 right-hand sides");
+    device_prepare(d, nrhs, SKELFMM_F32);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const Layout& L = d->L;
+    const int Wp = static_cast<int>(padded_width(nrhs, SKELFMM_F32, true));
+    const float* T = d->T32.as<float>();
+    const float* Tt = d->Tt32.as<float>();
+    float* Q = d->Q.as<float>();
+    float* Qh = d->Qh.as<float>();
+    float* U = d->U.as<float>();
+    float* Uh = d->Uh.as<float>();
+    hipEvent_t a, b;
+    SKF_HIP(hipEventCreate(&a));
+    SKF_HIP(hipEventCreate(&b));
+    for (int c = 0; c < SKELFMM_NXFER; ++c) {
+        d->xfer = c;
         for (int rep = 0; rep < 4; ++rep) {
             if (rep == 1) SKF_HIP(hipEventRecord(a, s));
-            if (!single) {
-                using P = kern::Pol<double, double, double, DIM, KIND>;
-                launch_near<P, false>(d, s, d->Q.p, d->Qh.p, d->U.p, d->Uh.p);
-            } else if (d->f64_leaf) {
-                using P = kern::Pol<double, double, float, DIM, KIND>;
-                launch_near<P, false>(d, s, d->Q.p, d->Qh.p, d->U.p, d->Uh.p);
-            } else {
-                using P = kern::Pol<float, double, float, DIM, KIND>;
-                launch_near<P, false>(d, s, d->Q.p, d->Qh.p, d->U.p, d->Uh.p);
-            }
+            for (int l = L.max_level; l >= 2; --l) xfer_level(d, s, true, l, Wp, T, Q, Qh, Tt, Uh, U);
+            for (int l = 2; l <= L.max_level; ++l) xfer_level(d, s, false, l, Wp, T, Q, Qh, Tt, Uh, U);
         }
         SKF_HIP(hipEventRecord(b, s));
         SKF_HIP(hipEventSynchronize(b));
         float ms = 0.f;
         SKF_HIP(hipEventElapsedTime(&ms, a, b));
-        ms_out[tpl_slot(t)] = ms / 3.0f;
-        (void)hipEventDestroy(a);
-        (void)hipEventDestroy(b);
+        ms_out[c] = ms / 3.0f;
     }
-    int best = 1;
-    for (int t : {1, 2, 3, 4})
-        if (ms_out[tpl_slot(t)] < ms_out[tpl_slot(best)]) best = t;
-    d->tpl = best;
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    int best = 0;
+    for (int c = 1; c < SKELFMM_NXFER; ++c)
+        if (ms_out[c] < ms_out[best]) best = c;
+    d->xfer = best;
+    return best;
 }
 
-int device_autotune(DeviceOp* d, int dtype, void* stream, float* ms_out) {
-    device_prepare(d, 1, dtype);
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    const Layout& L = d->L;
-    if (L.kind == 1) tune_near<3, 1>(d, dtype, s, ms_out);
-    else if (L.dim == 3) tune_near<3, 0>(d, dtype, s, ms_out);
-    else tune_near<2, 0>(d, dtype, s, ms_out);
-    return d->tpl;
+void device_set_xfer(DeviceOp* d, int shape) {
+    if (shape < 0 || shape >= SKELFMM_NXFER) throw std::invalid_argument("transfer launch shape out of range");
+    d->xfer = shape;
+}
+
+DeviceOp* batch_merged(DeviceBatch* b) { return b->merged.get(); }
+
+int batch_autotune_xfer(DeviceBatch* b, int64_t nrhs, void* stream, float* ms_out) {
+    return device_autotune_xfer(b->merged.get(), nrhs, stream, ms_out);
 }
 
 void device_set_tpl(DeviceOp* d, int tpl) {
@@ -691,6 +366,10 @@ DeviceBatch* batch_create(const std::vector<DeviceOp*>& ops) {
     b->merged->L.allow_expanded = ops[0]->L.allow_expanded;
     if (ops[0]->L.sym) make_symmetric(b->merged->L, kSymGroup);
     b->merged->f64_leaf = ops[0]->f64_leaf;
+    for (auto* o : ops)
+        if (o->compensated != ops[0]->compensated)
+            throw std::invalid_argument("batched operators must share compensated_leaf");
+    b->merged->compensated = ops[0]->compensated;
     check_ranks(b->merged->L);
     b->gbase.assign(ops.size() + 1, 0);
     for (size_t i = 0; i < ops.size(); ++i) b->gbase[i + 1] = b->gbase[i] + ops[i]->L.n_points;
@@ -711,3 +390,4 @@ void batch_apply(DeviceBatch* b, const void* const* q, void* const* u, int64_t n
 void batch_destroy(DeviceBatch* b) { delete b; }
 
 }  // namespace skelfmm
+

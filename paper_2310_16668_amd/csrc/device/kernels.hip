@@ -17,9 +17,12 @@
 // runs over a prefix of the same loop.
 //
 // Precision.  Coordinates, their differences and |d|^2 are always float64:
-// float64 add / multiply-add issue at the float32 rate on CDNA4, and float32
-// differences of nearby points lose their relative precision whenever the
-// points sit far from the coordinate origin (a clustered surface).  Policies:
+// float32 differences of nearby points lose their relative precision whenever
+// the points sit far from the coordinate origin (a clustered surface).  A
+// float64 add or multiply-add issues in four cycles per wavefront against two
+// for a float32 multiply-add, so |d|^2 costs about as much as the reciprocal
+// square root; the pair kernel's expanded form keeps it to one add and three
+// multiply-adds.  Policies:
 //   F64   kernel value and accumulators in float64 (reciprocal square root
 //         refined by one Newton step);
 //   F32   |d|^2 rounded once to float32, kernel value (reciprocal square root,
@@ -30,6 +33,7 @@
 
 #include <cstdint>
 
+#include "../hankel.h"
 #include "device.h"
 
 namespace skelfmm {
@@ -73,26 +77,47 @@ __device__ __forceinline__ float neg_log_r2(float r2) { return r2 > 0.0f ? -__lo
 __device__ __forceinline__ void sin_cos(double x, double* s, double* c) { sincos(x, s, c); }
 __device__ __forceinline__ void sin_cos(float x, float* s, float* c) { sincosf(x, s, c); }
 
-template <typename R, typename A, typename V, int DIM, int KIND>
+template <typename R, typename A, typename V, int DIM, int KIND, bool COMP = false>
 struct Pol {
     using Rt = R;   // kernel evaluation (coordinates are float64 in every policy)
     using At = A;   // accumulators
     using Vt = V;   // stored vectors
     static constexpr int dim = DIM;
     static constexpr int kind = KIND;   // 0 Laplace, 1 Helmholtz
+    // float32 pair kernel: partial sums of at most four products before they
+    // reach float64, column sums over the lanes in float64
+    static constexpr bool comp = COMP;
     static constexpr int nv = KIND == 1 ? 2 : 1;
     // 3D Laplace in float64 evaluates 2/r (see two_inv_r); the factor is undone in the scale
     static constexpr bool twice = DIM == 3 && KIND == 0 && sizeof(R) == 8;
     static constexpr double gscale = twice ? 0.5 : 1.0;
 };
+// The same policy with the pair kernel's compensated leaf sums.
+template <class P>
+using WithComp = Pol<typename P::Rt, typename P::At, typename P::Vt, P::dim, P::kind, true>;
 
-// G(x_t, x_s) without the common factor 1/(4 pi) (for 2D: -log r^2, i.e. the
-// kernel times 4 pi), applied once at the end.  MASK: zero the pair at r = 0
+// G(x_t, x_s) without the common factor kscale (for 2D Laplace: -log r^2, the
+// kernel times 4 pi; for 2D Helmholtz: i H0^(1)(kappa r), the kernel times 4),
+// applied once at the end.  MASK: zero the pair at r = 0
 // (only needed where a box meets itself).  Real kernels return gr only.
+// The common factor applied once at the end: 1 / (4 pi) for the 3D kernels and
+// for 2D Laplace (evaluated as -log r^2), 1/4 for 2D Helmholtz (evaluated as
+// i H0^(1)).
+template <class P>
+constexpr double kscale() { return (P::dim == 2 && P::kind == 1) ? 0.25 : kInv4Pi; }
+
 template <class P, bool CONJ, bool MASK>
 __device__ __forceinline__ void green_r2(double r2d, typename P::Rt kappa, typename P::Rt& gr,
                                          typename P::Rt& gi) {
     using R = typename P::Rt;
+    if constexpr (P::dim == 2 && P::kind == 1) {
+        // i H0^(1)(kappa r) = -Y0 + i J0, evaluated in float64 in every policy
+        double j0 = 0.0, y0 = 0.0;
+        if (r2d > 0.0) hankel::h0(static_cast<double>(kappa) * sqrt(r2d), &j0, &y0);
+        gr = static_cast<R>(-y0);
+        gi = static_cast<R>(CONJ ? -j0 : j0);
+        return;
+    }
     const R r2 = static_cast<R>(r2d);
     R ir;
     if constexpr (sizeof(R) == 8) ir = (P::twice) ? two_inv_r(r2) : inv_r(r2);
@@ -497,6 +522,23 @@ __device__ __forceinline__ B column_sum(const B (&r)[kSymBlock], B* tile, int la
     return v;
 }
 
+// The same column sums formed in float64 (the compensated leaf sums): each of
+// the four lanes of a column converts its 16 values and adds them in float64.
+template <typename B>
+__device__ __forceinline__ double column_sum_f64(const B (&r)[kSymBlock], B* tile, int lane) {
+#pragma unroll
+    for (int c = 0; c < kSymBlock; ++c) tile[c * kSymRow + lane] = r[c];
+    wave_sync();
+    const int c = lane >> 2, q = lane & 3;
+    double v = 0.0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v += static_cast<double>(tile[c * kSymRow + q + 4 * i]);
+    wave_sync();
+    v += __shfl_xor(v, 1);
+    v += __shfl_xor(v, 2);
+    return v;
+}
+
 // One source of a block, staged in the wave's LDS area.
 // A block's sources staged in the wave's LDS area: positions and charges in
 // separate arrays, so a source costs two 16-byte reads and one charge read.
@@ -578,19 +620,41 @@ __device__ __forceinline__ void sym_block(const SrcStage<typename P::Rt>* src, i
                 rh[c] = fma(g, whi[p], rh[c]);
             }
         }
+        // compensated leaf sums: the forward partials reach float64 every four sources
+        if constexpr (P::comp && sizeof(R) == 4) {
+            if (c % 4 == 3 && c != kSymBlock - 1) {
+#pragma unroll
+                for (int p = 0; p < TPL; ++p) {
+                    acc[p] += static_cast<A>(bacc[p]);
+                    bacc[p] = R(0);
+                    if constexpr (H) {
+                        acch[p] += static_cast<A>(bh[p]);
+                        bh[p] = R(0);
+                    }
+                }
+            }
+        }
     }
 #pragma unroll
     for (int p = 0; p < TPL; ++p) {
         acc[p] += static_cast<A>(bacc[p]);
         if constexpr (H) acch[p] += static_cast<A>(bh[p]);
     }
-    {
+    if constexpr (P::comp && sizeof(R) == 4) {
+        const double v = column_sum_f64<R>(ru, tile, lane);
+        if (own) rev_u[s0 + cs] = prev_u + sc * v;
+    } else {
         const R v = column_sum<R>(ru, tile, lane);
         if (own) rev_u[s0 + cs] = prev_u + sc * static_cast<double>(v);
     }
     if constexpr (H) {
-        const R v = column_sum<R>(rh, tile, lane);
-        if (own) rev_h[s0 + cs] = prev_h - sc * static_cast<double>(v);
+        if constexpr (P::comp && sizeof(R) == 4) {
+            const double v = column_sum_f64<R>(rh, tile, lane);
+            if (own) rev_h[s0 + cs] = prev_h - sc * v;
+        } else {
+            const R v = column_sum<R>(rh, tile, lane);
+            if (own) rev_h[s0 + cs] = prev_h - sc * static_cast<double>(v);
+        }
     }
 }
 
@@ -1265,6 +1329,233 @@ __global__ void __launch_bounds__(256) k_downward_mr(const BoxRec* __restrict__ 
             const double uh = static_cast<double>(Uh[(tb.hoff + i) * Wp + c]) +
                               static_cast<double>(U[static_cast<int64_t>(pmap[tb.hoff + i]) * Wp + c]);
             U[(tb.voff + i) * Wp + c] = static_cast<V>(static_cast<double>(U[(tb.voff + i) * Wp + c]) + uh);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// many right-hand sides, float32 policy: transfers on the matrix cores
+// ---------------------------------------------------------------------------
+// The upward transfer of a box is the product qhat = Q_S + T Q_R (T k x m,
+// Q_R m x W); the downward one u_R += T^T X with X = uhat + the parent's u at
+// the box's slots.  Both are GEMMs C += A B whose left factor A (T, or T^T) is
+// read row by row: rows of T are the columns of the stored T^T copy and rows of
+// T^T the columns of T, so each is contiguous and padded to a multiple of 32
+// entries.  A work item is one block of WPB wavefronts over 32 WPB rows of C
+// and one group of 32 NT columns; wave w owns the 32-row tile w and NT 32 x 32
+// accumulator tiles of v_mfma_f32_32x32x2f32.  The inner dimension runs in
+// chunks of kXK: the block stages the chunk's kXK rows of B in LDS (double
+// buffered, one barrier per chunk, the next chunk's loads in flight during the
+// current chunk's MFMAs), and each lane holds 16 consecutive entries of its A
+// row, so MFMA step u of a chunk pairs column j0 + 16 h + u of A (lane half h)
+// with row j0 + 16 h + u of B.  Every kXferFlush chunks the float32 tiles are
+// added to float64 totals, so no float32 partial sum holds more than
+// 32 kXferFlush products; the MFMA sequence of a tile is the same in every
+// launch shape (WPB, NT), so all shapes give the same bits.
+constexpr int kXK = 32;          // inner-dimension entries per LDS chunk (16 MFMA steps)
+constexpr int kXPitch = 68;      // LDS row pitch in floats (16-byte aligned rows)
+constexpr int kXferFlush = 2;    // chunks per float32 partial (64 products)
+constexpr int kXferRowsPerWave = 32;
+
+// Row of accumulator register v in a 32 x 32 tile (lane l: column l % 32).
+__device__ __forceinline__ int mfma_row(int v, int half) { return 8 * (v / 4) + 4 * half + (v % 4); }
+
+// The lane's 16 entries of its A row for chunk j0 (zeros for a row past the end).
+__device__ __forceinline__ void xfer_load_a(const float* __restrict__ arow, int j0, int half, float4 (&a)[4]) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        a[i] = arow ? *reinterpret_cast<const float4*>(arow + j0 + 16 * half + 4 * i) : make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+// 16 MFMA steps of one chunk: B rows from the staged LDS chunk.
+template <int NT>
+__device__ __forceinline__ void xfer_chunk(const float4 (&a)[4], const float* __restrict__ bs, int lane,
+                                           floatx16 (&c)[NT]) {
+    const int col = lane & 31, half = lane >> 5;
+    const float* av = reinterpret_cast<const float*>(a);
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const float* brow = bs + (16 * half + u) * kXPitch + col;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) c[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[u], brow[32 * t], c[t], 0, 0, 0);
+    }
+}
+
+// The GEMM of one work item.  arow: the lane's A row (null past the last row),
+// K inner entries; brow(j, q) loads float4 q of B row j (j < K) of the column
+// group; the result tiles land in acc (float64).
+template <int WPB, int NT, typename BF>
+__device__ __forceinline__ void xfer_gemm(const float* __restrict__ arow, bool wave_rows, int K, int ncol4,
+                                          BF brow, float* __restrict__ smem, double (&acc)[NT][16]) {
+    constexpr int NQ = 8 * NT;                        // float4 per staged row
+    constexpr int PER = (kXK * NQ + 64 * WPB - 1) / (64 * WPB);
+    const int tid = threadIdx.x, lane = tid & 63, half = lane >> 5;
+    const int nch = (K + kXK - 1) / kXK;
+    float4 breg[PER];
+    auto fetch_b = [&](int j0) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int idx = tid + i * 64 * WPB;
+            const int r = idx / NQ, q = idx - r * NQ;
+            breg[i] = (idx < kXK * NQ && j0 + r < K && q < ncol4) ? brow(j0 + r, q) : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    };
+    auto store_b = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int idx = tid + i * 64 * WPB;
+            const int r = idx / NQ, q = idx - r * NQ;
+            if (idx < kXK * NQ) *reinterpret_cast<float4*>(smem + buf * kXK * kXPitch + r * kXPitch + 4 * q) = breg[i];
+        }
+    };
+    floatx16 c[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) c[t] = floatx16{};
+    float4 a[4], an[4];
+    if (nch > 0) {
+        fetch_b(0);
+        if (wave_rows) xfer_load_a(arow, 0, half, a);
+        store_b(0);
+    }
+    __syncthreads();
+    for (int ch = 0; ch < nch; ++ch) {
+        const bool more = ch + 1 < nch;
+        if (more) {
+            fetch_b((ch + 1) * kXK);
+            if (wave_rows) xfer_load_a(arow, (ch + 1) * kXK, half, an);
+        }
+        if (wave_rows) xfer_chunk<NT>(a, smem + (ch & 1) * kXK * kXPitch, lane, c);
+        if (wave_rows && (ch % kXferFlush == kXferFlush - 1 || !more)) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    acc[t][v] += static_cast<double>(c[t][v]);
+                    c[t][v] = 0.0f;
+                }
+        }
+        if (more) {
+            store_b((ch + 1) & 1);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = an[i];
+        }
+        __syncthreads();
+    }
+}
+
+// upward: work item = (box, first row r0 of a block of 32 WPB of its k skeleton
+// rows) x column group.  Writes qhat to Qh and to the parent's entries; reads
+// this level's entries of Q and writes the parent level's: the two never overlap.
+template <int WPB, int NT>
+__global__ void __launch_bounds__(256) k_upward_mfma(const int2* __restrict__ work, int ngroups,
+                                                    const BoxRec* __restrict__ box, const int64_t* __restrict__ ttoff,
+                                                    const int32_t* __restrict__ pmap, int Wp,
+                                                    const float* __restrict__ Tt, float* __restrict__ Q,
+                                                    float* __restrict__ Qh) {
+    __shared__ __align__(16) float smem[2 * kXK * kXPitch];
+    const int lane = threadIdx.x & 63, half = lane >> 5, col = lane & 31;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int2 wk = work[blockIdx.x / ngroups];
+    const int c0 = (blockIdx.x % ngroups) * kMfmaTile * NT;
+    const int ncol4 = min(Wp - c0, kMfmaTile * NT) / 4;
+    const BoxRec tb = box[wk.x];
+    const int k = tb.k, m = tb.n - tb.k;
+    const int r0w = wk.y + kXferRowsPerWave * wave;
+    const bool wave_rows = r0w < k;
+    const int r = r0w + col;
+    // row r of T = column r of the stored T^T (m entries, padded)
+    const float* arow = (wave_rows && r < k) ? Tt + ttoff[wk.x] + static_cast<int64_t>(r) * ld_pad(m) : nullptr;
+    double acc[NT][16];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[t][v] = 0.0;
+    const float* __restrict__ Qr = Q + (tb.voff + k) * Wp + c0;
+    xfer_gemm<WPB, NT>(arow, wave_rows, m, ncol4,
+                       [&](int j, int q) { return *reinterpret_cast<const float4*>(Qr + static_cast<int64_t>(j) * Wp + 4 * q); },
+                       smem, acc);
+    if (!wave_rows) return;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int rr = r0w + mfma_row(v, half);
+        if (rr < k) {
+            const int64_t pe = static_cast<int64_t>(pmap[tb.hoff + rr]) * Wp;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const int c = c0 + kMfmaTile * t + col;
+                if (c >= Wp) continue;
+                const float val = static_cast<float>(static_cast<double>(Q[(tb.voff + rr) * Wp + c]) + acc[t][v]);
+                Qh[(tb.hoff + rr) * Wp + c] = val;
+                Q[pe + c] = val;
+            }
+        }
+    }
+}
+
+// downward: work item = (box, first row r0 of a block of 32 WPB of its m
+// redundant rows; a box without redundant rows has one item) x column group:
+// u[k + r] += sum_i T^T[r, i] x_i with x = uhat + the parent's u at the slots;
+// the items of row 0 also add x to the box's skeleton entries.  Reads uhat and
+// the parent level's u, writes this box's entries only.
+template <int WPB, int NT>
+__global__ void __launch_bounds__(256) k_downward_mfma(const int2* __restrict__ work, int ngroups,
+                                                      const BoxRec* __restrict__ box, const int64_t* __restrict__ toff,
+                                                      const int32_t* __restrict__ pmap, int Wp,
+                                                      const float* __restrict__ T, const float* __restrict__ Uh,
+                                                      float* __restrict__ U) {
+    __shared__ __align__(16) float smem[2 * kXK * kXPitch];
+    const int lane = threadIdx.x & 63, half = lane >> 5, col = lane & 31;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int2 wk = work[blockIdx.x / ngroups];
+    const int c0 = (blockIdx.x % ngroups) * kMfmaTile * NT;
+    const int ncol4 = min(Wp - c0, kMfmaTile * NT) / 4;
+    const BoxRec tb = box[wk.x];
+    const int k = tb.k, m = tb.n - tb.k;
+    const int32_t* __restrict__ pm = pmap + tb.hoff;
+    const float* __restrict__ uh = Uh + tb.hoff * Wp + c0;
+    const float* __restrict__ up = U + c0;
+    if (m > 0) {
+        const int r0w = wk.y + kXferRowsPerWave * wave;
+        const bool wave_rows = r0w < m;
+        const int r = r0w + col;
+        // row r of T^T = column r of T (k entries, padded)
+        const float* arow = (wave_rows && r < m) ? T + toff[wk.x] + static_cast<int64_t>(r) * ld_pad(k) : nullptr;
+        double acc[NT][16];
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[t][v] = 0.0;
+        xfer_gemm<WPB, NT>(arow, wave_rows, k, ncol4,
+                           [&](int i, int q) {
+                               const float4 x = *reinterpret_cast<const float4*>(uh + static_cast<int64_t>(i) * Wp + 4 * q);
+                               const float4 y = *reinterpret_cast<const float4*>(up + static_cast<int64_t>(pm[i]) * Wp + 4 * q);
+                               return make_float4(x.x + y.x, x.y + y.y, x.z + y.z, x.w + y.w);
+                           },
+                           smem, acc);
+        if (wave_rows) {
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int rr = r0w + mfma_row(v, half);
+                if (rr < m) {
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) {
+                        const int c = c0 + kMfmaTile * t + col;
+                        if (c >= Wp) continue;
+                        float* u = U + (tb.voff + k + rr) * Wp + c;
+                        *u = static_cast<float>(static_cast<double>(*u) + acc[t][v]);
+                    }
+                }
+            }
+        }
+    }
+    if (wk.y == 0) {
+        const int w = 4 * ncol4;
+        for (int e = threadIdx.x; e < k * w; e += blockDim.x) {
+            const int i = e / w, c = c0 + e - i * w;
+            float* u = U + (tb.voff + i) * Wp + c;
+            const double x = static_cast<double>(Uh[(tb.hoff + i) * Wp + c]) +
+                             static_cast<double>(U[static_cast<int64_t>(pm[i]) * Wp + c]);
+            *u = static_cast<float>(static_cast<double>(*u) + x);
         }
     }
 }

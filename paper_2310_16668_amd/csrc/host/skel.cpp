@@ -11,8 +11,9 @@
 //       edges).
 // For a real symmetric kernel the concatenated matrix of equation (5) has two
 // identical blocks, so M alone is compressed.  For the complex symmetric
-// Helmholtz kernel, [M; conj M] is unitarily equivalent to sqrt2 [Re M; Im M],
-// a real matrix, so the interpolation matrix comes out real.
+// Helmholtz kernels (3D exp(i kappa r) / (4 pi r), 2D (i/4) H0^(1)(kappa r)),
+// [M; conj M] is unitarily equivalent to sqrt2 [Re M; Im M], a real matrix, so
+// the interpolation matrix comes out real.
 // Column-pivoted Householder QR (pivot: largest remaining column norm, lowest
 // index on ties) stops at the first pivot with |R_jj| <= tol |R_11|; the first
 // k pivots are the skeleton, T = R11^{-1} R12.
@@ -22,6 +23,7 @@
 #include <numeric>
 #include <stdexcept>
 
+#include "../hankel.h"
 #include "parallel.h"
 #include "plan.h"
 
@@ -185,9 +187,15 @@ void skeletonize_box(const Plan& p, int b, BoxSkel& out) {
             const double rr = std::sqrt(s);
             if (p.kind == 0) {
                 col[r] = p.dim == 2 ? -std::log(rr) / (2 * kPi) : 1.0 / (4 * kPi * rr);
-            } else {
+            } else if (p.dim == 3) {
                 col[r] = std::cos(p.kappa * rr) / (4 * kPi * rr);
                 col[np + r] = std::sin(p.kappa * rr) / (4 * kPi * rr);
+            } else {
+                // (i/4) H0^(1)(kappa r) = (-Y0 + i J0) / 4
+                double j0, y0;
+                hankel::h0(p.kappa * rr, &j0, &y0);
+                col[r] = -0.25 * y0;
+                col[np + r] = 0.25 * j0;
             }
         }
     }

@@ -300,7 +300,6 @@ void skeletonize(Plan& p, const std::vector<int64_t>& order, const std::vector<i
 void build_plan(Plan& p) {
     if (p.dim != 2 && p.dim != 3) throw std::invalid_argument("dim must be 2 or 3");
     if (p.kind != 0 && p.kind != 1) throw std::invalid_argument("unknown kernel kind");
-    if (p.kind == 1 && p.dim != 3) throw std::invalid_argument("Helmholtz is supported in 3D only");
     if (p.kind == 1 && !(p.kappa >= 0.0 && std::isfinite(p.kappa))) throw std::invalid_argument("kappa must be >= 0");
     if (p.n <= 0) throw std::invalid_argument("n must be positive");
     if (!(p.tol > 0.0 && p.tol < 1.0)) throw std::invalid_argument("tol must be in (0, 1)");

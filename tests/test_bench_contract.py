@@ -1,5 +1,4 @@
 """bench.py contract checks that need no GPU."""
-import hashlib
 import json
 import os
 import subprocess
@@ -18,16 +17,21 @@ def test_more_than_one_gpu_is_refused():
     assert "error" in json.loads(r.stdout.strip().splitlines()[-1])
 
 
-def test_traffic_table_matches_the_kernel_source():
-    """roofline.traffic is reported only for the kernel source its counters were
-    taken on: a change to the kernels needs the FETCH_SIZE / WRITE_SIZE runs again."""
-    src = os.path.join(ROOT, "paper_2310_16668_amd", "csrc", "device", "kernels.hip")
-    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+def test_traffic_is_reported_only_for_the_measured_kernel_source(monkeypatch):
+    """roofline.traffic comes from FETCH_SIZE / WRITE_SIZE runs of one source of the
+    pair kernel: it is reported for that source only, and null after any change."""
     tr = bench.NEAR_TRAFFIC["f32"]
     assert tr["kernel"] == "k_near_sym"
-    assert tr["kernels_sha256"] == digest
     assert sorted(tr["bytes_by_tpl"]) == [1, 2, 3, 4]
     assert all(v > 0 for v in tr["bytes_by_tpl"].values())
+    digest = bench.pair_kernel_digest()
+    assert len(digest) == 16
+    monkeypatch.setitem(tr, "kernels_sha256", digest)
+    assert bench.near_traffic("f32", "k_near_sym", 3) == tr["bytes_by_tpl"][3]
+    assert bench.near_traffic("f32", "k_near", 3) is None
+    assert bench.near_traffic("f64", "k_near_sym", 3) is None
+    monkeypatch.setitem(tr, "kernels_sha256", "0" * 16)
+    assert bench.near_traffic("f32", "k_near_sym", 3) is None
 
 
 def test_alu_peaks_are_the_published_vector_figures():

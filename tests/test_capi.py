@@ -39,7 +39,7 @@ def _build_raw(points, n, dim=3, kind=0, kappa=0.0, tol=1e-6, leaf=16, opt=None,
 
 @pytest.mark.parametrize("case,expect", [
     ("null_points", -1), ("n_zero", -1), ("bad_dim", -1), ("tol_zero", -1), ("tol_one", -1),
-    ("leaf_zero", -1), ("neg_kappa", -1), ("nan_point", -1), ("helm_2d", -4), ("bad_kind", -1),
+    ("leaf_zero", -1), ("neg_kappa", -1), ("nan_point", -1), ("helm_2d_neg_kappa", -1), ("bad_kind", -1),
     ("null_out", -1), ("bad_proxy", -1),
 ])
 def test_build_argument_errors(case, expect):
@@ -63,8 +63,8 @@ def test_build_argument_errors(case, expect):
         y = x.copy()
         y[5, 1] = np.nan
         st, _ = _build_raw(y, 100)
-    elif case == "helm_2d":
-        st, _ = _build_raw(np.ascontiguousarray(x[:, :2]), 100, dim=2, kind=1, kappa=1.0)
+    elif case == "helm_2d_neg_kappa":
+        st, _ = _build_raw(np.ascontiguousarray(x[:, :2]), 100, dim=2, kind=1, kappa=-1.0)
     elif case == "bad_kind":
         st, _ = _build_raw(x, 100, kind=7)
     elif case == "null_out":

@@ -29,6 +29,7 @@ CASES = {
     "lap3d_uniform": (lambda: workloads.uniform_points(4000, 3, 22), "laplace", 0.0, 32),
     "lap3d_ellipsoid": (lambda: workloads.ellipsoid_points(5000, 23), "laplace", 0.0, 24),
     "helm3d_uniform": (lambda: workloads.uniform_points(4000, 3, 24), "helmholtz", 15.0, 32),
+    "helm2d_uniform": (lambda: workloads.uniform_points(3000, 2, 25), "helmholtz", 100.0, 24),
 }
 
 
@@ -54,7 +55,8 @@ def test_no_compression_equals_direct(case):
 
 
 @pytest.mark.parametrize("dim,kind,kappa,geom", [(2, "laplace", 0.0, "uniform"), (3, "laplace", 0.0, "uniform"),
-                                                 (3, "laplace", 0.0, "ellipsoid"), (3, "helmholtz", 10.0, "uniform")])
+                                                 (3, "laplace", 0.0, "ellipsoid"), (3, "helmholtz", 10.0, "uniform"),
+                                                 (2, "helmholtz", 40.0, "uniform")])
 def test_matrix_form_equals_o2(dim, kind, kappa, geom):
     x = workloads.uniform_points(700, dim, 31) if geom == "uniform" else workloads.ellipsoid_points(900, 32)
     op = sk.build(x, kind, tol=1e-4, leaf_size=12, kappa=kappa)

@@ -5,8 +5,10 @@ arithmetic (no kernel, no tree, no skeletonization), so both the HIP path and
 the CPU oracle can take their inputs from it without sharing any code.
 
 Every array is produced on the host in float64 with numpy's PCG64 generator.
-Seeds follow one rule per workload number ``c``: points ``1000 + c``, charges
-``1100 + c``, target subset ``1200 + c``, weights ``1300 + c``.
+Seeds follow one rule per workload number ``c`` (1 .. 6): points ``1000 + c``,
+charges ``1100 + c``, target subset ``1200 + c``, weights ``1300 + c``; the
+geometries of the batched workload (c = 5) add their index g as a second word
+of the seed, ``[1000 + c, g]``.
 
 The paper's experiments use synthetic point clouds (uniform square / cube,
 sphere surface; section "Numerical results").  The workloads below take those
@@ -20,7 +22,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 
-def _rng(seed: int) -> np.random.Generator:
+def _rng(seed) -> np.random.Generator:
     return np.random.Generator(np.random.PCG64(seed))
 
 
@@ -92,9 +94,14 @@ class Workload:
     complex_charges: bool = False
     n_targets: int = 2048
     extra: dict = field(default_factory=dict)
+    index: int | None = None      # geometry index inside a batched workload
+
+    def _seed(self, base: int):
+        s = base + self.number
+        return s if self.index is None else [s, self.index]
 
     def points(self) -> np.ndarray:
-        seed = 1000 + self.number
+        seed = self._seed(1000)
         if self.geometry == "uniform":
             return uniform_points(self.n, self.dim, seed)
         if self.geometry == "ellipsoid":
@@ -102,24 +109,28 @@ class Workload:
         raise ValueError(self.geometry)
 
     def charges(self, nrhs: int | None = None) -> np.ndarray:
-        return charges(self.n, nrhs or self.nrhs, 1100 + self.number, self.complex_charges)
+        return charges(self.n, nrhs or self.nrhs, self._seed(1100), self.complex_charges)
 
     def targets(self, m: int | None = None) -> np.ndarray:
-        return target_subset(self.n, m or self.n_targets, 1200 + self.number)
+        return target_subset(self.n, m or self.n_targets, self._seed(1200))
 
     def weights(self, nrhs: int | None = None) -> np.ndarray:
-        return normal_weights(self.n, nrhs or self.nrhs, 1300 + self.number)
+        return normal_weights(self.n, nrhs or self.nrhs, self._seed(1300))
 
 
 # 2D Laplace, N = 16,384 uniform in the unit square, leaf <= 64, tol 1e-8.
-LAPLACE2D_16K = Workload("laplace2d_uniform_16k", 0, 2, "laplace", 16384, 1e-8, 64, "uniform")
+LAPLACE2D_16K = Workload("laplace2d_uniform_16k", 1, 2, "laplace", 16384, 1e-8, 64, "uniform")
 # 3D Laplace, N = 2^20 uniform in the unit cube, leaf <= 128, tol 1e-7.
-LAPLACE3D_1M = Workload("laplace3d_uniform_1m", 1, 3, "laplace", 1 << 20, 1e-7, 128, "uniform")
+LAPLACE3D_1M = Workload("laplace3d_uniform_1m", 2, 3, "laplace", 1 << 20, 1e-7, 128, "uniform")
 # 3D Laplace, N = 2^22 on the (1, 0.5, 0.25) ellipsoid surface, leaf <= 128, tol 1e-6.
-LAPLACE3D_ELLIPSOID_4M = Workload("laplace3d_ellipsoid_4m", 2, 3, "laplace", 1 << 22, 1e-6, 128, "ellipsoid")
+LAPLACE3D_ELLIPSOID_4M = Workload("laplace3d_ellipsoid_4m", 3, 3, "laplace", 1 << 22, 1e-6, 128, "ellipsoid")
 # 3D Helmholtz kappa = 20, N = 2^20 uniform, complex charges, leaf <= 128, tol 1e-6.
-HELMHOLTZ3D_1M = Workload("helmholtz3d_k20_uniform_1m", 3, 3, "helmholtz", 1 << 20, 1e-6, 128, "uniform",
+HELMHOLTZ3D_1M = Workload("helmholtz3d_k20_uniform_1m", 4, 3, "helmholtz", 1 << 20, 1e-6, 128, "uniform",
                           kappa=20.0, complex_charges=True)
+# 2D Helmholtz kappa = 100 (the paper's 2D Helmholtz wavenumber), N = 16,384 uniform
+# in the unit square, complex charges, leaf <= 64, tol 1e-8.
+HELMHOLTZ2D_16K = Workload("helmholtz2d_k100_uniform_16k", 6, 2, "helmholtz", 16384, 1e-8, 64, "uniform",
+                           kappa=100.0, complex_charges=True)
 
 
 def batch_sizes(n_geom: int = 8, n_min: int = 65536, n_max: int = 2097152) -> list[int]:
@@ -134,8 +145,8 @@ def batch_workloads(n_geom: int = 8, sizes: list[int] | None = None, nrhs: int =
     out = []
     for g, n in enumerate(sizes):
         geo = "uniform" if g % 2 == 0 else "ellipsoid"
-        out.append(Workload(f"batch_g{g}_{geo}_{n}", 40 + g, 3, "laplace", n, 1e-6, 128, geo, nrhs=nrhs))
+        out.append(Workload(f"batch_g{g}_{geo}_{n}", 5, 3, "laplace", n, 1e-6, 128, geo, nrhs=nrhs, index=g))
     return out
 
 
-ALL = {w.name: w for w in (LAPLACE2D_16K, LAPLACE3D_1M, LAPLACE3D_ELLIPSOID_4M, HELMHOLTZ3D_1M)}
+ALL = {w.name: w for w in (LAPLACE2D_16K, LAPLACE3D_1M, LAPLACE3D_ELLIPSOID_4M, HELMHOLTZ3D_1M, HELMHOLTZ2D_16K)}
