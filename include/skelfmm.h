@@ -81,8 +81,9 @@ typedef struct {
                                 ifo terms cancel exactly (default 0: they are skipped) */
     int32_t f64_leaf;        /* C64/F32 applies: evaluate and accumulate the near field in float64 */
     int32_t nonsymmetric;    /* 1: evaluate both orders of every colleague pair separately (default 0:
-                                for the real Laplace kernels one evaluation of G(B_i, B_j) serves
-                                the ifo terms i <- j and j <- i; single-RHS applies only) */
+                                one evaluation of G(B_i, B_j) serves the ifo terms i <- j and j <- i,
+                                since G(x, y) = G(y, x) for every kernel here (real for Laplace,
+                                complex symmetric for Helmholtz); single-RHS applies only) */
     int32_t no_expansion;    /* 1: the float32 pair kernel always forms |d|^2 from coordinate
                                 differences (default 0: pairs whose distance bound allows it use
                                 the expanded form |t'|^2 + |s'|^2 - 2 t'.s', see skelfmm_stats) */
@@ -91,7 +92,11 @@ typedef struct {
                                 forms its per-source column sums in float64 before everything is
                                 accumulated in float64 (default 0: float32 partials over blocks of 16
                                 sources and float32 column sums over the 64 x tpl targets of a pass) */
-    int32_t reserved[5];
+    int32_t gpu_build;       /* 1: skelfmm_build computes the interpolative decompositions (proxy
+                                matrices, pivoted QR, T = R11^{-1} R12) level by level on the current
+                                HIP device; the tree and neighbor lists stay on the host (default 0:
+                                all on the host).  ENOTSUP when no HIP device is present */
+    int32_t reserved[4];
 } skelfmm_options;
 
 /* Build-time and layout statistics (section 5 / table "Notation for reported results"). */
@@ -147,7 +152,9 @@ typedef struct {
 
 /* Build the operator for n points (host buffer, n x dim row-major, copied) with
  * interpolative-decomposition tolerance tol in (0, 1) and leaf size >= 1.
- * Host-only and synchronous; touches no GPU.  On success *out owns the operator. */
+ * Synchronous; host-only unless options->gpu_build is set (then the IDs run on
+ * the current HIP device and the device memory they used is freed on return).
+ * On success *out owns the operator. */
 skelfmm_status skelfmm_build(const double* points, int64_t n, skelfmm_kernel kernel, double tol,
                              int32_t leaf_size, const skelfmm_options* opt, skelfmm_op** out);
 

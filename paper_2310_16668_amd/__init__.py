@@ -47,7 +47,8 @@ class Options(ctypes.Structure):
                 ("proxy_scale", ctypes.c_double), ("no_compression", ctypes.c_int32),
                 ("num_threads", ctypes.c_int32), ("keep_transparent", ctypes.c_int32),
                 ("f64_leaf", ctypes.c_int32), ("nonsymmetric", ctypes.c_int32), ("no_expansion", ctypes.c_int32),
-                ("compensated_leaf", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("compensated_leaf", ctypes.c_int32), ("gpu_build", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
 
 
 class Stats(ctypes.Structure):
@@ -272,14 +273,16 @@ class Operator:
 def build(points, kind: str = "laplace", tol: float = 1e-6, leaf_size: int = 64, kappa: float = 0.0,
           proxy_shape: int = 0, proxy_points: int = 0, proxy_scale: float = 0.0, no_compression: bool = False,
           num_threads: int = 0, keep_transparent: bool = False, f64_leaf: bool = False,
-          symmetric: bool = True, expansion: bool = True, compensated_leaf: bool = False) -> Operator:
+          symmetric: bool = True, expansion: bool = True, compensated_leaf: bool = False,
+          gpu_build: bool = False) -> Operator:
     """Build the skeleton operator for ``points`` (n x dim, host, float64).
 
     ``symmetric=False`` evaluates both orders of every colleague pair separately
     (the pairing applies to the real Laplace kernels with one right-hand side);
     ``expansion=False`` keeps the float32 pair kernel on coordinate differences;
     ``compensated_leaf=True`` keeps its float32 partial sums to four products and
-    forms its column sums in float64."""
+    forms its column sums in float64; ``gpu_build=True`` computes the
+    interpolative decompositions on the current HIP device."""
     pts = np.ascontiguousarray(points, dtype=np.float64)
     if pts.ndim != 2:
         raise ValueError("points must be n x dim")
@@ -292,6 +295,7 @@ def build(points, kind: str = "laplace", tol: float = 1e-6, leaf_size: int = 64,
     o.nonsymmetric = int(not symmetric)
     o.no_expansion = int(not expansion)
     o.compensated_leaf = int(compensated_leaf)
+    o.gpu_build = int(gpu_build)
     h = _vp()
     _check(_lib.skelfmm_build(pts.ctypes.data_as(_P(ctypes.c_double)), n, k, tol, leaf_size,
                               ctypes.byref(o), ctypes.byref(h)))

@@ -12,7 +12,8 @@ LIB = os.path.join(HERE, "libskelfmm.so")
 OBJ = os.path.join(HERE, "_build")
 
 HOST_SOURCES = ["capi.cpp", "host/tree.cpp", "host/skel.cpp", "device/layout.cpp"]
-DEVICE_SOURCES = ["device/sweep_lap3.hip", "device/sweep_helm3.hip", "device/sweep_lap2.hip", "device/sweep_helm2.hip", "device/exec.hip"]
+DEVICE_SOURCES = ["device/sweep_lap3.hip", "device/sweep_helm3.hip", "device/sweep_lap2.hip", "device/sweep_helm2.hip", "device/exec.hip",
+                  "device/build_gpu.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function"]

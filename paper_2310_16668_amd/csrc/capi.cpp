@@ -109,6 +109,7 @@ skelfmm_status skelfmm_build(const double* points, int64_t n, skelfmm_kernel ker
             p.opt.proxy_scale = op->opt.proxy_scale;
             p.opt.no_compression = op->opt.no_compression;
             p.opt.num_threads = op->opt.num_threads;
+            p.opt.gpu_build = op->opt.gpu_build;
             if (p.opt.proxy_shape < 0 || p.opt.proxy_shape > 2 || p.opt.proxy_points < 0 || p.opt.proxy_scale < 0)
                 throw std::invalid_argument("invalid proxy options");
             if (p.opt.proxy_shape == 2 && p.dim == 3) throw std::invalid_argument("the proxy circle is 2D only");

@@ -103,8 +103,10 @@ Layout make_layout(const Plan& p, bool keep_transparent, int tile);
 // Work list for another tile size, largest estimated cost first, over the full
 // segment lists (ns = false) or the lists left after symmetric pairing (ns = true).
 std::vector<Task> make_tasks(const Layout& L, int tile, bool ns = false);
-// Pair up colleague segments of compressed boxes for the symmetric near field.
-void make_symmetric(Layout& L, int group);
+// Pair up colleague segments of compressed boxes for the symmetric near field;
+// self_items: a box's segment with itself becomes one pair item too (else it
+// stays on the segment lists).
+void make_symmetric(Layout& L, int group, bool self_items);
 // Kernel evaluations of the pair items with tpl targets per lane: out[0] pairs
 // serving both directions, out[1] their skeleton pairs, out[2] one-direction
 // evaluations in the diagonal tiles of self items, out[3] their skeleton pairs.

@@ -39,8 +39,9 @@ DeviceOp* device_create(const Plan& p, bool keep_transparent, bool f64_leaf, boo
     auto d = std::make_unique<DeviceOp>();
     d->L = make_layout(p, keep_transparent, 64 * kDefaultTPL);
     d->L.allow_expanded = expanded;
-    // the pairing needs G(x, y) = G(y, x) with real values
-    if (symmetric && p.kind == 0) make_symmetric(d->L, kSymGroup);
+    // the pairing needs G(x, y) = G(y, x): the real Laplace kernels, and the
+    // complex-symmetric Helmholtz kernels (distinct boxes only)
+    if (symmetric) make_symmetric(d->L, kSymGroup, p.kind == 0);
     d->f64_leaf = f64_leaf;
     d->compensated = compensated;
     check_ranks(d->L);
@@ -195,7 +196,7 @@ static WorkBytes work_bytes(const DeviceOp* d, int64_t nrhs, int dtype) {
     const size_t vb = dtype_is_single(dtype) ? 4 : 8;
     const size_t wp = static_cast<size_t>(padded_width(nrhs, dtype, use_mfma(d, nrhs, dtype)));
     return WorkBytes{static_cast<size_t>(d->L.n_entries) * wp * vb, static_cast<size_t>(d->L.n_hentries) * wp * vb,
-                     d->L.sym ? static_cast<size_t>(d->L.slot_size) * sizeof(double) : 0};
+                     d->L.sym ? static_cast<size_t>(d->L.slot_size) * sizeof(double) * (d->L.kind == 1 ? 2 : 1) : 0};
 }
 
 // Uploads the operator for dtype; nrhs >= 1 also sizes its own workspace.
@@ -364,7 +365,7 @@ DeviceBatch* batch_create(const std::vector<DeviceOp*>& ops) {
         if (o->L.sym != ops[0]->L.sym || o->L.allow_expanded != ops[0]->L.allow_expanded)
             throw std::invalid_argument("batched operators must share the pairing options");
     b->merged->L.allow_expanded = ops[0]->L.allow_expanded;
-    if (ops[0]->L.sym) make_symmetric(b->merged->L, kSymGroup);
+    if (ops[0]->L.sym) make_symmetric(b->merged->L, kSymGroup, b->merged->L.kind == 0);
     b->merged->f64_leaf = ops[0]->f64_leaf;
     for (auto* o : ops)
         if (o->compensated != ops[0]->compensated)

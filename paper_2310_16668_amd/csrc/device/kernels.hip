@@ -166,7 +166,7 @@ struct alignas(32) BoxRec {
 // load).
 // ---------------------------------------------------------------------------
 template <int NV>
-constexpr int chunks_max() { return 16 / NV; }
+constexpr int chunks_max() { return 32 / NV; }
 
 template <int NV>
 __device__ __forceinline__ int chunk_len(int cols) {
@@ -199,7 +199,7 @@ __device__ __forceinline__ void gemv_chunk(const TT* __restrict__ A, int64_t ld,
     using M = RowMap<TT>;
     using VT = typename Vec8<TT>::type;
     if (M::vec * lane >= rows) return;
-#pragma unroll 4
+#pragma unroll 8
     for (int c = c0; c < c1; ++c) {
         double x[NV];
         xf(c, x);
@@ -1492,16 +1492,31 @@ __global__ void __launch_bounds__(256) k_upward_mfma(const int2* __restrict__ wo
     }
 }
 
+// downward, first step of a level: x = uhat + the parent's u at the box's slots,
+// formed in place in uhat (one block per box of the level), so the level's
+// GEMMs read contiguous rows.  uhat is not read again in the sweep.
+template <typename V>
+__global__ void __launch_bounds__(256) k_down_prep(const BoxRec* __restrict__ box, const int32_t* __restrict__ pmap,
+                                                  int b0, int Wp, const V* __restrict__ U, V* __restrict__ Uh) {
+    const BoxRec tb = box[b0 + blockIdx.x];
+    const int64_t cnt = static_cast<int64_t>(tb.k) * Wp;
+    V* __restrict__ x = Uh + tb.hoff * Wp;
+    const int32_t* __restrict__ pm = pmap + tb.hoff;
+    for (int64_t e = threadIdx.x; e < cnt; e += blockDim.x) {
+        const int64_t i = e / Wp, c = e - i * Wp;
+        x[e] = x[e] + U[static_cast<int64_t>(pm[i]) * Wp + c];
+    }
+}
+
 // downward: work item = (box, first row r0 of a block of 32 WPB of its m
 // redundant rows; a box without redundant rows has one item) x column group:
-// u[k + r] += sum_i T^T[r, i] x_i with x = uhat + the parent's u at the slots;
-// the items of row 0 also add x to the box's skeleton entries.  Reads uhat and
-// the parent level's u, writes this box's entries only.
+// u[k + r] += sum_i T^T[r, i] x_i with x (uhat + the parent's u at the slots)
+// formed by k_down_prep; the items of row 0 also add x to the box's skeleton
+// entries.  Reads x and writes this box's entries only.
 template <int WPB, int NT>
 __global__ void __launch_bounds__(256) k_downward_mfma(const int2* __restrict__ work, int ngroups,
                                                       const BoxRec* __restrict__ box, const int64_t* __restrict__ toff,
-                                                      const int32_t* __restrict__ pmap, int Wp,
-                                                      const float* __restrict__ T, const float* __restrict__ Uh,
+                                                      int Wp, const float* __restrict__ T, const float* __restrict__ X,
                                                       float* __restrict__ U) {
     __shared__ __align__(16) float smem[2 * kXK * kXPitch];
     const int lane = threadIdx.x & 63, half = lane >> 5, col = lane & 31;
@@ -1511,9 +1526,7 @@ __global__ void __launch_bounds__(256) k_downward_mfma(const int2* __restrict__ 
     const int ncol4 = min(Wp - c0, kMfmaTile * NT) / 4;
     const BoxRec tb = box[wk.x];
     const int k = tb.k, m = tb.n - tb.k;
-    const int32_t* __restrict__ pm = pmap + tb.hoff;
-    const float* __restrict__ uh = Uh + tb.hoff * Wp + c0;
-    const float* __restrict__ up = U + c0;
+    const float* __restrict__ xb = X + tb.hoff * Wp + c0;
     if (m > 0) {
         const int r0w = wk.y + kXferRowsPerWave * wave;
         const bool wave_rows = r0w < m;
@@ -1527,9 +1540,7 @@ __global__ void __launch_bounds__(256) k_downward_mfma(const int2* __restrict__ 
             for (int v = 0; v < 16; ++v) acc[t][v] = 0.0;
         xfer_gemm<WPB, NT>(arow, wave_rows, k, ncol4,
                            [&](int i, int q) {
-                               const float4 x = *reinterpret_cast<const float4*>(uh + static_cast<int64_t>(i) * Wp + 4 * q);
-                               const float4 y = *reinterpret_cast<const float4*>(up + static_cast<int64_t>(pm[i]) * Wp + 4 * q);
-                               return make_float4(x.x + y.x, x.y + y.y, x.z + y.z, x.w + y.w);
+                               return *reinterpret_cast<const float4*>(xb + static_cast<int64_t>(i) * Wp + 4 * q);
                            },
                            smem, acc);
         if (wave_rows) {
@@ -1553,9 +1564,209 @@ __global__ void __launch_bounds__(256) k_downward_mfma(const int2* __restrict__ 
         for (int e = threadIdx.x; e < k * w; e += blockDim.x) {
             const int i = e / w, c = c0 + e - i * w;
             float* u = U + (tb.voff + i) * Wp + c;
-            const double x = static_cast<double>(Uh[(tb.hoff + i) * Wp + c]) +
-                             static_cast<double>(U[static_cast<int64_t>(pm[i]) * Wp + c]);
-            *u = static_cast<float>(static_cast<double>(*u) + x);
+            *u = static_cast<float>(static_cast<double>(*u) + static_cast<double>(X[(tb.hoff + i) * Wp + c]));
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// symmetric near field of the complex-symmetric Helmholtz kernels (one RHS)
+// ---------------------------------------------------------------------------
+// G(x, y) = G(y, x) holds for exp(i kappa r) / (4 pi r) and (i/4) H0^(1)(kappa r)
+// as well (the kernel is complex symmetric, not Hermitian), so the terms
+// i <- j and j <- i of two distinct colleagues (or distinct top-level boxes)
+// share one evaluation of every kernel value, as in the real pair kernel:
+//   forward  u_i[t]  += G(t, s) q_j[s]          uhat_i[t] -= G(t, s) qhat_j[s]
+//   reverse  u_j[s]  += G(t, s) q_i[t]          uhat_j[s] -= G(t, s) qhat_i[t]
+// with complex products (the adjoint conjugates G in both directions).  A box
+// paired with itself is left to k_near.  A work item is one wavefront: passes
+// of 64 TPL targets of box i in the lanes against the sources of box j in
+// wave-uniform blocks of kSymBlockC staged in the wave's LDS area.  Forward
+// sums accumulate in float64 per product; reverse sums are formed per block in
+// the lanes (TPL products), summed over the lanes in float64 through the
+// wave's LDS tile (eight lanes per source and a shuffle tree), and added to
+// the item's slot row.  Slot offsets count complex entries (two doubles).
+constexpr int kSymBlockC = 8;
+constexpr int kSymRowC = 72;     // LDS row pitch: the column reads of a half-wave hit distinct banks
+
+template <typename R>
+struct SrcStageC {
+    SrcPos p[kSymBlockC];
+    R w[kSymBlockC][2];
+    R wh[kSymBlockC][2];
+};
+
+// Column sums of kSymBlockC x 64 lane partials: every lane of source c's group
+// of eight receives the float64 sum over the 64 lanes.
+template <typename B>
+__device__ __forceinline__ double column_sum_c(const B (&r)[kSymBlockC], B* tile, int lane) {
+    constexpr int LPS = 64 / kSymBlockC;
+#pragma unroll
+    for (int c = 0; c < kSymBlockC; ++c) tile[c * kSymRowC + lane] = r[c];
+    wave_sync();
+    const int c = lane / LPS, q = lane % LPS;
+    double v = 0.0;
+#pragma unroll
+    for (int i = 0; i < kSymBlockC; ++i) v += static_cast<double>(tile[c * kSymRowC + q + LPS * i]);
+    wave_sync();
+#pragma unroll
+    for (int o = 1; o < LPS; o <<= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+template <class P, int TPL, bool CONJ>
+__device__ __forceinline__ void sym_pass_c(const SymTask& it, const BoxRec& bi, const BoxRec& bj, int tp,
+                                           const Rec4<double>* __restrict__ X, const typename P::Vt* __restrict__ Q,
+                                           const typename P::Vt* __restrict__ Qh, double* __restrict__ slots,
+                                           typename P::Rt kappa, double sc, typename P::Rt* tile,
+                                           SrcStageC<typename P::Rt>* src, int lane) {
+    using R = typename P::Rt;
+    using A = typename P::At;
+    const bool first = tp == it.t0;
+    const bool hp = tp < bi.k && bj.k > 0;
+    double xt[TPL], yt[TPL], zt[TPL];
+    R wi[TPL][2], whi[TPL][2];
+    A acc[TPL][2], acch[TPL][2];
+#pragma unroll
+    for (int p = 0; p < TPL; ++p) {
+        const int t = tp + lane + 64 * p;
+        const bool ok = t < it.t1;
+        const int tc = ok ? t : it.t1 - 1;
+        const Rec4<double> x = X[bi.voff + tc];
+        xt[p] = x.x; yt[p] = x.y; zt[p] = x.z;
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+            wi[p][v] = ok ? static_cast<R>(Q[(bi.voff + tc) * 2 + v]) : R(0);
+            whi[p][v] = (ok && t < bi.k) ? static_cast<R>(Qh[(bi.hoff + t) * 2 + v]) : R(0);
+            acc[p][v] = A(0);
+            acch[p][v] = A(0);
+        }
+    }
+    double* __restrict__ rev_u = slots + 2 * it.rev_u;
+    double* __restrict__ rev_h = slots + 2 * (it.rev_h >= 0 ? it.rev_h : 0);
+    // sources in blocks: the skeleton of j first (uhat terms when hp), then the rest
+    const int kH = hp ? bj.k : 0;
+    const int nbH = (kH + kSymBlockC - 1) / kSymBlockC;
+    const int nb = nbH + (bj.n - kH + kSymBlockC - 1) / kSymBlockC;
+    const Rec4<double>* __restrict__ Xs = X + bj.voff;
+    const int cs = lane / (64 / kSymBlockC);
+    for (int b = 0; b < nb; ++b) {
+        const bool H = b < nbH;
+        const int s0 = H ? b * kSymBlockC : kH + (b - nbH) * kSymBlockC;
+        const int cnt = min(kSymBlockC, (H ? kH : bj.n) - s0);
+        // the running reverse sums of earlier passes, fetched before the block's arithmetic
+        const bool own = (lane % (64 / kSymBlockC)) == 0 && cs < cnt;
+        double prev_u[2] = {0.0, 0.0}, prev_h[2] = {0.0, 0.0};
+        if (own && !first) {
+            prev_u[0] = rev_u[2 * (s0 + cs)];
+            prev_u[1] = rev_u[2 * (s0 + cs) + 1];
+            if (H) {
+                prev_h[0] = rev_h[2 * (s0 + cs)];
+                prev_h[1] = rev_h[2 * (s0 + cs) + 1];
+            }
+        }
+        wave_sync();
+        if (lane < kSymBlockC) {
+            const int si = s0 + min(lane, cnt - 1);
+            const Rec4<double> x = Xs[si];
+            src->p[lane] = SrcPos{x.x, x.y, x.z, 0.0};
+#pragma unroll
+            for (int v = 0; v < 2; ++v) {
+                src->w[lane][v] = lane < cnt ? static_cast<R>(Q[(bj.voff + si) * 2 + v]) : R(0);
+                src->wh[lane][v] = (lane < cnt && H) ? static_cast<R>(Qh[(bj.hoff + si) * 2 + v]) : R(0);
+            }
+        }
+        wave_sync();
+        R ru[2][kSymBlockC], rh[2][kSymBlockC];
+#pragma unroll
+        for (int c = 0; c < kSymBlockC; ++c) {
+            const SrcPos sv = src->p[c];
+            const R w0 = src->w[c][0], w1 = src->w[c][1];
+            const R h0 = src->wh[c][0], h1 = src->wh[c][1];
+#pragma unroll
+            for (int v = 0; v < 2; ++v) { ru[v][c] = R(0); rh[v][c] = R(0); }
+#pragma unroll
+            for (int p = 0; p < TPL; ++p) {
+                R gr, gi;
+                green<P, CONJ, false>(xt[p] - sv.x, yt[p] - sv.y, zt[p] - sv.z, kappa, gr, gi);
+                const A g = static_cast<A>(gr), h = static_cast<A>(gi);
+                // forward: acc += G w_j
+                acc[p][0] = fma(g, static_cast<A>(w0), fma(-h, static_cast<A>(w1), acc[p][0]));
+                acc[p][1] = fma(g, static_cast<A>(w1), fma(h, static_cast<A>(w0), acc[p][1]));
+                // reverse partial: G w_i
+                ru[0][c] = fma(gr, wi[p][0], fma(-gi, wi[p][1], ru[0][c]));
+                ru[1][c] = fma(gr, wi[p][1], fma(gi, wi[p][0], ru[1][c]));
+                if (H) {
+                    acch[p][0] = fma(g, static_cast<A>(h0), fma(-h, static_cast<A>(h1), acch[p][0]));
+                    acch[p][1] = fma(g, static_cast<A>(h1), fma(h, static_cast<A>(h0), acch[p][1]));
+                    rh[0][c] = fma(gr, whi[p][0], fma(-gi, whi[p][1], rh[0][c]));
+                    rh[1][c] = fma(gr, whi[p][1], fma(gi, whi[p][0], rh[1][c]));
+                }
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+            const double su = column_sum_c<R>(ru[v], tile, lane);
+            if (own) rev_u[2 * (s0 + cs) + v] = prev_u[v] + sc * su;
+        }
+        if (H) {
+#pragma unroll
+            for (int v = 0; v < 2; ++v) {
+                const double sh = column_sum_c<R>(rh[v], tile, lane);
+                if (own) rev_h[2 * (s0 + cs) + v] = prev_h[v] - sc * sh;
+            }
+        }
+    }
+    double* __restrict__ fwd_u = slots + 2 * it.fwd_u;
+    double* __restrict__ fwd_h = slots + 2 * (it.fwd_h >= 0 ? it.fwd_h : 0);
+#pragma unroll
+    for (int p = 0; p < TPL; ++p) {
+        const int t = tp + lane + 64 * p;
+        if (t < it.t1) {
+#pragma unroll
+            for (int v = 0; v < 2; ++v) {
+                fwd_u[2 * (t - it.t0) + v] = sc * static_cast<double>(acc[p][v]);
+                if (t < bi.k) fwd_h[2 * (t - it.t0) + v] = -sc * static_cast<double>(acch[p][v]);
+            }
+        }
+    }
+}
+
+template <class P, int TPL, bool CONJ>
+__global__ void __launch_bounds__(256) k_near_sym_c(const SymTask* __restrict__ tasks, int ntasks,
+                                                    const BoxRec* __restrict__ box,
+                                                    const Rec4<double>* __restrict__ X,
+                                                    const typename P::Vt* __restrict__ Q,
+                                                    const typename P::Vt* __restrict__ Qh,
+                                                    double* __restrict__ slots, typename P::Rt kappa, double scale) {
+    using R = typename P::Rt;
+    __shared__ R tiles[4][kSymBlockC * kSymRowC];
+    __shared__ SrcStageC<R> srcs[4];
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int tid = blockIdx.x * 4 + wv;
+    if (tid >= ntasks) return;
+    const SymTask it = tasks[tid];
+    const BoxRec bi = box[it.bi], bj = box[it.bj];
+    const double sc = scale * P::gscale;
+    for (int tp = it.t0; tp < it.t1; tp += 64 * TPL)
+        sym_pass_c<P, TPL, CONJ>(it, bi, bj, tp, X, Q, Qh, slots, kappa, sc, tiles[wv], &srcs[wv], lane);
+}
+
+// u and uhat of one box += its complex slot rows (two doubles per entry), in row order.
+template <typename V>
+__global__ void __launch_bounds__(256) k_sym_reduce_c(const SymRows* __restrict__ rows,
+                                                      const BoxRec* __restrict__ box,
+                                                      const double* __restrict__ slots, V* __restrict__ U,
+                                                      V* __restrict__ Uh) {
+    const SymRows r = rows[blockIdx.x];
+    const BoxRec rec = box[r.box];
+    for (int e = threadIdx.x; e < 2 * rec.n; e += blockDim.x) {
+        V* u = U + 2 * rec.voff + e;
+        *u = static_cast<V>(add_rows(static_cast<double>(*u), slots + 2 * r.base_u + e, r.ru, 2 * rec.n));
+        if (e < 2 * rec.k && r.rh > 0) {
+            V* uh = Uh + 2 * rec.hoff + e;
+            *uh = static_cast<V>(add_rows(static_cast<double>(*uh), slots + 2 * r.base_h + e, r.rh, 2 * rec.k));
         }
     }
 }

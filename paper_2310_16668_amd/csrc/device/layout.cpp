@@ -276,7 +276,7 @@ Layout make_layout(const Plan& p, bool keep_transparent, int tile) {
 // i, one uhat row) of box j; a box paired with itself has a forward and a
 // reverse row of each kind.  The reduction adds a box's rows to its u and uhat
 // in row order, so results stay deterministic.
-void make_symmetric(Layout& L, int group) {
+void make_symmetric(Layout& L, int group, bool self_items) {
     L.sym = true;
     const int nb = L.n_boxes;
     struct Pair { int32_t bi, bj; };
@@ -293,7 +293,12 @@ void make_symmetric(Layout& L, int group) {
                 continue;
             }
             if (c == b) {   // a box with itself: one item over all its targets
-                if (L.nb[b] > 0) pairs_list.push_back(Pair{b, b});
+                if (!self_items) {
+                    rem[b].push_back(c);
+                    remm[b].push_back(mode);
+                } else if (L.nb[b] > 0) {
+                    pairs_list.push_back(Pair{b, b});
+                }
                 continue;
             }
             if (c < b) continue;   // the pair was handled from the smaller id

@@ -215,7 +215,23 @@ void launch_near_t(const DeviceOp* d, hipStream_t s, void* Q, void* Qh, void* U,
             SKF_HIP(hipGetLastError());
         }
     }
+    if constexpr (P::kind == 1) {
+        if (sym && d->nsym > 0) {
+            hipLaunchKernelGGL((kern::k_near_sym_c<P, TPL, CONJ>), dim3(blocks_for(d->nsym, 4)), dim3(256), 0, s,
+                               d->symtasks.as<SymTask>(), d->nsym, d->boxrec.as<kern::BoxRec>(),
+                               d->X64.as<kern::Rec4<double>>(), static_cast<const V*>(Q), static_cast<const V*>(Qh),
+                               slots, static_cast<R>(d->L.kappa), kern::kscale<P>());
+            SKF_HIP(hipGetLastError());
+        }
+    }
     if (pm) pm->mark(4);
+    if constexpr (P::kind == 1) {
+        if (sym && d->nred > 0) {
+            hipLaunchKernelGGL((kern::k_sym_reduce_c<V>), dim3(d->nred), dim3(256), 0, s, d->symrows.as<SymRows>(),
+                               d->boxrec.as<kern::BoxRec>(), slots, static_cast<V*>(U), static_cast<V*>(Uh));
+            SKF_HIP(hipGetLastError());
+        }
+    }
     if constexpr (P::kind == 0) {
         if (sym && d->nred > 0) {
             hipLaunchKernelGGL((kern::k_sym_reduce<V>), dim3(d->nred), dim3(256), 0, s, d->symrows.as<SymRows>(),
@@ -288,7 +304,7 @@ void launch_near_mfma(const DeviceOp* d, hipStream_t s, int Wp, void* Q, void* Q
 // T^T from the stored T.
 template <int WPB, int NT>
 void xfer_level_t(const DeviceOp* d, hipStream_t s, bool up, int l, int Wp, const float* T, float* Q, float* Qh,
-                  const float* Tt, const float* Uh, float* U) {
+                  const float* Tt, float* Uh, float* U) {
     const int g = WPB == 2 ? 2 : 3;
     const auto& ptr = up ? d->up_ptr[g] : d->down_ptr[g];
     const int64_t w0 = ptr[l], nwk = ptr[l + 1] - w0;
@@ -299,15 +315,20 @@ void xfer_level_t(const DeviceOp* d, hipStream_t s, bool up, int l, int Wp, cons
         hipLaunchKernelGGL((kern::k_upward_mfma<WPB, NT>), dim3(nb), dim3(64 * WPB), 0, s,
                            d->upwork[g].as<int2>() + w0, ng, d->boxrec.as<kern::BoxRec>(), d->ttoff.as<int64_t>(),
                            d->pmap.as<int32_t>(), Wp, Tt, Q, Qh);
-    else
+    else {
+        const int b0 = d->L.level_ptr[l], nbx = d->L.level_ptr[l + 1] - b0;
+        hipLaunchKernelGGL(kern::k_down_prep<float>, dim3(nbx), dim3(256), 0, s, d->boxrec.as<kern::BoxRec>(),
+                           d->pmap.as<int32_t>(), b0, Wp, U, Uh);
+        SKF_HIP(hipGetLastError());
         hipLaunchKernelGGL((kern::k_downward_mfma<WPB, NT>), dim3(nb), dim3(64 * WPB), 0, s,
                            d->downwork[g].as<int2>() + w0, ng, d->boxrec.as<kern::BoxRec>(), d->toff.as<int64_t>(),
-                           d->pmap.as<int32_t>(), Wp, T, Uh, U);
+                           Wp, T, Uh, U);
+    }
     SKF_HIP(hipGetLastError());
 }
 
 inline void xfer_level(const DeviceOp* d, hipStream_t s, bool up, int l, int Wp, const float* T, float* Q,
-                       float* Qh, const float* Tt, const float* Uh, float* U) {
+                       float* Qh, const float* Tt, float* Uh, float* U) {
     const XferShape sh = kXferShapes[d->xfer];
     if (sh.wpb == 4 && sh.nt == 2) xfer_level_t<4, 2>(d, s, up, l, Wp, T, Q, Qh, Tt, Uh, U);
     else if (sh.wpb == 4) xfer_level_t<4, 1>(d, s, up, l, Wp, T, Q, Qh, Tt, Uh, U);

@@ -25,6 +25,15 @@
 #else
 #define SKF_HD
 #endif
+// The error-free transformations below need every sum and product rounded as
+// written: no multiply-add contraction across statements (the device compiler
+// contracts by default, which would fold a product into the sum whose rounding
+// error the next statement recovers).
+#if defined(__clang__)
+#define SKF_EXACT_FP _Pragma("clang fp contract(off)")
+#else
+#define SKF_EXACT_FP
+#endif
 
 namespace skelfmm {
 namespace hankel {
@@ -40,15 +49,18 @@ struct DD {
 };
 
 SKF_HD inline DD two_sum(double a, double b) {
+    SKF_EXACT_FP
     const double s = a + b;
     const double bb = s - a;
     return DD{s, (a - (s - bb)) + (b - bb)};
 }
 SKF_HD inline DD quick_two_sum(double a, double b) {
+    SKF_EXACT_FP
     const double s = a + b;
     return DD{s, b - (s - a)};
 }
 SKF_HD inline DD dd_add(DD a, DD b) {
+    SKF_EXACT_FP
     DD s = two_sum(a.hi, b.hi);
     const DD t = two_sum(a.lo, b.lo);
     s.lo += t.hi;
@@ -58,12 +70,14 @@ SKF_HD inline DD dd_add(DD a, DD b) {
 }
 SKF_HD inline DD dd_neg(DD a) { return DD{-a.hi, -a.lo}; }
 SKF_HD inline DD dd_mul(DD a, DD b) {
+    SKF_EXACT_FP
     const double p = a.hi * b.hi;
     const double e = std::fma(a.hi, b.hi, -p);
     return quick_two_sum(p, e + (a.hi * b.lo + a.lo * b.hi));
 }
 // a / d for a double d
 SKF_HD inline DD dd_div(DD a, double d) {
+    SKF_EXACT_FP
     const double q1 = a.hi / d;
     // remainder a - q1 d, exact in its leading part
     const double p = q1 * d;
@@ -75,6 +89,7 @@ SKF_HD inline DD dd_div(DD a, double d) {
 
 // H0^(1)(x) for x > 0: *j0 = J0(x), *y0 = Y0(x).
 SKF_HD inline void h0(double x, double* j0, double* y0) {
+    SKF_EXACT_FP
     if (x < kSwitch) {
         // q = x^2 / 4 exactly as a double-double
         const double x2 = x * x;

@@ -17,6 +17,7 @@ struct BuildOptions {
     int no_compression = 0;    // force k = n everywhere (test mode)
     int max_depth = 20;
     int num_threads = 0;       // 0 = hardware concurrency
+    int gpu_build = 0;         // 1: interpolative decompositions on the current HIP device
 };
 
 struct Plan {

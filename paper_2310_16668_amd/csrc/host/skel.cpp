@@ -20,12 +20,14 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <numeric>
 #include <stdexcept>
 
 #include "../hankel.h"
 #include "parallel.h"
 #include "plan.h"
+#include "skel.h"
 
 namespace skelfmm {
 
@@ -33,59 +35,14 @@ namespace {
 
 constexpr double kPi = 3.14159265358979323846;
 
-struct BoxSkel {
-    std::vector<int64_t> idx;     // natural order
-    int k = 0;
-    std::vector<int64_t> pos;     // [sk | rd]
-    std::vector<double> T;        // k x (n-k) column-major
-};
-
 void proxy_points(const Plan& p, int lev, const int32_t* c, std::vector<double>& Y) {
     const double a = std::ldexp(p.root_side, -lev);
     double ctr[3] = {0, 0, 0};
     for (int d = 0; d < p.dim; ++d) ctr[d] = p.root_lo[d] + (c[d] + 0.5) * a;
-    const double scale = p.opt.proxy_scale > 0 ? p.opt.proxy_scale : 2.95;
-    Y.clear();
-    if (p.dim == 3) {
-        const int q = p.opt.proxy_points > 0 ? p.opt.proxy_points : 10;
-        const double h = 0.5 * scale * a;
-        std::vector<double> t(q);
-        for (int i = 0; i < q; ++i) t[i] = std::cos((2.0 * i + 1.0) * kPi / (2.0 * q));
-        for (int ax = 0; ax < 3; ++ax)
-            for (int sgn = -1; sgn <= 1; sgn += 2)
-                for (int i = 0; i < q; ++i)
-                    for (int j = 0; j < q; ++j) {
-                        double y[3];
-                        y[ax] = sgn * h;
-                        y[(ax + 1) % 3] = t[i] * h;
-                        y[(ax + 2) % 3] = t[j] * h;
-                        for (int d = 0; d < 3; ++d) Y.push_back(ctr[d] + y[d]);
-                    }
-    } else {
-        const bool circle = p.opt.proxy_shape != 1;
-        if (circle) {
-            const int m = p.opt.proxy_points > 0 ? p.opt.proxy_points : 128;
-            const double r = 0.5 * scale * a;
-            for (int j = 0; j < m; ++j) {
-                const double th = 2.0 * kPi * j / m;
-                Y.push_back(ctr[0] + r * std::cos(th));
-                Y.push_back(ctr[1] + r * std::sin(th));
-            }
-        } else {
-            const int q = p.opt.proxy_points > 0 ? p.opt.proxy_points : 32;
-            const double h = 0.5 * scale * a;
-            for (int ax = 0; ax < 2; ++ax)
-                for (int sgn = -1; sgn <= 1; sgn += 2)
-                    for (int i = 0; i < q; ++i) {
-                        const double t = std::cos((2.0 * i + 1.0) * kPi / (2.0 * q));
-                        double y[2];
-                        y[ax] = sgn * h;
-                        y[1 - ax] = t * h;
-                        Y.push_back(ctr[0] + y[0]);
-                        Y.push_back(ctr[1] + y[1]);
-                    }
-        }
-    }
+    std::vector<double> U;
+    const double h = proxy_pattern(p, U) * a;
+    Y.resize(U.size());
+    for (size_t i = 0; i < U.size(); ++i) Y[i] = ctr[i % p.dim] + h * U[i];
 }
 
 // Column-pivoted Householder QR of the column-major m x n matrix A (destroyed),
@@ -206,6 +163,45 @@ void skeletonize_box(const Plan& p, int b, BoxSkel& out) {
 
 }  // namespace
 
+double proxy_pattern(const Plan& p, std::vector<double>& U) {
+    const double scale = p.opt.proxy_scale > 0 ? p.opt.proxy_scale : 2.95;
+    U.clear();
+    if (p.dim == 3) {
+        const int q = p.opt.proxy_points > 0 ? p.opt.proxy_points : 10;
+        std::vector<double> t(q);
+        for (int i = 0; i < q; ++i) t[i] = std::cos((2.0 * i + 1.0) * kPi / (2.0 * q));
+        for (int ax = 0; ax < 3; ++ax)
+            for (int sgn = -1; sgn <= 1; sgn += 2)
+                for (int i = 0; i < q; ++i)
+                    for (int j = 0; j < q; ++j) {
+                        double y[3];
+                        y[ax] = sgn;
+                        y[(ax + 1) % 3] = t[i];
+                        y[(ax + 2) % 3] = t[j];
+                        for (int d = 0; d < 3; ++d) U.push_back(y[d]);
+                    }
+    } else if (p.opt.proxy_shape != 1) {
+        const int m = p.opt.proxy_points > 0 ? p.opt.proxy_points : 128;
+        for (int j = 0; j < m; ++j) {
+            const double th = 2.0 * kPi * j / m;
+            U.push_back(std::cos(th));
+            U.push_back(std::sin(th));
+        }
+    } else {
+        const int q = p.opt.proxy_points > 0 ? p.opt.proxy_points : 32;
+        for (int ax = 0; ax < 2; ++ax)
+            for (int sgn = -1; sgn <= 1; sgn += 2)
+                for (int i = 0; i < q; ++i) {
+                    double y[2];
+                    y[ax] = sgn;
+                    y[1 - ax] = std::cos((2.0 * i + 1.0) * kPi / (2.0 * q));
+                    U.push_back(y[0]);
+                    U.push_back(y[1]);
+                }
+    }
+    return 0.5 * scale;
+}
+
 double host_kernel_real(const Plan& p, const double* x, const double* y) {
     double s = 0.0;
     for (int d = 0; d < p.dim; ++d) { const double t = x[d] - y[d]; s += t * t; }
@@ -219,6 +215,8 @@ void skeletonize(Plan& p, const std::vector<int64_t>& order, const std::vector<i
     const int threads = host_threads(p.opt.num_threads);
     std::vector<BoxSkel> S(nb);
     const int top = p.top_level;
+    std::unique_ptr<LevelSkeletonizer> dev;
+    if (p.opt.gpu_build && !p.opt.no_compression) dev = make_device_skeletonizer(p);
     // index sets and skeletons, deepest level first
     for (int l = p.max_level; l >= top; --l) {
         const int b0 = p.level_ptr[l], b1 = p.level_ptr[l + 1];
@@ -233,14 +231,15 @@ void skeletonize(Plan& p, const std::vector<int64_t>& order, const std::vector<i
                     for (int i = 0; i < c.k; ++i) s.idx.push_back(c.idx[c.pos[i]]);
                 }
             }
-            if (l > top) {
-                skeletonize_box(p, b, s);
-            } else {
+            if (l <= top) {
                 s.k = -1;
                 s.pos.resize(s.idx.size());
                 std::iota(s.pos.begin(), s.pos.end(), 0);
+            } else if (!dev) {
+                skeletonize_box(p, b, s);
             }
         });
+        if (dev && l > top) dev->level(p, b0, b1, S);
     }
     // flatten into CSR arrays (boxes above the top level keep empty sets)
     p.idx_ptr.assign(nb + 1, 0);

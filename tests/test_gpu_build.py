@@ -1,0 +1,132 @@
+"""The interpolative decompositions computed on the GPU (gpu_build): the same
+ID as the host build (column-pivoted QR of the proxy matrix, truncated at
+|R_jj| <= tol |R_11|), so its skeletons may differ from the host's only where
+rounding decides a near tie.  Checks on every kernel family:
+  * the ID residual of sampled boxes on the proxy matrix and on true far-field
+    points (<= 10 tol, the host build's bound);
+  * the whole method against the dense sum O1 (<= 10 tol);
+  * the GPU apply against O2 on the GPU-built plan (float64, <= 1e-12);
+  * ranks within a few percent of the host build's.
+"""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from _record import record
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2310_16668_amd as sk  # noqa: E402
+
+
+def relerr(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+CASES = {
+    "lap3d_uniform_64k": (lambda: workloads.uniform_points(65536, 3, 801), "laplace", 0.0, 1e-7, 128),
+    "lap3d_ellipsoid_60k": (lambda: workloads.ellipsoid_points(60000, 802), "laplace", 0.0, 1e-6, 64),
+    "helm3d_uniform_32k": (lambda: workloads.uniform_points(32768, 3, 803), "helmholtz", 20.0, 1e-6, 64),
+    "lap2d_16k": (lambda: workloads.uniform_points(16384, 2, 804), "laplace", 0.0, 1e-8, 64),
+    "helm2d_k100_16k": (lambda: workloads.uniform_points(16384, 2, 805), "helmholtz", 100.0, 1e-8, 64),
+}
+
+
+def _box_points(P, b):
+    return P["points"][P["idx"][P["idx_ptr"][b]:P["idx_ptr"][b + 1]]]
+
+
+def _proxy_surface(P, b, dim):
+    """The build's proxy points of box b from their definition: 3D first-kind
+    Chebyshev nodes (10 per side) on the faces of a cube of side 2.95 a, 2D 128
+    equispaced points on a circle of radius 1.475 a."""
+    a = P["root_side"] / 2 ** P["level"][b]
+    c = P["root_lo"][:dim] + (P["coord"][b][:dim] + 0.5) * a
+    h = 1.475 * a
+    if dim == 2:
+        th = 2 * np.pi * np.arange(128) / 128
+        return c + h * np.stack([np.cos(th), np.sin(th)], axis=1)
+    t = np.cos((2 * np.arange(10) + 1) * np.pi / 20)
+    Y = []
+    for ax in range(3):
+        for sgn in (-1, 1):
+            for i in range(10):
+                for j in range(10):
+                    y = np.zeros(3)
+                    y[ax] = sgn
+                    y[(ax + 1) % 3], y[(ax + 2) % 3] = t[i], t[j]
+                    Y.append(c + h * y)
+    return np.array(Y)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_gpu_build_matches_contract(name):
+    mk, kind, kappa, tol, b = CASES[name]
+    x = mk()
+    dim = x.shape[1]
+    t0 = time.perf_counter()
+    op = sk.build(x, kind, tol=tol, leaf_size=b, kappa=kappa, gpu_build=True)
+    t_gpu = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    op_h = sk.build(x, kind, tol=tol, leaf_size=b, kappa=kappa)
+    t_host = time.perf_counter() - t0
+    P, Ph = op.export(), op_h.export()
+    st, sh = op.stats(), op_h.stats()
+    # same tree; ranks close to the host build's
+    np.testing.assert_array_equal(P["level"], Ph["level"])
+    kg = np.maximum(P["rank"], 0).sum()
+    kh = np.maximum(Ph["rank"], 0).sum()
+    assert abs(kg - kh) <= 0.02 * kh + 8, (kg, kh)
+    # ID residuals of sampled compressed boxes on the proxy surface and the far field
+    rng = np.random.default_rng(0)
+    boxes = [bb for bb in range(P["n_boxes"])
+             if 0 < P["rank"][bb] < P["idx_ptr"][bb + 1] - P["idx_ptr"][bb]]
+    res_p = res_f = 0.0
+    for bb in rng.choice(boxes, min(6, len(boxes)), replace=False):
+        n = P["idx_ptr"][bb + 1] - P["idx_ptr"][bb]
+        k = P["rank"][bb]
+        pos = P["pos"][P["idx_ptr"][bb]:P["idx_ptr"][bb + 1]]
+        T = P["T"][P["T_ptr"][bb]:P["T_ptr"][bb + 1]].reshape(n - k, k).T
+        xb = _box_points(P, bb)
+        M = oracle.kernel(_proxy_surface(P, bb, dim), xb, kind, kappa)
+        res_p = max(res_p, np.linalg.norm(M[:, pos[k:]] - M[:, pos[:k]] @ T) / np.linalg.norm(M))
+        a = P["root_side"] / 2 ** P["level"][bb]
+        c = P["root_lo"][:dim] + (P["coord"][bb][:dim] + 0.5) * a
+        far = x[np.max(np.abs(x - c), axis=1) > 1.5 * a]
+        F = oracle.kernel(far, xb, kind, kappa)
+        res_f = max(res_f, np.linalg.norm(F[:, pos[k:]] - F[:, pos[:k]] @ T) / np.linalg.norm(F))
+    # the method against the dense sum, and the GPU apply against O2 on this plan
+    q = workloads.charges(x.shape[0], 1, 806, complex_=(kind == "helmholtz"))
+    dt = torch.complex128 if kind == "helmholtz" else torch.float64
+    u = op.apply(torch.from_numpy(q).to("cuda:0", dt)).cpu().numpy()
+    tg = workloads.target_subset(x.shape[0], 2048, 807)
+    e1 = relerr(u[tg], oracle.direct(x, q, kind, kappa, targets=tg))
+    e2 = relerr(u, oracle.apply(P, q))
+    record(f"{name} gpu_build", build_s=t_gpu, host_build_s=t_host, t_skel=st["t_skel"],
+           t_skel_host=sh["t_skel"], ranks=kg, ranks_host=kh, id_res_proxy=res_p, id_res_far=res_f,
+           vs_o1=e1, vs_o2=e2)
+    assert res_p <= 10 * tol and res_f <= 10 * tol
+    assert e1 <= 10 * tol
+    assert e2 <= 1e-12
+
+
+def test_gpu_build_1m_cube():
+    """The 1M-point cube built with the IDs on the GPU: time against the host
+    build, and the result against the dense sum (<= 1e-6 as the benchmark)."""
+    w = workloads.LAPLACE3D_1M
+    x = w.points()
+    t0 = time.perf_counter()
+    op = sk.build(x, "laplace", tol=w.tol, leaf_size=w.leaf_size, gpu_build=True)
+    t_gpu = time.perf_counter() - t0
+    st = op.stats()
+    q = w.charges()
+    tg = w.targets()
+    u = op.apply(torch.from_numpy(q).to("cuda:0", torch.float64)).cpu().numpy()
+    e1 = relerr(u[tg], oracle.direct(x, q, targets=tg))
+    record(f"{w.name} gpu_build", build_s=t_gpu, t_tree=st["t_tree"], t_skel=st["t_skel"], k_max=st["k_max"],
+           vs_o1=e1)
+    assert e1 <= 1e-6

@@ -395,3 +395,35 @@ def test_matrix_core_transfers_every_shape(name, nrhs):
     record(f"{name} {nrhs} rhs float32 matrix-core transfers", vs_o2=e_u, adjoint_vs_o2t=e_w,
            tuned_shape=tuned["shape"])
     assert e_u <= F32_VS_O2 and e_w <= F32_VS_O2
+
+
+@pytest.mark.parametrize("name", ["helm3d_uniform_32k", "helm2d_k100_16k"])
+def test_helmholtz_symmetric_pairing(name):
+    """The complex-symmetric Helmholtz kernels share one evaluation per pair of
+    distinct colleagues between both directions (complex products, conjugated
+    in the adjoint): complex128 against O2 and the unpaired sweep at every
+    targets-per-lane setting, complex64 (float64 leaf sums) against O2."""
+    x, op, P = _op(name)
+    _, op_ns, _ = _op(name, symmetric=False)
+    assert op.stats()["n_sym_tasks"] > 0 and op_ns.stats()["n_sym_tasks"] == 0
+    q = _charges(name, x.shape[0], 12)
+    u2 = oracle.apply(P, q)
+    w2 = oracle.apply(P, q, adjoint=True)
+    un = host(op_ns.apply(dev(q, torch.complex128)))
+    for t in (1, 2, 3, 4):
+        op.set_targets_per_lane(t)
+        u = host(op.apply(dev(q, torch.complex128)))
+        w = host(op.apply_adjoint(dev(q, torch.complex128)))
+        e2, en, ew = relerr(u, u2), relerr(u, un), relerr(w, w2)
+        record(f"{name} c128 paired tpl{t}", vs_o2=e2, vs_unpaired=en, adjoint_vs_o2t=ew)
+        assert e2 <= 1e-12 and en <= 1e-12 and ew <= 1e-12
+    _, op_l, _ = _op(name, f64_leaf=True)
+    qr = q.astype(np.complex64).astype(np.complex128)
+    u2r, w2r = oracle.apply(P, qr), oracle.apply(P, qr, adjoint=True)
+    for t in (1, 2):
+        op_l.set_targets_per_lane(t)
+        uc = host(op_l.apply(dev(q, torch.complex64))).astype(np.complex128)
+        wc = host(op_l.apply_adjoint(dev(q, torch.complex64))).astype(np.complex128)
+        ec, ewc = relerr(uc, u2r), relerr(wc, w2r)
+        record(f"{name} c64 f64-leaf paired tpl{t}", vs_o2=ec, adjoint_vs_o2t=ewc)
+        assert ec <= F32_VS_O2 and ewc <= F32_VS_O2
