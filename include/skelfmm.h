@@ -159,7 +159,8 @@ skelfmm_status skelfmm_build(const double* points, int64_t n, skelfmm_kernel ker
                              int32_t leaf_size, const skelfmm_options* opt, skelfmm_op** out);
 
 /* Upload the operator to the current HIP device and size its workspace for up to
- * nrhs_max right-hand sides of `dtype` (nrhs_max = 0: upload only, no workspace).  Synchronous; may allocate.  Calling apply with a
+ * nrhs_max right-hand sides of `dtype` (nrhs_max = 0: upload only, no workspace;
+ * for skelfmm_apply_noalloc).  Synchronous; may allocate.  Calling apply with a
  * larger nrhs (or a new dtype) prepares implicitly, which then allocates. */
 skelfmm_status skelfmm_prepare(skelfmm_op* op, int64_t nrhs_max, skelfmm_dtype dtype);
 
@@ -170,6 +171,24 @@ skelfmm_status skelfmm_apply(skelfmm_op* op, const void* q, void* u, int64_t nrh
 /* w = Atilde^H v on the GPU (the transposed sweep).  Same layout as skelfmm_apply. */
 skelfmm_status skelfmm_apply_adjoint(skelfmm_op* op, const void* v, void* w, int64_t nrhs,
                                      skelfmm_dtype dtype, void* hip_stream);
+
+/* u = Atilde q (adjoint = 0) or w = Atilde^H v (adjoint = 1) without any device
+ * allocation, for callers that cannot allocate while they apply (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).  The same
+ * sweep and kernels as skelfmm_apply / skelfmm_apply_adjoint, with the same
+ * layout, stream and result; the workspace (entry and skeleton vectors, pair
+ * slots) comes from one static device array of skelfmm_noalloc_scratch_bytes()
+ * bytes (64 MiB) per device, held until the process ends, instead of the
+ * operator.  Requires the operator uploaded for dtype on the current device
+ * (skelfmm_prepare, nrhs_max = 0 is enough).  Errors (before any GPU work):
+ * EINVAL if it is not uploaded, if it was prepared on another device, or if the
+ * apply needs more workspace than the array holds (the message gives both sizes).
+ * Every call on a device shares that device's array and leaves its contents
+ * there; nothing in it needs clearing, but calls that overlap on one device
+ * (two streams, two threads) race on it. */
+skelfmm_status skelfmm_apply_noalloc(skelfmm_op* op, const void* q, void* u, int64_t nrhs,
+                                    skelfmm_dtype dtype, int32_t adjoint, void* hip_stream);
+int64_t skelfmm_noalloc_scratch_bytes(void);
 
 skelfmm_status skelfmm_stats_get(const skelfmm_op* op, skelfmm_stats* out);
 

@@ -104,6 +104,10 @@ _lib.skelfmm_batch_timing.argtypes = [_vp, ctypes.c_int32]
 _lib.skelfmm_batch_timing.restype = ctypes.c_int
 _lib.skelfmm_batch_timing_read.argtypes = [_vp, _P(ctypes.c_double), _P(ctypes.c_int64)]
 _lib.skelfmm_batch_timing_read.restype = ctypes.c_int
+_lib.skelfmm_apply_noalloc.argtypes = [_vp, _vp, _vp, ctypes.c_int64, ctypes.c_int, ctypes.c_int32, _vp]
+_lib.skelfmm_apply_noalloc.restype = ctypes.c_int
+_lib.skelfmm_noalloc_scratch_bytes.argtypes = []
+_lib.skelfmm_noalloc_scratch_bytes.restype = ctypes.c_int64
 _lib.skelfmm_last_error.restype = ctypes.c_char_p
 for _f in ("skelfmm_build", "skelfmm_prepare", "skelfmm_apply", "skelfmm_apply_adjoint", "skelfmm_stats_get",
            "skelfmm_export", "skelfmm_batch_create", "skelfmm_batch_apply", "skelfmm_timing",
@@ -116,7 +120,8 @@ EXPORTED = ("skelfmm_build", "skelfmm_prepare", "skelfmm_apply", "skelfmm_apply_
             "skelfmm_destroy", "skelfmm_last_error", "skelfmm_timing", "skelfmm_timing_read",
             "skelfmm_autotune", "skelfmm_set_targets_per_lane", "skelfmm_autotune_transfers",
             "skelfmm_set_transfer_shape", "skelfmm_batch_autotune_transfers", "skelfmm_batch_timing",
-            "skelfmm_batch_timing_read")
+            "skelfmm_batch_timing_read", "skelfmm_apply_noalloc",
+            "skelfmm_noalloc_scratch_bytes")
 NXFER = 4
 PASSES = ("gather", "upward", "near_field", "near_pairs", "near_reduce", "downward", "output")
 
@@ -264,6 +269,21 @@ class Operator:
     def apply(self, q):
         """u = Atilde q for a device tensor q of shape [n] or [n, nrhs]."""
         return self._run(q, False)
+
+    def apply_noalloc(self, q, out, adjoint: bool = False):
+        """Atilde q (or Atilde^H q) into the caller's tensor ``out`` with the library's
+        static scratch workspace (skelfmm_apply_noalloc): no device allocation.  The
+        operator must be uploaded for q's dtype first (``prepare(0, dtype)``)."""
+        torch = _torch()
+        if not (q.is_cuda and out.is_cuda) or not (q.is_contiguous() and out.is_contiguous()):
+            raise ValueError("q and out must be contiguous device tensors")
+        if q.shape != out.shape or q.dtype != out.dtype or q.shape[0] != self.n:
+            raise ValueError("q and out must have the same shape and dtype, with n rows")
+        nrhs = 1 if q.dim() == 1 else q.shape[1]
+        stream = torch.cuda.current_stream(q.device).cuda_stream
+        _check(_lib.skelfmm_apply_noalloc(self._h, q.data_ptr(), out.data_ptr(), nrhs, _dtype_code(q),
+                                          int(adjoint), stream))
+        return out
 
     def apply_adjoint(self, v):
         """w = Atilde^H v (the transposed sweep)."""

@@ -159,6 +159,21 @@ skelfmm_status skelfmm_apply_adjoint(skelfmm_op* op, const void* v, void* w, int
     return apply_common(op, v, w, nrhs, dtype, hip_stream, true);
 }
 
+skelfmm_status skelfmm_apply_noalloc(skelfmm_op* op, const void* q, void* u, int64_t nrhs, skelfmm_dtype dtype,
+                                    int32_t adjoint, void* hip_stream) {
+    if (!alive(op)) return fail(SKELFMM_EINVAL, "invalid operator");
+    if (!q || !u) return fail(SKELFMM_EINVAL, "NULL vector");
+    if (q == u) return fail(SKELFMM_EINVAL, "input and output must not alias");
+    if (nrhs < 1) return fail(SKELFMM_EINVAL, "nrhs must be >= 1");
+    if (skelfmm_status s = check_dtype(op, dtype)) return s;
+    return guarded([&]() -> skelfmm_status {
+        skelfmm::device_apply_noalloc(op->dev, q, u, nrhs, static_cast<int>(dtype), hip_stream, adjoint != 0);
+        return SKELFMM_OK;
+    });
+}
+
+int64_t skelfmm_noalloc_scratch_bytes(void) { return static_cast<int64_t>(skelfmm::device_scratch_bytes()); }
+
 skelfmm_status skelfmm_stats_get(const skelfmm_op* op, skelfmm_stats* out) {
     if (!alive(op)) return fail(SKELFMM_EINVAL, "invalid operator");
     if (!out) return fail(SKELFMM_EINVAL, "out is NULL");

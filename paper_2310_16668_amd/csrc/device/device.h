@@ -123,6 +123,9 @@ DeviceOp* device_create(const Plan& p, bool keep_transparent, bool f64_leaf, boo
                         bool compensated);
 void device_prepare(DeviceOp* d, int64_t nrhs_max, int dtype);
 void device_apply(DeviceOp* d, const void* q, void* u, int64_t nrhs, int dtype, void* stream, bool adjoint);
+void device_apply_noalloc(DeviceOp* d, const void* q, void* u, int64_t nrhs, int dtype, void* stream,
+                          bool adjoint);
+size_t device_scratch_bytes();
 void device_fill_stats(const DeviceOp* d, skelfmm_stats* out);
 void device_destroy(DeviceOp* d);
 void device_timing(DeviceOp* d, bool enable);

@@ -20,7 +20,14 @@
 // versa, so the segment lists are reused unchanged; the upward pass becomes a
 // top-down pass of the downward form; the gather becomes the output scatter.
 // The adjoint therefore runs the forward launches with the kernel conjugated.
+#include <mutex>
+
 #include "sweep.h"
+
+// Workspace of skelfmm_apply_noalloc (see device_apply_noalloc): one copy per
+// device, held until the process ends.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 namespace skelfmm {
 
@@ -235,6 +242,61 @@ void run(DeviceOp* d, const std::vector<IO>& io, int64_t nrhs, int dtype, void* 
 
 void device_apply(DeviceOp* d, const void* q, void* u, int64_t nrhs, int dtype, void* stream, bool adjoint) {
     run(d, {IO{q, u, 0, d->L.n_points}}, nrhs, dtype, stream, adjoint);
+}
+
+// ---------------------------------------------------------------------------
+// apply without allocation: the workspace lives in a static device array
+// ---------------------------------------------------------------------------
+// For callers that cannot allocate device memory while they apply (code under
+// graph capture, serving loops).  Every sweep writes each workspace entry
+// before it reads it, so the array needs no clearing between calls; it keeps
+// the last call's contents, and calls that overlap on one device race on it.
+namespace {
+
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_ptr;   // device address of `scratch`, per device
+
+// The device address of the array on the current device, looked up once per
+// device (the array's host-side name is not a device address).
+void* scratch_on(int dev) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (static_cast<int>(g_scratch_ptr.size()) <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        SKF_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
+}
+
+constexpr size_t kSpare = 256;   // as DevMem: merged wave-uniform loads at an array's end stay inside
+size_t round_up(size_t x) { return (x + 255) / 256 * 256; }
+
+}  // namespace
+
+size_t device_scratch_bytes() { return kScratchBytes; }
+
+void device_apply_noalloc(DeviceOp* d, const void* q, void* u, int64_t nrhs, int dtype, void* stream,
+                          bool adjoint) {
+    if (nrhs > (int64_t(1) << 20)) throw std::invalid_argument("nrhs too large");
+    const bool single = dtype_is_single(dtype);
+    if (!d->uploaded || (single ? !d->T32.p || !d->Tt32.p : !d->T64.p || !d->Tt64.p))
+        throw std::invalid_argument("operator not uploaded for this dtype: call skelfmm_prepare (nrhs_max = 0 "
+                                    "uploads it without a workspace) before skelfmm_apply_noalloc");
+    int dev = -1;
+    SKF_HIP(hipGetDevice(&dev));
+    if (dev != d->device) throw std::invalid_argument("operator was prepared on another device");
+    const WorkBytes wb = work_bytes(d, nrhs, dtype);
+    const size_t oe = round_up(wb.e + kSpare), oh = round_up(wb.h + kSpare);
+    const size_t need = 2 * oe + 2 * oh + round_up(wb.slots + kSpare);
+    if (need > kScratchBytes)
+        throw std::invalid_argument("this apply needs " + std::to_string(need) + " bytes of workspace; the static " +
+                                    "scratch array holds " + std::to_string(kScratchBytes));
+    unsigned char* base = static_cast<unsigned char*>(scratch_on(dev));
+    // no per-pass events either: this path creates nothing
+    const Work w{base, base + 2 * oe, base + oe, base + 2 * oe + oh,
+                 reinterpret_cast<double*>(base + 2 * oe + 2 * oh), false};
+    sweep_any(d, {IO{q, u, 0, d->L.n_points}}, nrhs, dtype, static_cast<hipStream_t>(stream), adjoint, w);
 }
 
 int device_autotune(DeviceOp* d, int dtype, void* stream, float* ms_out) {
