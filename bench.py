@@ -70,6 +70,10 @@ FLOPS_PER_SYM_SKEL_PAIR = 4
 # multiply-add into uhat (8).  Transcendentals count one flop each.
 FLOPS_PER_HELM_PAIR = 26
 FLOPS_PER_HELM_SKEL_PAIR = 8
+# a paired Helmholtz evaluation serves both directions: the evaluation (18) and two
+# complex multiply-adds (16); a skeleton pair adds two more (16)
+FLOPS_PER_HELM_SYM_PAIR = 34
+FLOPS_PER_HELM_SYM_SKEL_PAIR = 16
 # HBM bytes per near-field launch from rocprofv3 FETCH_SIZE + WRITE_SIZE runs of this
 # workload (scaled by a plain 512 MiB copy: x2.000 fetch, x1.000 write), per
 # targets-per-lane variant, valid only for the kernel and kernel source they were
@@ -196,7 +200,9 @@ def near_kernels(st: dict, pm: dict, helm: bool = False) -> dict:
     pairs_ns = st["pairs_near"] - 2 * st["pairs_sym"] - st["pairs_tile"]
     skel_ns = st["pairs_skel"] - 2 * st["pairs_sym_skel"] - st["pairs_tile_skel"]
     if helm:
-        return {"k_near": (pm["near_field"], FLOPS_PER_HELM_PAIR * pairs_ns + FLOPS_PER_HELM_SKEL_PAIR * skel_ns)}
+        return {"k_near": (pm["near_field"], FLOPS_PER_HELM_PAIR * pairs_ns + FLOPS_PER_HELM_SKEL_PAIR * skel_ns),
+                "k_near_sym_c": (pm["near_pairs"], FLOPS_PER_HELM_SYM_PAIR * st["pairs_sym"]
+                                 + FLOPS_PER_HELM_SYM_SKEL_PAIR * st["pairs_sym_skel"])}
     return {
         "k_near": (pm["near_field"], FLOPS_PER_PAIR * pairs_ns + FLOPS_PER_SKEL_PAIR * skel_ns),
         "k_near_sym": (pm["near_pairs"], FLOPS_PER_SYM_PAIR * st["pairs_sym"]

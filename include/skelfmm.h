@@ -120,6 +120,10 @@ typedef struct {
     int32_t n_sym_expanded;          /* pair items whose float32 evaluation expands |d|^2 about an
                                         origin (the build's distance bound allows it) */
     int32_t reserved[1];
+    double t_skel_qr;                /* seconds of t_skel spent in the interpolative decompositions
+                                        themselves (proxy matrices, pivoted QR, T; on the device with
+                                        gpu_build, copies included) */
+    double t_layout;                 /* seconds to pack the device layout (work lists, pairing) */
 } skelfmm_stats;
 
 /* Read-only host view of the skeleton operators, valid while the operator lives.

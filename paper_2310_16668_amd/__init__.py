@@ -60,7 +60,7 @@ class Stats(ctypes.Structure):
                 ("tile_targets", ctypes.c_int32), ("n_sym_tasks", ctypes.c_int32), ("pairs_sym", ctypes.c_int64),
                 ("pairs_sym_skel", ctypes.c_int64), ("pairs_tile", ctypes.c_int64),
                 ("pairs_tile_skel", ctypes.c_int64), ("n_sym_expanded", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 1)]
+                ("reserved", ctypes.c_int32 * 1), ("t_skel_qr", ctypes.c_double), ("t_layout", ctypes.c_double)]
 
 
 _P = ctypes.POINTER

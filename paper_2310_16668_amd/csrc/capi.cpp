@@ -1,6 +1,7 @@
 // C ABI of the library: argument checks, error reporting, ownership.
 // Every entry point catches all C++ exceptions and turns them into a status
 // code plus a thread-local message.
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -114,9 +115,11 @@ skelfmm_status skelfmm_build(const double* points, int64_t n, skelfmm_kernel ker
                 throw std::invalid_argument("invalid proxy options");
             if (p.opt.proxy_shape == 2 && p.dim == 3) throw std::invalid_argument("the proxy circle is 2D only");
             skelfmm::build_plan(p);
+            const auto tl0 = std::chrono::steady_clock::now();
             op->dev = skelfmm::device_create(p, op->opt.keep_transparent != 0, op->opt.f64_leaf != 0,
                                              op->opt.nonsymmetric == 0, op->opt.no_expansion == 0,
                                              op->opt.compensated_leaf != 0);
+            p.t_layout = std::chrono::duration<double>(std::chrono::steady_clock::now() - tl0).count();
         } catch (...) {
             delete op;
             throw;
@@ -191,6 +194,8 @@ skelfmm_status skelfmm_stats_get(const skelfmm_op* op, skelfmm_stats* out) {
         out->proxy_count = p.proxy_count;
         out->t_tree = p.t_tree;
         out->t_skel = p.t_skel;
+        out->t_skel_qr = p.t_skel_qr;
+        out->t_layout = p.t_layout;
         out->m_proj_elems = static_cast<int64_t>(p.T.size());
         skelfmm::device_fill_stats(op->dev, out);
         return SKELFMM_OK;

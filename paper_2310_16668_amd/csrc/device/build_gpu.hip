@@ -2,13 +2,14 @@
 // equation (5), the proxy-surface ID; section 3, "Build stage", Algorithm
 // "Strong recursive skeletonization").  The host still builds the tree, the
 // neighbor lists and every box's index set; per level, the device
-//   1. evaluates the proxy matrices M = G(Y_B, X_B) of all boxes (m x n,
-//      column-major; Helmholtz: m = 2 np rows, [Re M; Im M], which is unitarily
+//   1. evaluates the proxy matrices M = G(Y_B, X_B) of all boxes (m x n, stored
+//      row by row; Helmholtz: m = 2 np rows, [Re M; Im M], which is unitarily
 //      equivalent to the concatenation [M; conj M] of equation (5), so T is real),
-//   2. runs column-pivoted Householder QR on each of them, one block per box,
-//      stopping at the first pivot with |R_jj| <= tol |R_11| (pivot: largest
-//      remaining column norm, lowest index on ties; norms downdated and
-//      recomputed when cancellation looms, as the host build does),
+//   2. runs column-pivoted Householder QR on each of them, one block per box
+//      and one thread per column, so every step streams the trailing rows with
+//      coalesced loads; it stops at the first pivot with |R_jj| <= tol |R_11|
+//      (pivot: largest remaining column norm, lowest index on ties; norms
+//      downdated and recomputed when cancellation looms, as the host build does),
 //   3. solves T = R11^{-1} R12 by back substitution, one thread per column,
 // and hands k, the pivot order and T back to the host.  The arithmetic is that
 // of the host build in float64; only the summation order differs, so the
@@ -40,17 +41,10 @@ namespace {
     } while (0)
 
 constexpr double kPiB = 3.14159265358979323846;
-constexpr int kQrThreads = 256;
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
-
-// Proxy matrix of box b (blockIdx.y): M[r + a m] = G(y_r, x_idx[a]) (real
-// kernels), rows np..2np-1 the imaginary parts (Helmholtz).  The proxy points
-// are y_r = c_b + h_b U_r, as on the host.
+// Proxy matrix of box b (blockIdx.y), row-major: M[r n + a] = G(y_r, x_idx[a])
+// (real kernels), rows np..2np-1 the imaginary parts (Helmholtz).  The proxy
+// points are y_r = c_b + h_b U_r, as on the host; consecutive threads take
+// consecutive points of one proxy row.
 __global__ void __launch_bounds__(256) k_proxy_matrix(const double* __restrict__ pts, int dim, int kind,
                                                       double kappa, const int32_t* __restrict__ idx,
                                                       const int64_t* __restrict__ ioff,
@@ -65,7 +59,7 @@ __global__ void __launch_bounds__(256) k_proxy_matrix(const double* __restrict__
     const int64_t total = static_cast<int64_t>(np) * n;
     for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
          e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-        const int a = static_cast<int>(e / np), r = static_cast<int>(e - static_cast<int64_t>(a) * np);
+        const int r = static_cast<int>(e / n), a = static_cast<int>(e - static_cast<int64_t>(r) * n);
         const int64_t pi = idx[ioff[b] + a];
         double s = 0.0;
         for (int d = 0; d < dim; ++d) {
@@ -74,50 +68,50 @@ __global__ void __launch_bounds__(256) k_proxy_matrix(const double* __restrict__
             s += t * t;
         }
         const double rr = sqrt(s);
-        double* col = M + moff[b] + static_cast<int64_t>(a) * m;
+        double* row = M + moff[b] + static_cast<int64_t>(r) * n + a;
         if (kind == 0) {
-            col[r] = dim == 2 ? -log(rr) / (2 * kPiB) : 1.0 / (4 * kPiB * rr);
+            row[0] = dim == 2 ? -log(rr) / (2 * kPiB) : 1.0 / (4 * kPiB * rr);
         } else if (dim == 3) {
             double sn, cs;
             sincos(kappa * rr, &sn, &cs);
-            col[r] = cs / (4 * kPiB * rr);
-            col[np + r] = sn / (4 * kPiB * rr);
+            row[0] = cs / (4 * kPiB * rr);
+            row[static_cast<int64_t>(np) * n] = sn / (4 * kPiB * rr);
         } else {
             double j0, y0;
             hankel::h0(kappa * rr, &j0, &y0);
-            col[r] = -0.25 * y0;
-            col[np + r] = 0.25 * j0;
+            row[0] = -0.25 * y0;
+            row[static_cast<int64_t>(np) * n] = 0.25 * j0;
         }
     }
 }
 
-// Column-pivoted Householder QR of box blockIdx.x's m x n matrix A (in place),
-// truncated at |R_jj| <= tol |R_11|.  perm receives the pivot order, kout k;
-// nrm holds 2 n doubles of scratch per box (running and reference column norms).
-__global__ void __launch_bounds__(kQrThreads) k_cpqr(double* __restrict__ M, const int64_t* __restrict__ moff,
-                                                     const int32_t* __restrict__ nn, int m, double tol,
-                                                     int32_t* __restrict__ kout, int32_t* __restrict__ perm,
-                                                     const int64_t* __restrict__ poff, double* __restrict__ nrmbuf) {
+// Column-pivoted Householder QR of box blockIdx.x's m x n matrix A (row-major,
+// in place), truncated at |R_jj| <= tol |R_11|.  Thread t owns columns t,
+// t + blockDim, ... (blockDim a power of two, for the tree reductions); perm
+// receives the pivot order, kout k; nrm holds 2 n doubles of scratch per box
+// (running and reference column norms).
+__global__ void __launch_bounds__(1024) k_cpqr(double* __restrict__ M, const int64_t* __restrict__ moff,
+                                               const int32_t* __restrict__ nn, int m, double tol,
+                                               int32_t* __restrict__ kout, int32_t* __restrict__ perm,
+                                               const int64_t* __restrict__ poff, double* __restrict__ nrmbuf) {
     extern __shared__ double v[];   // the Householder vector, m entries
-    __shared__ double red_v[kQrThreads];
-    __shared__ int red_i[kQrThreads];
-    const int b = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    constexpr int NW = kQrThreads / 64;
+    __shared__ double red_v[1024];
+    __shared__ int red_i[1024];
+    const int b = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
     double* __restrict__ A = M + moff[b];
     const int n = nn[b];
     int32_t* __restrict__ pm = perm + poff[b];
     double* __restrict__ nrm = nrmbuf + 2 * poff[b];
     double* __restrict__ ref = nrm + n;
-    for (int c = wave; c < n; c += NW) {
-        const double* cc = A + static_cast<int64_t>(c) * m;
+    for (int c = tid; c < n; c += nt) {
         double s = 0.0;
-        for (int i = lane; i < m; i += 64) s += cc[i] * cc[i];
-        s = wave_sum(s);
-        if (lane == 0) {
-            nrm[c] = s;
-            ref[c] = s;
-            pm[c] = c;
+        for (int i = 0; i < m; ++i) {
+            const double x = A[static_cast<int64_t>(i) * n + c];
+            s += x * x;
         }
+        nrm[c] = s;
+        ref[c] = s;
+        pm[c] = c;
     }
     __syncthreads();
     const double tol_norm2 = 1.4901161193847656e-08;   // sqrt(2^-52): recompute a norm below this fraction
@@ -128,14 +122,14 @@ __global__ void __launch_bounds__(kQrThreads) k_cpqr(double* __restrict__ M, con
         // pivot: the largest remaining norm, the lowest index on ties
         double best = -1.0;
         int bi = n;
-        for (int c = j + tid; c < n; c += kQrThreads) {
+        for (int c = j + tid; c < n; c += nt) {
             const double x = nrm[c];
             if (x > best) { best = x; bi = c; }
         }
         red_v[tid] = best;
         red_i[tid] = bi;
         __syncthreads();
-        for (int o = kQrThreads / 2; o > 0; o >>= 1) {
+        for (int o = nt / 2; o > 0; o >>= 1) {
             if (tid < o) {
                 const double x = red_v[tid + o];
                 const int xi = red_i[tid + o];
@@ -149,12 +143,11 @@ __global__ void __launch_bounds__(kQrThreads) k_cpqr(double* __restrict__ M, con
         const int piv = red_i[0];
         __syncthreads();
         if (piv != j) {
-            double* cj = A + static_cast<int64_t>(j) * m;
-            double* cp = A + static_cast<int64_t>(piv) * m;
-            for (int i = tid; i < m; i += kQrThreads) {
-                const double t = cj[i];
-                cj[i] = cp[i];
-                cp[i] = t;
+            for (int i = tid; i < m; i += nt) {
+                double* row = A + static_cast<int64_t>(i) * n;
+                const double t = row[j];
+                row[j] = row[piv];
+                row[piv] = t;
             }
             if (tid == 0) {
                 double t = nrm[j]; nrm[j] = nrm[piv]; nrm[piv] = t;
@@ -163,50 +156,53 @@ __global__ void __launch_bounds__(kQrThreads) k_cpqr(double* __restrict__ M, con
             }
         }
         __syncthreads();
-        double* cj = A + static_cast<int64_t>(j) * m;
+        // alpha = |A[j:, j]|: the column's rows, one per thread, then a tree sum
         double s = 0.0;
-        for (int i = j + tid; i < m; i += kQrThreads) s += cj[i] * cj[i];
-        s = wave_sum(s);
-        if (lane == 0) red_v[wave] = s;
+        for (int i = j + tid; i < m; i += nt) {
+            const double x = A[static_cast<int64_t>(i) * n + j];
+            v[i] = x;
+            s += x * x;
+        }
+        red_v[tid] = s;
         __syncthreads();
-        double tot = 0.0;
-        for (int w = 0; w < NW; ++w) tot += red_v[w];
+        for (int o = nt / 2; o > 0; o >>= 1) {
+            if (tid < o) red_v[tid] += red_v[tid + o];
+            __syncthreads();
+        }
+        const double alpha = sqrt(red_v[0]);
         __syncthreads();
-        const double alpha = sqrt(tot);
         if (j == 0) r11 = alpha;
         if (!(alpha > tol * r11) || alpha == 0.0) break;
         // Householder reflector H = I - beta v v^T with H x = rjj e1, v_j = 1
-        const double x0 = cj[j];
+        const double x0 = v[j];
         const double rjj = x0 >= 0 ? -alpha : alpha;
         const double v0 = x0 - rjj;
         const double beta = -v0 / rjj;
-        for (int i = j + tid; i < m; i += kQrThreads) v[i] = i == j ? 1.0 : cj[i] / v0;
         __syncthreads();
-        for (int i = j + tid; i < m; i += kQrThreads) cj[i] = i == j ? rjj : 0.0;
-        // the trailing columns, one wave each
-        for (int c = j + 1 + wave; c < n; c += NW) {
-            double* cc = A + static_cast<int64_t>(c) * m;
-            double w = 0.0, first = 0.0;
-            for (int i = j + lane; i < m; i += 64) {
-                const double x = cc[i];
-                if (i == j) first = x;
-                w += v[i] * x;
-            }
-            w = wave_sum(w) * beta;
-            const double cj_old = __shfl(first, 0);
-            double s2 = 0.0;
-            for (int i = j + lane; i < m; i += 64) {
-                const double x = cc[i] - w * v[i];
-                cc[i] = x;
+        for (int i = j + tid; i < m; i += nt) {
+            v[i] = i == j ? 1.0 : v[i] / v0;
+            A[static_cast<int64_t>(i) * n + j] = i == j ? rjj : 0.0;
+        }
+        __syncthreads();
+        // the trailing columns, one per thread: w = beta v^T A[j:, c]; A[j:, c] -= w v
+        for (int c = j + 1 + tid; c < n; c += nt) {
+            double* col = A + c;
+            double w = 0.0;
+            for (int i = j; i < m; ++i) w += v[i] * col[static_cast<int64_t>(i) * n];
+            w *= beta;
+            double s2 = 0.0, cjn = 0.0;
+            for (int i = j; i < m; ++i) {
+                const double x = col[static_cast<int64_t>(i) * n] - w * v[i];
+                col[static_cast<int64_t>(i) * n] = x;
                 if (i > j) s2 += x * x;
+                else cjn = x;
             }
-            const double cjn = cj_old - w;
             double t = nrm[c] - cjn * cjn;
             if (t <= tol_norm2 * ref[c]) {
-                t = wave_sum(s2);
-                if (lane == 0) ref[c] = t;
+                t = s2;
+                ref[c] = t;
             }
-            if (lane == 0) nrm[c] = t > 0.0 ? t : 0.0;
+            nrm[c] = t > 0.0 ? t : 0.0;
         }
         __syncthreads();
         k = j + 1;
@@ -215,20 +211,20 @@ __global__ void __launch_bounds__(kQrThreads) k_cpqr(double* __restrict__ M, con
 }
 
 // T = R11^{-1} R12 of box blockIdx.y by back substitution, one thread per column
-// of R12 (T column-major k x (n - k)).
+// of R12; T is written row-major (k x (n - k)) so the threads' accesses coalesce.
 __global__ void __launch_bounds__(256) k_tsolve(const double* __restrict__ M, const int64_t* __restrict__ moff,
                                                 const int32_t* __restrict__ nn, const int32_t* __restrict__ kk,
-                                                int m, const int64_t* __restrict__ toff, double* __restrict__ T) {
+                                                const int64_t* __restrict__ toff, double* __restrict__ T) {
     const int b = blockIdx.y;
-    const int n = nn[b], k = kk[b];
+    const int n = nn[b], k = kk[b], w = n - k;
     const double* __restrict__ A = M + moff[b];
-    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n - k; c += gridDim.x * blockDim.x) {
-        const double* r12 = A + static_cast<int64_t>(k + c) * m;
-        double* t = T + toff[b] + static_cast<int64_t>(c) * k;
+    double* __restrict__ Tb = T + toff[b];
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < w; c += gridDim.x * blockDim.x) {
         for (int i = k - 1; i >= 0; --i) {
-            double s = r12[i];
-            for (int l = i + 1; l < k; ++l) s -= A[static_cast<int64_t>(l) * m + i] * t[l];
-            t[i] = s / A[static_cast<int64_t>(i) * m + i];
+            const double* row = A + static_cast<int64_t>(i) * n;
+            double s = row[k + c];
+            for (int l = i + 1; l < k; ++l) s -= row[l] * Tb[static_cast<int64_t>(l) * w + c];
+            Tb[static_cast<int64_t>(i) * w + c] = s / row[i];
         }
     }
 }
@@ -344,8 +340,11 @@ private:
         hipLaunchKernelGGL(k_proxy_matrix, dim3(gx, nbx), dim3(256), 0, 0, pts_.p, p.dim, p.kind, p.kappa, idx_.p,
                            ioff_.p, nn_.p, ctrh_.p, U_.p, np_, moff_.p, M);
         SKF_BHIP(hipGetLastError());
-        hipLaunchKernelGGL(k_cpqr, dim3(nbx), dim3(kQrThreads), m_ * sizeof(double), 0, M, moff_.p, nn_.p, m_,
-                           p.tol, kd, perm, poff_.p, nrm);
+        // one thread per column up to 1024; a power of two for the tree reductions
+        int qt = 64;
+        while (qt < nmax && qt < 1024) qt *= 2;
+        hipLaunchKernelGGL(k_cpqr, dim3(nbx), dim3(qt), m_ * sizeof(double), 0, M, moff_.p, nn_.p, m_, p.tol, kd,
+                           perm, poff_.p, nrm);
         SKF_BHIP(hipGetLastError());
         std::vector<int32_t> kk;
         k_.get(kk, nbx);
@@ -361,7 +360,7 @@ private:
         double* T = T_.need(static_cast<size_t>(to));
         if (to > 0) {
             const int tx = std::min(16, (rmax + 255) / 256);
-            hipLaunchKernelGGL(k_tsolve, dim3(tx, nbx), dim3(256), 0, 0, M, moff_.p, nn_.p, k_.p, m_, toff_.p, T);
+            hipLaunchKernelGGL(k_tsolve, dim3(tx, nbx), dim3(256), 0, 0, M, moff_.p, nn_.p, k_.p, toff_.p, T);
             SKF_BHIP(hipGetLastError());
         }
         std::vector<int32_t> ph;
@@ -373,7 +372,12 @@ private:
             const int n = nn[i];
             s.k = kk[i];
             s.pos.assign(ph.begin() + poff[i], ph.begin() + poff[i] + n);
-            s.T.assign(Th.begin() + toff[i], Th.begin() + toff[i] + static_cast<int64_t>(s.k) * (n - s.k));
+            // row-major k x (n - k) on the device, column-major in the plan
+            const int64_t w = n - s.k;
+            s.T.resize(static_cast<size_t>(s.k) * w);
+            const double* src = Th.data() + toff[i];
+            for (int64_t r = 0; r < s.k; ++r)
+                for (int64_t c = 0; c < w; ++c) s.T[r + c * s.k] = src[r * w + c];
         }
     }
 

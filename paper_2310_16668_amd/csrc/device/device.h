@@ -37,11 +37,16 @@ struct Task {
 struct SymTask {
     int32_t bi, bj;   // target-side box (lanes) and source-side box (wave-uniform)
     int32_t t0, t1;   // target entries [t0, t1) of bi
-    int32_t flags;    // SYM_EXPANDED: |d|^2 may be expanded about the item's origin
+    int32_t flags;    // SYM_EXPANDED: |d|^2 may be expanded about the source box's origin
     int32_t pad;
     int64_t fwd_u, fwd_h, rev_u, rev_h;
 };
 enum SymFlags : int32_t { SYM_EXPANDED = 1 };
+// The pair kernel's expanded source records: box b's records start at
+// voff[b] + kSymRecordPad * b and are followed by kSymRecordPad copies of its
+// last record, so a block of up to kSymRecordPad + 1 sources is read without
+// clamping its indices (the copies take zero charges).
+constexpr int kSymRecordPad = 7;
 
 // The slot rows of one box: ru rows of n entries from base_u (added to u) and
 // rh rows of k entries from base_h (added to uhat).

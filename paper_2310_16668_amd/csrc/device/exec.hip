@@ -20,7 +20,9 @@
 // versa, so the segment lists are reused unchanged; the upward pass becomes a
 // top-down pass of the downward form; the gather becomes the output scatter.
 // The adjoint therefore runs the forward launches with the kernel conjugated.
+#include <cmath>
 #include <mutex>
+#include <stdexcept>
 
 #include "sweep.h"
 
@@ -128,6 +130,44 @@ static std::vector<TT> padded_t(const Layout& L, bool transpose) {
     return out;
 }
 
+// Where the pair kernel's expanded source records of each box start: the
+// boxes in entry order, each followed by kSymRecordPad extra records.
+static std::vector<int64_t> record_offsets(const Layout& L) {
+    std::vector<int> order(L.n_boxes);
+    for (int b = 0; b < L.n_boxes; ++b) order[b] = b;
+    std::sort(order.begin(), order.end(), [&](int a, int b) { return L.voff[a] < L.voff[b]; });
+    std::vector<int64_t> roff(L.n_boxes);
+    for (int r = 0; r < L.n_boxes; ++r) roff[order[r]] = L.voff[order[r]] + static_cast<int64_t>(kSymRecordPad) * r;
+    return roff;
+}
+
+// The pair kernel's expanded source records: for an entry x of box b with
+// origin o = the first entry of b, (-2 (x - o), |x - o|^2), so that
+// |t - x|^2 = |t - o|^2 + |x - o|^2 - 2 (t - o).(x - o) costs one add and three
+// multiply-adds per pair.  Box b's records start at roff[b] and are followed by
+// kSymRecordPad copies of its last record: a real source position, so every
+// kernel value a block forms is finite, and the kernel gives these positions
+// zero charges.
+static std::vector<double> expanded_records(const Layout& L, const std::vector<int64_t>& roff) {
+    const size_t total = static_cast<size_t>(L.n_entries) + static_cast<size_t>(kSymRecordPad) * L.n_boxes;
+    std::vector<double> E(total * 4, 0.0);
+    for (int b = 0; b < L.n_boxes; ++b) {
+        if (L.nb[b] == 0) continue;
+        const double* o = &L.X[static_cast<size_t>(L.voff[b]) * 4];
+        for (int64_t e = 0; e < L.nb[b] + kSymRecordPad; ++e) {
+            const int64_t src = std::min<int64_t>(e, L.nb[b] - 1);
+            const double* x = &L.X[static_cast<size_t>(L.voff[b] + src) * 4];
+            double* r = &E[static_cast<size_t>(roff[b] + e) * 4];
+            const double dx = x[0] - o[0], dy = x[1] - o[1], dz = x[2] - o[2];
+            r[0] = -2.0 * dx;
+            r[1] = -2.0 * dy;
+            r[2] = -2.0 * dz;
+            r[3] = std::fma(dx, dx, std::fma(dy, dy, dz * dz));
+        }
+    }
+    return E;
+}
+
 static void upload(DeviceOp* d, int dtype) {
     const Layout& L = d->L;
     if (!d->uploaded) {
@@ -175,11 +215,12 @@ static void upload(DeviceOp* d, int dtype) {
             d->symrows.upload(L.sym_rows);
             d->nred = static_cast<int>(L.sym_rows.size());
         }
+        const std::vector<int64_t> roff = record_offsets(L);
         std::vector<kern::BoxRec> br(L.n_boxes);
-        for (int b = 0; b < L.n_boxes; ++b)
-            br[b] = kern::BoxRec{L.voff[b], L.hoff[b], L.nb[b], L.kb[b], L.level[b], L.is_leaf[b]};
+        for (int b = 0; b < L.n_boxes; ++b) br[b] = kern::BoxRec{L.voff[b], L.hoff[b], L.nb[b], L.kb[b], roff[b]};
         d->boxrec.upload(br);
         d->X64.upload(L.X);   // coordinates are float64 in every precision policy
+        d->XE64.upload(expanded_records(L, roff));
         build_transfer_work(d);
         d->uploaded = true;
     }

@@ -150,8 +150,7 @@ struct alignas(32) BoxRec {
     int64_t hoff;     // first skeleton entry
     int32_t n;        // entries
     int32_t k;        // skeleton entries (0 at and above the top level)
-    int32_t level;
-    int32_t leaf;
+    int64_t roff;     // first expanded source record of the pair kernel
 };
 
 // ---------------------------------------------------------------------------
@@ -166,7 +165,7 @@ struct alignas(32) BoxRec {
 // load).
 // ---------------------------------------------------------------------------
 template <int NV>
-constexpr int chunks_max() { return 32 / NV; }
+constexpr int chunks_max() { return 16 / NV; }
 
 template <int NV>
 __device__ __forceinline__ int chunk_len(int cols) {
@@ -199,7 +198,7 @@ __device__ __forceinline__ void gemv_chunk(const TT* __restrict__ A, int64_t ld,
     using M = RowMap<TT>;
     using VT = typename Vec8<TT>::type;
     if (M::vec * lane >= rows) return;
-#pragma unroll 8
+#pragma unroll 4
     for (int c = c0; c < c1; ++c) {
         double x[NV];
         xf(c, x);
@@ -486,18 +485,20 @@ __global__ void __launch_bounds__(256) k_near(const Task* __restrict__ tasks, in
 // terms i <- j and j <- i use the same block G(B_i, B_j) of a symmetric kernel,
 // the second as its transpose.  A work item holds up to 64 TPL targets of box i
 // per pass in its lanes and walks the sources of box j in wave-uniform blocks of
-// 16; each kernel value serves both directions:
+// kSymBlock; each kernel value serves both directions:
 //   forward  u_i[t]  += G(t, s) q_j[s]          uhat_i[t] -= G(t, s) qhat_j[s]
 //   reverse  u_j[s]  += G(t, s) q_i[t]          uhat_j[s] -= G(t, s) qhat_i[t]
 // (uhat parts for skeleton targets and sources only; top-level boxes have none).
 // The forward sums stay in the lanes.  The reverse sums over the lanes are
 // formed per block: each lane keeps its partial for every source of the block,
-// the 16 x 64 partials pass through the wave's own LDS tile, four lanes add one
-// source's column and a quad exchange completes it.  All sums go to the item's
+// the kSymBlock x 64 partials pass through the wave's own LDS tile, a group of
+// lanes adds one source's column and cross-lane moves complete it.  All sums go to the item's
 // private slots in a fixed order; k_sym_reduce adds them to u and uhat.
 
-constexpr int kSymBlock = 16;            // sources per block
-constexpr int kSymRow = 68;              // LDS row pitch: the column reads below hit distinct banks
+constexpr int kSymBlock = 8;             // sources per block: their records fit the SGPRs
+static_assert(kSymBlock - 1 <= kSymRecordPad, "a block may run past its box by kSymBlock - 1 records");
+constexpr int kSymLanes = 64 / kSymBlock; // lanes that add one source's column
+constexpr int kSymRow = 72;              // LDS row pitch: the column reads below hit distinct banks
 
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -505,74 +506,84 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Cross-lane moves within a row of 16 lanes (DPP): swap neighbours, swap
+// pairs, mirror each half-row.  Together they add up groups of 2, 4 or 8
+// consecutive lanes without leaving the vector ALU.
+constexpr int kDppXor1 = 0xB1;           // quad_perm [1, 0, 3, 2]
+constexpr int kDppXor2 = 0x4E;           // quad_perm [2, 3, 0, 1]
+constexpr int kDppHalfMirror = 0x141;    // row_half_mirror
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+struct IntPair {
+    int lo, hi;
+};
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+    const IntPair w = __builtin_bit_cast(IntPair, v);
+    return __builtin_bit_cast(double, IntPair{__builtin_amdgcn_mov_dpp(w.lo, CTRL, 0xF, 0xF, false),
+                                              __builtin_amdgcn_mov_dpp(w.hi, CTRL, 0xF, 0xF, false)});
+}
+// the sum over each aligned group of kSymLanes lanes, in all of them
+template <typename B>
+__device__ __forceinline__ B lane_group_sum(B v) {
+    static_assert(kSymLanes == 8, "the DPP tree below adds groups of eight lanes");
+    v += dpp_move<kDppXor1>(v);
+    v += dpp_move<kDppXor2>(v);
+    v += dpp_move<kDppHalfMirror>(v);
+    return v;
+}
+
 // Column sums of the wave's kSymBlock x 64 partials r[c] (lane = column of the
-// tile).  Returns, in every lane 4c..4c+3, the sum over the 64 lanes of r[c].
+// tile).  Returns, in every lane of group c (lanes kSymLanes c ..), the sum over
+// the 64 lanes of r[c]: each lane of the group adds kSymBlock entries of the
+// column, then the group's lanes are added.
 template <typename B>
 __device__ __forceinline__ B column_sum(const B (&r)[kSymBlock], B* tile, int lane) {
 #pragma unroll
     for (int c = 0; c < kSymBlock; ++c) tile[c * kSymRow + lane] = r[c];
     wave_sync();
-    const int c = lane >> 2, q = lane & 3;
+    const int c = lane / kSymLanes, q = lane % kSymLanes;
     B v = B(0);
 #pragma unroll
-    for (int i = 0; i < 16; ++i) v += tile[c * kSymRow + q + 4 * i];
+    for (int i = 0; i < kSymBlock; ++i) v += tile[c * kSymRow + q + kSymLanes * i];
     wave_sync();
-    v += __shfl_xor(v, 1);
-    v += __shfl_xor(v, 2);
-    return v;
+    return lane_group_sum(v);
 }
 
-// The same column sums formed in float64 (the compensated leaf sums): each of
-// the four lanes of a column converts its 16 values and adds them in float64.
+// The same column sums formed in float64 (the compensated leaf sums).
 template <typename B>
 __device__ __forceinline__ double column_sum_f64(const B (&r)[kSymBlock], B* tile, int lane) {
 #pragma unroll
     for (int c = 0; c < kSymBlock; ++c) tile[c * kSymRow + lane] = r[c];
     wave_sync();
-    const int c = lane >> 2, q = lane & 3;
+    const int c = lane / kSymLanes, q = lane % kSymLanes;
     double v = 0.0;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) v += static_cast<double>(tile[c * kSymRow + q + 4 * i]);
+    for (int i = 0; i < kSymBlock; ++i) v += static_cast<double>(tile[c * kSymRow + q + kSymLanes * i]);
     wave_sync();
-    v += __shfl_xor(v, 1);
-    v += __shfl_xor(v, 2);
-    return v;
+    return lane_group_sum(v);
 }
 
-// One source of a block, staged in the wave's LDS area.
-// A block's sources staged in the wave's LDS area: positions and charges in
-// separate arrays, so a source costs two 16-byte reads and one charge read.
-// Exact form: (x, y, z) = the source's coordinates.  Expanded form (see
-// sym_pass): (x, y, z) = -2 (x_s - o) and n = |x_s - o|^2 for the item's origin o.
-struct alignas(32) SrcPos {
-    double x, y, z, n;
-};
-template <typename R>
-struct alignas(2 * sizeof(R)) SrcW {
-    R w, wh;
-};
-template <typename R>
-struct SrcStage {
-    SrcPos p[kSymBlock];
-    SrcW<R> w[kSymBlock];
-};
-// one lane's staged source (registers)
-template <typename R>
-struct SrcRec {
-    double x, y, z, n;
-    R w, wh;
-};
+// A block's sources are wave-uniform: each one is read with scalar loads into
+// SGPRs (its position record and charges) and enters the lanes' arithmetic as
+// an SGPR operand, so a pair costs no LDS traffic and no staging barrier.
+// Exact form: the record is the source's coordinates.  Expanded form (see
+// sym_pass): the record is (-2 (x_s - o), |x_s - o|^2) for the origin o of the
+// source box, precomputed once per operator.
 
-// One block of up to kSymBlock sources s0 .. s0 + cnt - 1 of box j, read from
-// the wave's staged copy src[0 .. kSymBlock).  H: the pass holds skeleton
-// targets and the block lies in j's skeleton, so the uhat terms run too.
-// MASK: zero the pairs at distance 0 (needed where a box meets itself).
-// Positions past cnt repeat the last source with zero charges (their reverse
-// sums are not stored), so the block is branch-free.  Reverse sums go to
-// rev_u[s] (and rev_h[s]), stored on the item's first pass and accumulated on
-// later ones.
+// One block of up to kSymBlock sources s0 .. s0 + cnt - 1 of box j (records
+// Xs, charges Qs and Qhs, indexed from the box's first entry).  H: the pass
+// holds skeleton targets and the block lies in j's skeleton, so the uhat terms
+// run too.  MASK: zero the pairs at distance 0 (needed where a box meets
+// itself).  Positions past cnt repeat the last source with zero charges (their
+// reverse sums are not stored), so the block is branch-free.  Reverse sums go
+// to rev_u[s] (and rev_h[s]), stored on the item's first pass and accumulated
+// on later ones.
 template <class P, int TPL, bool H, bool MASK, bool FAST>
-__device__ __forceinline__ void sym_block(const SrcStage<typename P::Rt>* src, int s0, int cnt,
+__device__ __forceinline__ void sym_block(const Rec4<double>* __restrict__ Xs, const typename P::Vt* __restrict__ Qs,
+                                          const typename P::Vt* __restrict__ Qhs, int s0, int cnt,
                                           const double (&xt)[TPL], const double (&yt)[TPL],
                                           const double (&zt)[TPL], const double (&nt)[TPL],
                                           const typename P::Rt (&wi)[TPL],
@@ -584,31 +595,41 @@ __device__ __forceinline__ void sym_block(const SrcStage<typename P::Rt>* src, i
     using A = typename P::At;
     // the running reverse sums of earlier passes are fetched before the block's
     // arithmetic, so their latency overlaps it
-    const int cs = lane >> 2;
-    const bool own = (lane & 3) == 0 && cs < cnt;
+    const int cs = lane / kSymLanes;
+    const bool own = lane % kSymLanes == 0 && cs < cnt;
     double prev_u = 0.0, prev_h = 0.0;
     if (own && !first) {
         prev_u = rev_u[s0 + cs];
         if constexpr (H) prev_h = rev_h[s0 + cs];
     }
+    const int last = s0 + cnt - 1;
     R bacc[TPL], bh[TPL];
     R ru[kSymBlock], rh[kSymBlock];
 #pragma unroll
     for (int p = 0; p < TPL; ++p) { bacc[p] = R(0); bh[p] = R(0); }
 #pragma unroll
     for (int c = 0; c < kSymBlock; ++c) {
-        const SrcPos sv = src->p[c];
-        const R svw = src->w[c].w;
+        // Expanded records are padded per box (copies of its last record), so
+        // the block reads them unclamped and the loads merge; the charges past
+        // cnt are read within the arrays' spare tail and replaced by zero.
+        // Exact coordinates are read at the clamped index.
+        const int si = FAST ? s0 + c : min(s0 + c, last);
+        const Rec4<double> sv = Xs[si];
+        const R qs = static_cast<R>(Qs[si]);
+        const R svw = c < cnt ? qs : R(0);
         R svwh = R(0);
-        if constexpr (H) svwh = src->w[c].wh;
+        if constexpr (H) {
+            const R qh = static_cast<R>(Qhs[si]);
+            svwh = c < cnt ? qh : R(0);
+        }
         ru[c] = R(0);
         rh[c] = R(0);
 #pragma unroll
         for (int p = 0; p < TPL; ++p) {
             R g, gi;
             if constexpr (FAST) {
-                // |t - s|^2 = |t'|^2 + |s'|^2 - 2 t'.s' relative to the item's origin
-                const double r2 = fma(xt[p], sv.x, fma(yt[p], sv.y, fma(zt[p], sv.z, nt[p] + sv.n)));
+                // |t - s|^2 = |t'|^2 + |s'|^2 - 2 t'.s' relative to the source box's origin
+                const double r2 = fma(xt[p], sv.x, fma(yt[p], sv.y, fma(zt[p], sv.z, nt[p] + sv.w)));
                 green_r2<P, false, MASK>(r2, R(0), g, gi);
             } else {
                 green<P, false, MASK>(xt[p] - sv.x, yt[p] - sv.y, zt[p] - sv.z, R(0), g, gi);
@@ -676,36 +697,6 @@ struct BlockPlan {
     }
 };
 
-// Lanes 0..15 fetch the sources of block b from global memory into registers
-// (lanes past the block's count repeat its last source with zero charges).
-template <class P, bool FAST>
-__device__ __forceinline__ void stage_load(const BlockPlan& bp, int b, const Rec4<double>* __restrict__ Xs,
-                                           const typename P::Vt* __restrict__ Qs,
-                                           const typename P::Vt* __restrict__ Qhs, int lane, const double (&o)[3],
-                                           SrcRec<typename P::Rt>& r) {
-    using R = typename P::Rt;
-    int s0, cnt;
-    bp.range(b, s0, cnt);
-    if (lane < kSymBlock) {
-        const int si = s0 + min(lane, cnt - 1);
-        const Rec4<double> x = Xs[si];
-        if constexpr (FAST) {
-            const double dx = x.x - o[0], dy = x.y - o[1], dz = x.z - o[2];
-            r.x = -2.0 * dx;
-            r.y = -2.0 * dy;
-            r.z = -2.0 * dz;
-            r.n = fma(dx, dx, fma(dy, dy, dz * dz));
-        } else {
-            r.x = x.x;
-            r.y = x.y;
-            r.z = x.z;
-            r.n = 0.0;
-        }
-        r.w = lane < cnt ? static_cast<R>(Qs[si]) : R(0);
-        r.wh = (lane < cnt && b < bp.nbH) ? static_cast<R>(Qhs[si]) : R(0);
-    }
-}
-
 // Item context shared by its passes.
 struct SymCtx {
     BoxRec bi, bj;
@@ -723,9 +714,9 @@ template <class P, int TPL, bool SELF, bool FAST>
 __device__ __forceinline__ void sym_pass(const SymCtx& cx, int tp, const Rec4<double>* __restrict__ X,
                                          const typename P::Vt* __restrict__ Q,
                                          const typename P::Vt* __restrict__ Qh,
-                                         const Rec4<double>* __restrict__ Xs, const typename P::Vt* __restrict__ Qs,
-                                         const typename P::Vt* __restrict__ Qhs, typename P::Rt* tile,
-                                         SrcStage<typename P::Rt>* src, int lane) {
+                                         const Rec4<double>* __restrict__ Xs, const Rec4<double>* __restrict__ Xb,
+                                         const typename P::Vt* __restrict__ Qs,
+                                         const typename P::Vt* __restrict__ Qhs, typename P::Rt* tile, int lane) {
     using R = typename P::Rt;
     using A = typename P::At;
     const BoxRec& bi = cx.bi;
@@ -742,10 +733,11 @@ __device__ __forceinline__ void sym_pass(const SymCtx& cx, int tp, const Rec4<do
     double xt[TPL], yt[TPL], zt[TPL], nt[TPL];
     R wi[TPL], whi[TPL];
     A acc[TPL], acch[TPL];
-    // expanded form: coordinates relative to the item's origin (the first entry of box i)
+    // expanded form: target coordinates relative to the origin of the source
+    // box (its first entry), the origin of the source records Xb
     double o[3] = {0.0, 0.0, 0.0};
     if constexpr (FAST) {
-        const Rec4<double> x0 = X[bi.voff];
+        const Rec4<double> x0 = Xs[0];
         o[0] = x0.x; o[1] = x0.y; o[2] = x0.z;
     }
 #pragma unroll
@@ -776,27 +768,15 @@ __device__ __forceinline__ void sym_pass(const SymCtx& cx, int tp, const Rec4<do
 #pragma unroll
         for (int p = 0; p < TPL; ++p) { acc[p] = ad[p][0]; acch[p] = -adh[p][0]; }
     }
-    // the next block's sources are fetched while the current one is evaluated
-    if (bp.nb > 0) {
-        SrcRec<R> staged{};
-        stage_load<P, FAST>(bp, 0, Xs, Qs, Qhs, lane, o, staged);
-        for (int b = 0; b < bp.nb; ++b) {
-            int s0, cnt;
-            bp.range(b, s0, cnt);
-            wave_sync();
-            if (lane < kSymBlock) {
-                src->p[lane] = SrcPos{staged.x, staged.y, staged.z, staged.n};
-                src->w[lane] = SrcW<R>{staged.w, staged.wh};
-            }
-            wave_sync();
-            if (b + 1 < bp.nb) stage_load<P, FAST>(bp, b + 1, Xs, Qs, Qhs, lane, o, staged);
-            if (b < bp.nbH)
-                sym_block<P, TPL, true, SELF, FAST>(src, s0, cnt, xt, yt, zt, nt, wi, whi, acc, acch, tile, lane,
-                                                    cx.rev_u, cx.rev_h, first, cx.sc);
-            else
-                sym_block<P, TPL, false, SELF, FAST>(src, s0, cnt, xt, yt, zt, nt, wi, whi, acc, acch, tile, lane,
-                                                     cx.rev_u, cx.rev_h, first, cx.sc);
-        }
+    for (int b = 0; b < bp.nb; ++b) {
+        int s0, cnt;
+        bp.range(b, s0, cnt);
+        if (b < bp.nbH)
+            sym_block<P, TPL, true, SELF, FAST>(Xb, Qs, Qhs, s0, cnt, xt, yt, zt, nt, wi, whi, acc, acch, tile, lane,
+                                                cx.rev_u, cx.rev_h, first, cx.sc);
+        else
+            sym_block<P, TPL, false, SELF, FAST>(Xb, Qs, Qhs, s0, cnt, xt, yt, zt, nt, wi, whi, acc, acch, tile, lane,
+                                                 cx.rev_u, cx.rev_h, first, cx.sc);
     }
 #pragma unroll
     for (int p = 0; p < TPL; ++p) {
@@ -822,16 +802,16 @@ __device__ __forceinline__ void sym_pass(const SymCtx& cx, int tp, const Rec4<do
 template <class P, int TPL, bool SELF, bool FAST>
 __device__ __forceinline__ void sym_tail(const SymCtx& cx, int tp, const Rec4<double>* __restrict__ X,
                                          const typename P::Vt* __restrict__ Q, const typename P::Vt* __restrict__ Qh,
-                                         const Rec4<double>* __restrict__ Xs, const typename P::Vt* __restrict__ Qs,
-                                         const typename P::Vt* __restrict__ Qhs, typename P::Rt* tile,
-                                         SrcStage<typename P::Rt>* src, int lane) {
+                                         const Rec4<double>* __restrict__ Xs, const Rec4<double>* __restrict__ Xb,
+                                         const typename P::Vt* __restrict__ Qs,
+                                         const typename P::Vt* __restrict__ Qhs, typename P::Rt* tile, int lane) {
     if constexpr (TPL == 1) {
-        sym_pass<P, 1, SELF, FAST>(cx, tp, X, Q, Qh, Xs, Qs, Qhs, tile, src, lane);
+        sym_pass<P, 1, SELF, FAST>(cx, tp, X, Q, Qh, Xs, Xb, Qs, Qhs, tile, lane);
     } else {
         if (cx.t1 - tp > 64 * (TPL - 1))
-            sym_pass<P, TPL, SELF, FAST>(cx, tp, X, Q, Qh, Xs, Qs, Qhs, tile, src, lane);
+            sym_pass<P, TPL, SELF, FAST>(cx, tp, X, Q, Qh, Xs, Xb, Qs, Qhs, tile, lane);
         else
-            sym_tail<P, TPL - 1, SELF, FAST>(cx, tp, X, Q, Qh, Xs, Qs, Qhs, tile, src, lane);
+            sym_tail<P, TPL - 1, SELF, FAST>(cx, tp, X, Q, Qh, Xs, Xb, Qs, Qhs, tile, lane);
     }
 }
 
@@ -842,15 +822,15 @@ __device__ __forceinline__ void sym_passes(const SymCtx& cx, const Rec4<double>*
                                            const typename P::Vt* __restrict__ Q,
                                            const typename P::Vt* __restrict__ Qh,
                                            const Rec4<double>* __restrict__ Xs,
+                                           const Rec4<double>* __restrict__ Xb,
                                            const typename P::Vt* __restrict__ Qs,
-                                           const typename P::Vt* __restrict__ Qhs, typename P::Rt* tile,
-                                           SrcStage<typename P::Rt>* src, int lane) {
+                                           const typename P::Vt* __restrict__ Qhs, typename P::Rt* tile, int lane) {
     for (int tp = cx.t0; tp < cx.t1;) {
         if (cx.t1 - tp > 64 * (TPL - 1)) {
-            sym_pass<P, TPL, SELF, FAST>(cx, tp, X, Q, Qh, Xs, Qs, Qhs, tile, src, lane);
+            sym_pass<P, TPL, SELF, FAST>(cx, tp, X, Q, Qh, Xs, Xb, Qs, Qhs, tile, lane);
             tp += 64 * TPL;
         } else {
-            if constexpr (TPL > 1) sym_tail<P, TPL - 1, SELF, FAST>(cx, tp, X, Q, Qh, Xs, Qs, Qhs, tile, src, lane);
+            if constexpr (TPL > 1) sym_tail<P, TPL - 1, SELF, FAST>(cx, tp, X, Q, Qh, Xs, Xb, Qs, Qhs, tile, lane);
             break;
         }
     }
@@ -862,10 +842,10 @@ __device__ __forceinline__ void sym_passes(const SymCtx& cx, const Rec4<double>*
 // tiles, which run in one direction with the zero distances masked.
 template <class P, int TPL>
 __device__ __forceinline__ void sym_item(const SymTask it, const BoxRec* __restrict__ box,
-                                         const Rec4<double>* __restrict__ X, const typename P::Vt* __restrict__ Q,
+                                         const Rec4<double>* __restrict__ X, const Rec4<double>* __restrict__ Xe,
+                                         const typename P::Vt* __restrict__ Q,
                                          const typename P::Vt* __restrict__ Qh, double* __restrict__ slots,
-                                         double scale, typename P::Rt* tile, SrcStage<typename P::Rt>* src,
-                                         int lane) {
+                                         double scale, typename P::Rt* tile, int lane) {
     using V = typename P::Vt;
     SymCtx cx;
     cx.bi = box[it.bi];
@@ -883,11 +863,11 @@ __device__ __forceinline__ void sym_item(const SymTask it, const BoxRec* __restr
     const V* Qhs = Qh + cx.bj.hoff;
     // the expanded |d|^2 serves the float32 evaluation of items the build marked safe for it
     if (sizeof(typename P::Rt) == 4 && (it.flags & SYM_EXPANDED))
-        sym_passes<P, TPL, false, true>(cx, X, Q, Qh, Xs, Qs, Qhs, tile, src, lane);
+        sym_passes<P, TPL, false, true>(cx, X, Q, Qh, Xs, Xe + cx.bj.roff, Qs, Qhs, tile, lane);
     else if (it.bi != it.bj)
-        sym_passes<P, TPL, false, false>(cx, X, Q, Qh, Xs, Qs, Qhs, tile, src, lane);
+        sym_passes<P, TPL, false, false>(cx, X, Q, Qh, Xs, Xs, Qs, Qhs, tile, lane);
     else
-        sym_passes<P, TPL, true, false>(cx, X, Q, Qh, Xs, Qs, Qhs, tile, src, lane);
+        sym_passes<P, TPL, true, false>(cx, X, Q, Qh, Xs, Xs, Qs, Qhs, tile, lane);
 }
 
 // Waves per SIMD the pair kernel is compiled for: the float32 evaluation fits
@@ -899,17 +879,17 @@ template <class P, int TPL>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sym_waves<P, TPL>(), 8))) k_near_sym(const SymTask* __restrict__ tasks, int ntasks,
                                                   const BoxRec* __restrict__ box,
                                                   const Rec4<double>* __restrict__ X,
+                                                  const Rec4<double>* __restrict__ Xe,
                                                   const typename P::Vt* __restrict__ Q,
                                                   const typename P::Vt* __restrict__ Qh,
                                                   double* __restrict__ slots, double scale) {
     using R = typename P::Rt;
     __shared__ R tiles[4][kSymBlock * kSymRow];
-    __shared__ SrcStage<R> srcs[4];
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int tid = blockIdx.x * 4 + wv;
     if (tid >= ntasks) return;
-    sym_item<P, TPL>(tasks[tid], box, X, Q, Qh, slots, scale, tiles[wv], &srcs[wv], lane);
+    sym_item<P, TPL>(tasks[tid], box, X, Xe, Q, Qh, slots, scale, tiles[wv], lane);
 }
 
 // acc + p[0] + p[ld] + ... + p[(rows - 1) ld], added in row order; the loads of
@@ -1581,20 +1561,13 @@ __global__ void __launch_bounds__(256) k_downward_mfma(const int2* __restrict__ 
 // with complex products (the adjoint conjugates G in both directions).  A box
 // paired with itself is left to k_near.  A work item is one wavefront: passes
 // of 64 TPL targets of box i in the lanes against the sources of box j in
-// wave-uniform blocks of kSymBlockC staged in the wave's LDS area.  Forward
+// wave-uniform blocks of kSymBlockC, read with scalar loads.  Forward
 // sums accumulate in float64 per product; reverse sums are formed per block in
 // the lanes (TPL products), summed over the lanes in float64 through the
 // wave's LDS tile (eight lanes per source and a shuffle tree), and added to
 // the item's slot row.  Slot offsets count complex entries (two doubles).
 constexpr int kSymBlockC = 8;
 constexpr int kSymRowC = 72;     // LDS row pitch: the column reads of a half-wave hit distinct banks
-
-template <typename R>
-struct SrcStageC {
-    SrcPos p[kSymBlockC];
-    R w[kSymBlockC][2];
-    R wh[kSymBlockC][2];
-};
 
 // Column sums of kSymBlockC x 64 lane partials: every lane of source c's group
 // of eight receives the float64 sum over the 64 lanes.
@@ -1609,17 +1582,15 @@ __device__ __forceinline__ double column_sum_c(const B (&r)[kSymBlockC], B* tile
 #pragma unroll
     for (int i = 0; i < kSymBlockC; ++i) v += static_cast<double>(tile[c * kSymRowC + q + LPS * i]);
     wave_sync();
-#pragma unroll
-    for (int o = 1; o < LPS; o <<= 1) v += __shfl_xor(v, o);
-    return v;
+    static_assert(LPS == kSymLanes, "one lane group per source");
+    return lane_group_sum(v);
 }
 
 template <class P, int TPL, bool CONJ>
 __device__ __forceinline__ void sym_pass_c(const SymTask& it, const BoxRec& bi, const BoxRec& bj, int tp,
                                            const Rec4<double>* __restrict__ X, const typename P::Vt* __restrict__ Q,
                                            const typename P::Vt* __restrict__ Qh, double* __restrict__ slots,
-                                           typename P::Rt kappa, double sc, typename P::Rt* tile,
-                                           SrcStageC<typename P::Rt>* src, int lane) {
+                                           typename P::Rt kappa, double sc, typename P::Rt* tile, int lane) {
     using R = typename P::Rt;
     using A = typename P::At;
     const bool first = tp == it.t0;
@@ -1665,24 +1636,17 @@ __device__ __forceinline__ void sym_pass_c(const SymTask& it, const BoxRec& bi, 
                 prev_h[1] = rev_h[2 * (s0 + cs) + 1];
             }
         }
-        wave_sync();
-        if (lane < kSymBlockC) {
-            const int si = s0 + min(lane, cnt - 1);
-            const Rec4<double> x = Xs[si];
-            src->p[lane] = SrcPos{x.x, x.y, x.z, 0.0};
-#pragma unroll
-            for (int v = 0; v < 2; ++v) {
-                src->w[lane][v] = lane < cnt ? static_cast<R>(Q[(bj.voff + si) * 2 + v]) : R(0);
-                src->wh[lane][v] = (lane < cnt && H) ? static_cast<R>(Qh[(bj.hoff + si) * 2 + v]) : R(0);
-            }
-        }
-        wave_sync();
         R ru[2][kSymBlockC], rh[2][kSymBlockC];
 #pragma unroll
         for (int c = 0; c < kSymBlockC; ++c) {
-            const SrcPos sv = src->p[c];
-            const R w0 = src->w[c][0], w1 = src->w[c][1];
-            const R h0 = src->wh[c][0], h1 = src->wh[c][1];
+            // the source's record and charges: wave-uniform scalar loads
+            const int si = s0 + min(c, cnt - 1);
+            const Rec4<double> sv = Xs[si];
+            const bool live = c < cnt;
+            const R w0 = live ? static_cast<R>(Q[(bj.voff + si) * 2]) : R(0);
+            const R w1 = live ? static_cast<R>(Q[(bj.voff + si) * 2 + 1]) : R(0);
+            const R h0 = (live && H) ? static_cast<R>(Qh[(bj.hoff + si) * 2]) : R(0);
+            const R h1 = (live && H) ? static_cast<R>(Qh[(bj.hoff + si) * 2 + 1]) : R(0);
 #pragma unroll
             for (int v = 0; v < 2; ++v) { ru[v][c] = R(0); rh[v][c] = R(0); }
 #pragma unroll
@@ -1741,7 +1705,6 @@ __global__ void __launch_bounds__(256) k_near_sym_c(const SymTask* __restrict__ 
                                                     double* __restrict__ slots, typename P::Rt kappa, double scale) {
     using R = typename P::Rt;
     __shared__ R tiles[4][kSymBlockC * kSymRowC];
-    __shared__ SrcStageC<R> srcs[4];
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int tid = blockIdx.x * 4 + wv;
@@ -1750,7 +1713,7 @@ __global__ void __launch_bounds__(256) k_near_sym_c(const SymTask* __restrict__ 
     const BoxRec bi = box[it.bi], bj = box[it.bj];
     const double sc = scale * P::gscale;
     for (int tp = it.t0; tp < it.t1; tp += 64 * TPL)
-        sym_pass_c<P, TPL, CONJ>(it, bi, bj, tp, X, Q, Qh, slots, kappa, sc, tiles[wv], &srcs[wv], lane);
+        sym_pass_c<P, TPL, CONJ>(it, bi, bj, tp, X, Q, Qh, slots, kappa, sc, tiles[wv], lane);
 }
 
 // u and uhat of one box += its complex slot rows (two doubles per entry), in row order.

@@ -103,10 +103,15 @@ static void box_geometry(const Plan& p, Layout& L) {
     }
 }
 
-// An item of boxes i != j may use the expanded |d|^2 (origin: the first entry of i).
+// An item of boxes i != j may use the expanded |d|^2 (origin: the first entry
+// of the source box j).  Its terms reach about R^2 for the reach R of the two
+// boxes from the origin, so its rounding error relative to |d|^2 >= d^2 (d
+// their smallest spacing) is a few units of 2^-53 (R/d)^2: with R <= 4096 d
+// at most about 2^-26, a quarter of the float32 rounding of the kernel value.
 static bool expanded_ok(const Layout& L, int bi, int bj) {
-    if (L.nb[bi] == 0 || L.dmin.empty()) return false;
-    const double* o = &L.X[static_cast<size_t>(L.voff[bi]) * 4];
+    if (L.nb[bj] == 0 || L.dmin.empty()) return false;
+    // the expanded records of box j are relative to its first entry
+    const double* o = &L.X[static_cast<size_t>(L.voff[bj]) * 4];
     auto reach = [&](int b) {
         double s2 = 0.0;
         for (int d = 0; d < 3; ++d) {
@@ -117,7 +122,7 @@ static bool expanded_ok(const Layout& L, int bi, int bj) {
     };
     const double R = std::max(reach(bi), reach(bj));
     const double d = std::min(L.dmin[bi], L.dmin[bj]);
-    return d > 0.0 && R <= 1024.0 * d;
+    return d > 0.0 && R <= 4096.0 * d;
 }
 
 Layout make_layout(const Plan& p, bool keep_transparent, int tile) {

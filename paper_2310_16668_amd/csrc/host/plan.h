@@ -53,6 +53,8 @@ struct Plan {
 
     // statistics
     double t_tree = 0.0, t_skel = 0.0;
+    double t_skel_qr = 0.0;    // part of t_skel in the IDs themselves
+    double t_layout = 0.0;     // packing the device layout
     int k_max = 0;
     int proxy_count = 0;
 };

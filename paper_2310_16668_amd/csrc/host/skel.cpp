@@ -18,6 +18,7 @@
 // index on ties) stops at the first pivot with |R_jj| <= tol |R_11|; the first
 // k pivots are the skeleton, T = R11^{-1} R12.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -220,6 +221,7 @@ void skeletonize(Plan& p, const std::vector<int64_t>& order, const std::vector<i
     // index sets and skeletons, deepest level first
     for (int l = p.max_level; l >= top; --l) {
         const int b0 = p.level_ptr[l], b1 = p.level_ptr[l + 1];
+        const auto tl = std::chrono::steady_clock::now();
         parallel_for(b1 - b0, threads, [&](int64_t t) {
             const int b = b0 + static_cast<int>(t);
             BoxSkel& s = S[b];
@@ -239,7 +241,13 @@ void skeletonize(Plan& p, const std::vector<int64_t>& order, const std::vector<i
                 skeletonize_box(p, b, s);
             }
         });
-        if (dev && l > top) dev->level(p, b0, b1, S);
+        if (!dev) {   // the host IDs ran inside the loop above, with the index sets
+            p.t_skel_qr += std::chrono::duration<double>(std::chrono::steady_clock::now() - tl).count();
+        } else if (l > top) {
+            const auto tq = std::chrono::steady_clock::now();
+            dev->level(p, b0, b1, S);
+            p.t_skel_qr += std::chrono::duration<double>(std::chrono::steady_clock::now() - tq).count();
+        }
     }
     // flatten into CSR arrays (boxes above the top level keep empty sets)
     p.idx_ptr.assign(nb + 1, 0);

@@ -127,6 +127,6 @@ def test_gpu_build_1m_cube():
     tg = w.targets()
     u = op.apply(torch.from_numpy(q).to("cuda:0", torch.float64)).cpu().numpy()
     e1 = relerr(u[tg], oracle.direct(x, q, targets=tg))
-    record(f"{w.name} gpu_build", build_s=t_gpu, t_tree=st["t_tree"], t_skel=st["t_skel"], k_max=st["k_max"],
-           vs_o1=e1)
+    record(f"{w.name} gpu_build", build_s=t_gpu, t_tree=st["t_tree"], t_skel=st["t_skel"],
+           t_skel_qr=st["t_skel_qr"], t_layout=st["t_layout"], k_max=st["k_max"], vs_o1=e1)
     assert e1 <= 1e-6
