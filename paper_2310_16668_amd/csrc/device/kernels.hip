@@ -495,6 +495,9 @@ __global__ void __launch_bounds__(256) k_near(const Task* __restrict__ tasks, in
 // lanes adds one source's column and cross-lane moves complete it.  All sums go to the item's
 // private slots in a fixed order; k_sym_reduce adds them to u and uhat.
 
+// s_waitcnt vmcnt(0) with the other counters left free (gfx9 encoding:
+// vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8)
+constexpr int kWaitVmcnt0 = 0x0F70;
 constexpr int kSymBlock = 8;             // sources per block: their records fit the SGPRs
 static_assert(kSymBlock - 1 <= kSymRecordPad, "a block may run past its box by kSymBlock - 1 records");
 constexpr int kSymLanes = 64 / kSymBlock; // lanes that add one source's column
@@ -593,16 +596,20 @@ __device__ __forceinline__ void sym_block(const Rec4<double>* __restrict__ Xs, c
                                           double sc) {
     using R = typename P::Rt;
     using A = typename P::At;
-    // the running reverse sums of earlier passes are fetched before the block's
-    // arithmetic, so their latency overlaps it
+    // The running reverse sums of earlier passes are fetched before the block's
+    // arithmetic, so their latency overlaps it.  Every lane loads (its column's
+    // slot, clamped into the block) and forms the new sum, and only the store
+    // is masked: a load under a lane mask would leave the wait for it to a join
+    // point, where it would also wait for the store just issued.
+    const int last = s0 + cnt - 1;
     const int cs = lane / kSymLanes;
+    const int cl = min(s0 + cs, last);
     const bool own = lane % kSymLanes == 0 && cs < cnt;
     double prev_u = 0.0, prev_h = 0.0;
-    if (own && !first) {
-        prev_u = rev_u[s0 + cs];
-        if constexpr (H) prev_h = rev_h[s0 + cs];
+    if (!first) {
+        prev_u = rev_u[cl];
+        if constexpr (H) prev_h = rev_h[cl];
     }
-    const int last = s0 + cnt - 1;
     R bacc[TPL], bh[TPL];
     R ru[kSymBlock], rh[kSymBlock];
 #pragma unroll
@@ -661,21 +668,20 @@ __device__ __forceinline__ void sym_block(const Rec4<double>* __restrict__ Xs, c
         acc[p] += static_cast<A>(bacc[p]);
         if constexpr (H) acch[p] += static_cast<A>(bh[p]);
     }
-    if constexpr (P::comp && sizeof(R) == 4) {
-        const double v = column_sum_f64<R>(ru, tile, lane);
-        if (own) rev_u[s0 + cs] = prev_u + sc * v;
-    } else {
-        const R v = column_sum<R>(ru, tile, lane);
-        if (own) rev_u[s0 + cs] = prev_u + sc * static_cast<double>(v);
-    }
+    double nu, nh = 0.0;
+    if constexpr (P::comp && sizeof(R) == 4) nu = prev_u + sc * column_sum_f64<R>(ru, tile, lane);
+    else nu = prev_u + sc * static_cast<double>(column_sum<R>(ru, tile, lane));
     if constexpr (H) {
-        if constexpr (P::comp && sizeof(R) == 4) {
-            const double v = column_sum_f64<R>(rh, tile, lane);
-            if (own) rev_h[s0 + cs] = prev_h - sc * v;
-        } else {
-            const R v = column_sum<R>(rh, tile, lane);
-            if (own) rev_h[s0 + cs] = prev_h - sc * static_cast<double>(v);
-        }
+        if constexpr (P::comp && sizeof(R) == 4) nh = prev_h - sc * column_sum_f64<R>(rh, tile, lane);
+        else nh = prev_h - sc * static_cast<double>(column_sum<R>(rh, tile, lane));
+    }
+    // the reverse-sum loads have returned long ago; waiting for them here, in
+    // every lane, keeps the wait out of the join after the masked store (where
+    // it would also wait for that store)
+    __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+    if (own) {
+        rev_u[cl] = nu;
+        if constexpr (H) rev_h[cl] = nh;
     }
 }
 
