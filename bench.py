@@ -524,7 +524,8 @@ def main():
     if args.only:
         paths = [p for p in paths if p[0] == args.only]
     tuned = {}
-    clk = {"before": clocks()}
+    # rocm-smi is a separate program: not started under a profiler (--profile-only)
+    clk = {"before": clocks()} if not args.profile_only else {}
     for dt_name, tdt in paths:
         op.prepare(1, tdt)
         if not args.no_autotune:
@@ -540,7 +541,8 @@ def main():
 
         # the timed region: K steps and nothing else
         ms_step = timed_steps(step, args.steps, args.warmup)
-        clk["after_" + dt_name] = clocks()
+        if not args.profile_only:
+            clk["after_" + dt_name] = clocks()
         # per-pass durations: a separate run of the same steps with HIP events
         pm = pass_times(op, step, args.steps)
         res = {"ms_per_step": ms_step, "passes_ms_per_sweep": pm}
