@@ -53,7 +53,9 @@ PEAK_MFMA_F32_TFLOPS = 157.3
 # multiply-adds) therefore costs 40 cycles per wave of 64 pairs.
 CLOCK_GHZ = 2.4
 SIMDS = 1024
-MIX_CYCLES_PER_64_SYM_PAIRS = {"f32": 4 * 4 + 4 + 16 + 2 * 2}
+MIX_CYCLES_PER_64_SYM_PAIRS = {"f32": 4 * 4 + 4 + 16 + 2 * 2,
+                               # the fused forward + adjoint sweep: one evaluation, four multiply-adds
+                               "f32_fused": 4 * 4 + 4 + 16 + 4 * 2}
 PEAK_HBM_GBS = 8000.0
 # algorithmic flops of one 3D Laplace pair in k_near: 3 subtractions, |d|^2
 # (3 mul + 2 add), one reciprocal square root, one multiply-add into u; a skeleton
@@ -122,7 +124,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work to sample")
     ap.add_argument("--profile-only", action="store_true", help="skip accuracy checks and baseline")
-    ap.add_argument("--only", choices=["f32", "f64"], default=None, help="time one path only")
+    ap.add_argument("--only", choices=["f32", "f64", "f32_fused"], default=None, help="time one path only")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run one plain device-to-device copy of MIB MiB (counter calibration)")
     ap.add_argument("--no-autotune", action="store_true")
@@ -195,10 +197,19 @@ def pass_times(obj, step, steps: int) -> dict:
     return {k: v / n for k, v in t.items()}
 
 
-def near_kernels(st: dict, pm: dict, helm: bool = False) -> dict:
-    """(ms per launch, algorithmic flops per launch) of the near-field kernels."""
+def near_kernels(st: dict, pm: dict, helm: bool = False, columns: int = 1) -> dict:
+    """(ms per launch, algorithmic flops per launch) of the near-field kernels;
+    columns = 2 for the fused forward + adjoint sweep (each kernel value serves
+    two columns: the evaluation once, the multiply-adds twice)."""
     pairs_ns = st["pairs_near"] - 2 * st["pairs_sym"] - st["pairs_tile"]
     skel_ns = st["pairs_skel"] - 2 * st["pairs_sym_skel"] - st["pairs_tile_skel"]
+    if columns == 2:
+        ev = FLOPS_PER_PAIR - 2   # the evaluation without its multiply-add
+        return {
+            "k_near": (pm["near_field"], (ev + 4) * pairs_ns + 2 * FLOPS_PER_SKEL_PAIR * skel_ns),
+            "k_near_sym": (pm["near_pairs"], (ev + 8) * st["pairs_sym"] + 2 * FLOPS_PER_SYM_SKEL_PAIR * st["pairs_sym_skel"]
+                           + (ev + 4) * st["pairs_tile"] + 2 * FLOPS_PER_SKEL_PAIR * st["pairs_tile_skel"]),
+        }
     if helm:
         return {"k_near": (pm["near_field"], FLOPS_PER_HELM_PAIR * pairs_ns + FLOPS_PER_HELM_SKEL_PAIR * skel_ns),
                 "k_near_sym_c": (pm["near_pairs"], FLOPS_PER_HELM_SYM_PAIR * st["pairs_sym"]
@@ -520,24 +531,30 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] calibration copy of {args.calibrate_copy} MiB done")
         del a, b
-    paths = [("f64", torch.float64), ("f32", torch.float32)]
+    # f64 / f32: skelfmm_apply then skelfmm_apply_adjoint, two sweeps per step;
+    # f32_fused: skelfmm_apply_fwd_adj, both in one sweep of two columns
+    paths = [("f64", torch.float64), ("f32", torch.float32), ("f32_fused", torch.float32)]
     if args.only:
         paths = [p for p in paths if p[0] == args.only]
     tuned = {}
     # rocm-smi is a separate program: not started under a profiler (--profile-only)
     clk = {"before": clocks()} if not args.profile_only else {}
     for dt_name, tdt in paths:
+        fused = dt_name == "f32_fused"
         op.prepare(1, tdt)
         if not args.no_autotune:
-            tuned[dt_name] = op.autotune(tdt)
+            tuned[dt_name] = op.autotune_fwd_adj() if fused else op.autotune(tdt)
             log(f"[bench] {dt_name} autotune {tuned[dt_name]}")
         q = torch.from_numpy(q_h).to(dev, tdt)
         v = torch.from_numpy(v_h).to(dev, tdt)
         holder = {}
 
         def step():
-            holder["u"] = op.apply(q)
-            holder["w"] = op.apply_adjoint(v)
+            if fused:
+                holder["u"], holder["w"] = op.apply_fwd_adj(q, v)
+            else:
+                holder["u"] = op.apply(q)
+                holder["w"] = op.apply_adjoint(v)
 
         # the timed region: K steps and nothing else
         ms_step = timed_steps(step, args.steps, args.warmup)
@@ -568,11 +585,13 @@ def main():
         chosen = min(ok or list(results), key=lambda k: results[k]["ms_per_step"])
     r = results[chosen]
     pm = r["passes_ms_per_sweep"]
+    fused = chosen == "f32_fused"
+    base = chosen.split("_")[0]   # the arithmetic type
     # pair counts at the headline path's targets per lane (the diagonal tiles depend on it)
     if chosen in tuned:
         op.set_targets_per_lane(tuned[chosen]["targets_per_lane"])
     st = op.stats()
-    kernels = near_kernels(st, pm)
+    kernels = near_kernels(st, pm, columns=2 if fused else 1)
     dom = max(kernels, key=lambda k: kernels[k][0])
     near_ms, flops = kernels[dom]
     achieved = flops / (near_ms * 1e-3) / 1e12
@@ -600,12 +619,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": chosen,
+        "dtype": base,
         "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "dim": 3, "kernel": "laplace", "leaf_size": w.leaf_size,
-                   "tol": w.tol, "nrhs": 1, "step": "forward apply + adjoint apply"},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS[chosen], "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_TFLOPS[chosen], "traffic": traffic,
+                   "tol": w.tol, "nrhs": 1,
+                   "step": ("forward apply of q + adjoint apply of v in one two-column sweep (skelfmm_apply_fwd_adj)"
+                            if fused else "forward apply + adjoint apply")},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS[base], "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_TFLOPS[base], "traffic": traffic,
                      "issue_bound": issue_bound,
                      "kernel": dom, "ms_per_launch": near_ms,
                      "sym_pairs_per_launch": st["pairs_sym"], "sym_skel_pairs_per_launch": st["pairs_sym_skel"],
@@ -614,13 +635,16 @@ def main():
                      "near_kernels": {k: {"ms": v[0], "tflops": v[1] / (v[0] * 1e-3) / 1e12 if v[0] > 0 else None}
                                       for k, v in kernels.items()},
                      "near_reduce_ms": pm["near_reduce"]},
-        "transfer_passes": transfer_figures(st, pm, 8 if chosen == "f64" else 4),
+        "transfer_passes": transfer_figures(st, pm, 8 if chosen == "f64" else 4, width=2 if fused else 1),
         "paths": results,
         "autotune": tuned,
         "clocks": clk,
         "build_s": t_build,
     }
     f64_rate = w.n / (results["f64"]["ms_per_step"] * 1e-3) if "f64" in results else None
+    if f64_rate:
+        # the float32 step against the plain float64 forward + adjoint applies on this GPU
+        out["ratio_to_f64_fwd_adj"] = out["value"] / f64_rate
     legs = not (args.headline_only or args.profile_only)
     if legs and f64_rate:
         log("[bench] 64 float32 RHS on the same operator")

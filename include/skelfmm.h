@@ -17,6 +17,7 @@
  *   skelfmm_apply_adjoint  w = Atilde^H v, the transposed sweep (not in the paper):
  *                          transposed downward pass first, conjugated translations,
  *                          transposed upward pass last.  Runs on the GPU.
+ *   skelfmm_apply_fwd_adj  both at once; one shared sweep for real kernels in float32.
  *
  * Conventions shared by every call:
  *   - Status codes: SKELFMM_OK on success; a negative code otherwise, with a
@@ -176,6 +177,19 @@ skelfmm_status skelfmm_apply(skelfmm_op* op, const void* q, void* u, int64_t nrh
 skelfmm_status skelfmm_apply_adjoint(skelfmm_op* op, const void* v, void* w, int64_t nrhs,
                                      skelfmm_dtype dtype, void* hip_stream);
 
+/* u = Atilde q and w = Atilde^H v together (one right-hand side each), for callers
+ * that need both (the gradient of a loss, Krylov methods such as BiCG, LSQR, QMR).
+ * Same layout, stream and results as skelfmm_apply followed by skelfmm_apply_adjoint.
+ * For a real kernel in float32 the two run as ONE sweep with two interleaved
+ * columns: the adjoint of a real symmetric kernel's operator is the operator
+ * itself (one skeleton and one T per box serve its rows and columns), so every
+ * near-field kernel value and every read of T serves both vectors.  Other
+ * kernels and dtypes run the two sweeps in turn.  The fused sweep sizes its own
+ * workspace (two values per entry) on first use; q, v, u, w must be four distinct
+ * buffers.  Errors as skelfmm_apply. */
+skelfmm_status skelfmm_apply_fwd_adj(skelfmm_op* op, const void* q, const void* v, void* u, void* w,
+                                     skelfmm_dtype dtype, void* hip_stream);
+
 /* u = Atilde q (adjoint = 0) or w = Atilde^H v (adjoint = 1) without any device
  * allocation, for callers that cannot allocate while they apply (code under HIP
  * graph capture, tight serving loops, harnesses that forbid hipMalloc).  The same
@@ -202,10 +216,15 @@ skelfmm_status skelfmm_stats_get(const skelfmm_op* op, skelfmm_stats* out);
  * near-field launches for each tpl on `hip_stream` (synchronously; it overwrites
  * the workspace), keeps the fastest and returns it in *chosen, with the timings
  * in ms[SKELFMM_NTPL] (ms[tpl - 1]; may be NULL).  skelfmm_set_targets_per_lane
- * fixes tpl without timing. */
+ * fixes tpl without timing (for the single applies and the fused forward +
+ * adjoint sweep alike). */
 #define SKELFMM_NTPL 4
 skelfmm_status skelfmm_autotune(skelfmm_op* op, skelfmm_dtype dtype, void* hip_stream, int32_t* chosen, float* ms);
 skelfmm_status skelfmm_set_targets_per_lane(skelfmm_op* op, int32_t tpl);
+/* The same for the two-column near field of the fused float32 forward + adjoint
+ * sweep of a real kernel (its own setting).  ENOTSUP for complex kernels and for
+ * operators built with f64_leaf. */
+skelfmm_status skelfmm_autotune_fwd_adj(skelfmm_op* op, void* hip_stream, int32_t* chosen, float* ms);
 
 /* Launch shape of the many-RHS transfers on the matrix cores (float32 Laplace
  * applies with at least 8 right-hand sides; section 3, "FMM apply", equations

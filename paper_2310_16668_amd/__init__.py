@@ -106,6 +106,10 @@ _lib.skelfmm_batch_timing_read.argtypes = [_vp, _P(ctypes.c_double), _P(ctypes.c
 _lib.skelfmm_batch_timing_read.restype = ctypes.c_int
 _lib.skelfmm_apply_noalloc.argtypes = [_vp, _vp, _vp, ctypes.c_int64, ctypes.c_int, ctypes.c_int32, _vp]
 _lib.skelfmm_apply_noalloc.restype = ctypes.c_int
+_lib.skelfmm_apply_fwd_adj.argtypes = [_vp, _vp, _vp, _vp, _vp, ctypes.c_int, _vp]
+_lib.skelfmm_apply_fwd_adj.restype = ctypes.c_int
+_lib.skelfmm_autotune_fwd_adj.argtypes = [_vp, _vp, _P(ctypes.c_int32), _P(ctypes.c_float)]
+_lib.skelfmm_autotune_fwd_adj.restype = ctypes.c_int
 _lib.skelfmm_noalloc_scratch_bytes.argtypes = []
 _lib.skelfmm_noalloc_scratch_bytes.restype = ctypes.c_int64
 _lib.skelfmm_last_error.restype = ctypes.c_char_p
@@ -121,7 +125,7 @@ EXPORTED = ("skelfmm_build", "skelfmm_prepare", "skelfmm_apply", "skelfmm_apply_
             "skelfmm_autotune", "skelfmm_set_targets_per_lane", "skelfmm_autotune_transfers",
             "skelfmm_set_transfer_shape", "skelfmm_batch_autotune_transfers", "skelfmm_batch_timing",
             "skelfmm_batch_timing_read", "skelfmm_apply_noalloc",
-            "skelfmm_noalloc_scratch_bytes")
+            "skelfmm_noalloc_scratch_bytes", "skelfmm_apply_fwd_adj", "skelfmm_autotune_fwd_adj")
 NXFER = 4
 PASSES = ("gather", "upward", "near_field", "near_pairs", "near_reduce", "downward", "output")
 
@@ -288,6 +292,31 @@ class Operator:
     def apply_adjoint(self, v):
         """w = Atilde^H v (the transposed sweep)."""
         return self._run(v, True)
+
+    def apply_fwd_adj(self, q, v):
+        """(Atilde q, Atilde^H v) for two device vectors of shape [n] and one dtype
+        (skelfmm_apply_fwd_adj: one shared sweep for a real kernel in float32)."""
+        torch = _torch()
+        if q.dim() != 1 or v.dim() != 1 or q.shape[0] != self.n or v.shape[0] != self.n:
+            raise ValueError("q and v must be vectors of length n")
+        if q.dtype != v.dtype or not (q.is_cuda and v.is_cuda):
+            raise ValueError("q and v must be device tensors of one dtype")
+        q, v = q.contiguous(), v.contiguous()
+        u, w = torch.empty_like(q), torch.empty_like(v)
+        stream = torch.cuda.current_stream(q.device).cuda_stream
+        _check(_lib.skelfmm_apply_fwd_adj(self._h, q.data_ptr(), v.data_ptr(), u.data_ptr(), w.data_ptr(),
+                                          _dtype_code(q), stream))
+        return u, w
+
+    def autotune_fwd_adj(self) -> dict:
+        """Time the two-column near field of the fused float32 forward + adjoint sweep
+        with 1 .. 4 targets per lane; keep the fastest."""
+        torch = _torch()
+        chosen = ctypes.c_int32()
+        ms = (ctypes.c_float * 4)()
+        stream = torch.cuda.current_stream().cuda_stream
+        _check(_lib.skelfmm_autotune_fwd_adj(self._h, stream, ctypes.byref(chosen), ms))
+        return {"targets_per_lane": chosen.value, "ms": {t: ms[t - 1] for t in (1, 2, 3, 4)}}
 
 
 def build(points, kind: str = "laplace", tol: float = 1e-6, leaf_size: int = 64, kappa: float = 0.0,

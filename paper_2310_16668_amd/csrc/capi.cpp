@@ -162,6 +162,30 @@ skelfmm_status skelfmm_apply_adjoint(skelfmm_op* op, const void* v, void* w, int
     return apply_common(op, v, w, nrhs, dtype, hip_stream, true);
 }
 
+skelfmm_status skelfmm_apply_fwd_adj(skelfmm_op* op, const void* q, const void* v, void* u, void* w,
+                                     skelfmm_dtype dtype, void* hip_stream) {
+    if (!alive(op)) return fail(SKELFMM_EINVAL, "invalid operator");
+    if (!q || !v || !u || !w) return fail(SKELFMM_EINVAL, "NULL vector");
+    if (q == u || q == w || v == u || v == w || u == w)
+        return fail(SKELFMM_EINVAL, "inputs and outputs must be distinct buffers");
+    if (skelfmm_status s = check_dtype(op, dtype)) return s;
+    return guarded([&]() -> skelfmm_status {
+        skelfmm::device_apply_fwd_adj(op->dev, q, v, u, w, static_cast<int>(dtype), hip_stream);
+        return SKELFMM_OK;
+    });
+}
+
+skelfmm_status skelfmm_autotune_fwd_adj(skelfmm_op* op, void* hip_stream, int32_t* chosen, float* ms) {
+    if (!alive(op)) return fail(SKELFMM_EINVAL, "invalid operator");
+    if (!chosen) return fail(SKELFMM_EINVAL, "chosen is NULL");
+    return guarded([&]() -> skelfmm_status {
+        float t[SKELFMM_NTPL] = {};
+        *chosen = skelfmm::device_autotune_fwd_adj(op->dev, hip_stream, t);
+        if (ms) for (int i = 0; i < SKELFMM_NTPL; ++i) ms[i] = t[i];
+        return SKELFMM_OK;
+    });
+}
+
 skelfmm_status skelfmm_apply_noalloc(skelfmm_op* op, const void* q, void* u, int64_t nrhs, skelfmm_dtype dtype,
                                     int32_t adjoint, void* hip_stream) {
     if (!alive(op)) return fail(SKELFMM_EINVAL, "invalid operator");

@@ -128,6 +128,9 @@ DeviceOp* device_create(const Plan& p, bool keep_transparent, bool f64_leaf, boo
                         bool compensated);
 void device_prepare(DeviceOp* d, int64_t nrhs_max, int dtype);
 void device_apply(DeviceOp* d, const void* q, void* u, int64_t nrhs, int dtype, void* stream, bool adjoint);
+// u = A q and w = A^H v; real kernels in float32 share one sweep
+void device_apply_fwd_adj(DeviceOp* d, const void* q, const void* v, void* u, void* w, int dtype, void* stream);
+int device_autotune_fwd_adj(DeviceOp* d, void* stream, float* ms_out);
 void device_apply_noalloc(DeviceOp* d, const void* q, void* u, int64_t nrhs, int dtype, void* stream,
                           bool adjoint);
 size_t device_scratch_bytes();

@@ -285,6 +285,52 @@ void device_apply(DeviceOp* d, const void* q, void* u, int64_t nrhs, int dtype, 
     run(d, {IO{q, u, 0, d->L.n_points}}, nrhs, dtype, stream, adjoint);
 }
 
+// The forward + adjoint sweep of a real kernel in float32 (two interleaved
+// columns): whether this operator and dtype take it.
+static bool pair_sweep(const DeviceOp* d, int dtype) {
+    return d->L.kind == 0 && dtype == SKELFMM_F32 && !d->f64_leaf;
+}
+
+// Its workspace: two values per entry and per skeleton entry, two per slot.
+static void prepare_pair(DeviceOp* d) {
+    device_prepare(d, 1, SKELFMM_F32);
+    const size_t e = static_cast<size_t>(d->L.n_entries) * 2 * sizeof(float);
+    const size_t h = static_cast<size_t>(d->L.n_hentries) * 2 * sizeof(float);
+    const size_t sl = d->L.sym ? static_cast<size_t>(d->L.slot_size) * 2 * sizeof(double) : 0;
+    if (d->Q.bytes < e) { d->Q.alloc(e); d->U.alloc(e); }
+    if (d->Qh.bytes < h) { d->Qh.alloc(h); d->Uh.alloc(h); }
+    if (d->slots.bytes < sl) d->slots.alloc(sl);
+}
+
+void device_apply_fwd_adj(DeviceOp* d, const void* q, const void* v, void* u, void* w, int dtype, void* stream) {
+    if (!pair_sweep(d, dtype)) {
+        // complex kernels, float64 and float64 leaf sums: the two sweeps in turn
+        run(d, {IO{q, u, 0, d->L.n_points}}, 1, dtype, stream, false);
+        run(d, {IO{v, w, 0, d->L.n_points}}, 1, dtype, stream, true);
+        return;
+    }
+    int dev = -1;
+    SKF_HIP(hipGetDevice(&dev));
+    if (d->uploaded && dev != d->device) throw std::invalid_argument("operator was prepared on another device");
+    prepare_pair(d);
+    IO io{q, u, 0, d->L.n_points};
+    io.q2 = v;
+    io.u2 = w;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (d->L.dim == 3) sweep_pair_lap3(d, {io}, s, d->own_work());
+    else sweep_pair_lap2(d, {io}, s, d->own_work());
+}
+
+int device_autotune_fwd_adj(DeviceOp* d, void* stream, float* ms_out) {
+    if (!pair_sweep(d, SKELFMM_F32))
+        throw NotSupported("the forward + adjoint sweep serves real kernels in float32");
+    prepare_pair(d);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (d->L.dim == 3) tune_lap3(d, SKELFMM_F32, s, ms_out, true);
+    else tune_lap2(d, SKELFMM_F32, s, ms_out, true);
+    return d->tpl2;
+}
+
 // ---------------------------------------------------------------------------
 // apply without allocation: the workspace lives in a static device array
 // ---------------------------------------------------------------------------
@@ -346,8 +392,8 @@ int device_autotune(DeviceOp* d, int dtype, void* stream, float* ms_out) {
     const Layout& L = d->L;
     if (L.kind == 1 && L.dim == 2) tune_helm2(d, dtype, s, ms_out);
     else if (L.kind == 1) tune_helm3(d, dtype, s, ms_out);
-    else if (L.dim == 3) tune_lap3(d, dtype, s, ms_out);
-    else tune_lap2(d, dtype, s, ms_out);
+    else if (L.dim == 3) tune_lap3(d, dtype, s, ms_out, false);
+    else tune_lap2(d, dtype, s, ms_out, false);
     return d->tpl;
 }
 
@@ -406,6 +452,7 @@ int batch_autotune_xfer(DeviceBatch* b, int64_t nrhs, void* stream, float* ms_ou
 void device_set_tpl(DeviceOp* d, int tpl) {
     if (tpl < 1 || tpl > SKELFMM_NTPL) throw std::invalid_argument("targets per lane must be 1 .. 4");
     d->tpl = tpl;
+    d->tpl2 = tpl;
 }
 
 void device_fill_stats(const DeviceOp* d, skelfmm_stats* out) {

@@ -77,7 +77,7 @@ __device__ __forceinline__ float neg_log_r2(float r2) { return r2 > 0.0f ? -__lo
 __device__ __forceinline__ void sin_cos(double x, double* s, double* c) { sincos(x, s, c); }
 __device__ __forceinline__ void sin_cos(float x, float* s, float* c) { sincosf(x, s, c); }
 
-template <typename R, typename A, typename V, int DIM, int KIND, bool COMP = false>
+template <typename R, typename A, typename V, int DIM, int KIND, bool COMP = false, int RHS = 1>
 struct Pol {
     using Rt = R;   // kernel evaluation (coordinates are float64 in every policy)
     using At = A;   // accumulators
@@ -87,14 +87,20 @@ struct Pol {
     // float32 pair kernel: partial sums of at most four products before they
     // reach float64, column sums over the lanes in float64
     static constexpr bool comp = COMP;
-    static constexpr int nv = KIND == 1 ? 2 : 1;
+    // values per entry: the real and imaginary parts of a complex kernel's
+    // vector, or RHS interleaved columns of a real kernel (a forward apply and
+    // an adjoint apply share one sweep: for a real symmetric kernel the
+    // adjoint's kernel values are the forward's)
+    static constexpr int rhs = RHS;
+    static_assert(KIND == 0 || RHS == 1, "interleaved columns are for real kernels");
+    static constexpr int nv = KIND == 1 ? 2 : RHS;
     // 3D Laplace in float64 evaluates 2/r (see two_inv_r); the factor is undone in the scale
     static constexpr bool twice = DIM == 3 && KIND == 0 && sizeof(R) == 8;
     static constexpr double gscale = twice ? 0.5 : 1.0;
 };
 // The same policy with the pair kernel's compensated leaf sums.
 template <class P>
-using WithComp = Pol<typename P::Rt, typename P::At, typename P::Vt, P::dim, P::kind, true>;
+using WithComp = Pol<typename P::Rt, typename P::At, typename P::Vt, P::dim, P::kind, true, P::rhs>;
 
 // G(x_t, x_s) without the common factor kscale (for 2D Laplace: -log r^2, the
 // kernel times 4 pi; for 2D Helmholtz: i H0^(1)(kappa r), the kernel times 4),
@@ -357,10 +363,14 @@ __device__ __forceinline__ void near_loop(const Rec4<double>* __restrict__ X,
             R gr, gi;
             green<P, CONJ, MASK>(xt[p] - xs.x, yt[p] - xs.y, zt[p] - xs.z, kappa, gr, gi);
             const A g = static_cast<A>(gr);
-            if constexpr (nv == 1) {
-                acc[p][0] = fma(g, w[0], acc[p][0]);
-                if constexpr (MODE == 1) acch[p][0] = fma(-g, wh[0], acch[p][0]);
-                if constexpr (MODE == 2) acch[p][0] = fma(-g, w[0], acch[p][0]);
+            if constexpr (P::kind == 0) {
+                // a real kernel: each column on its own
+#pragma unroll
+                for (int v = 0; v < nv; ++v) {
+                    acc[p][v] = fma(g, w[v], acc[p][v]);
+                    if constexpr (MODE == 1) acch[p][v] = fma(-g, wh[v], acch[p][v]);
+                    if constexpr (MODE == 2) acch[p][v] = fma(-g, w[v], acch[p][v]);
+                }
             } else {
                 const A h = static_cast<A>(gi);
                 acc[p][0] = fma(g, w[0], fma(-h, w[1], acc[p][0]));
@@ -589,13 +599,14 @@ __device__ __forceinline__ void sym_block(const Rec4<double>* __restrict__ Xs, c
                                           const typename P::Vt* __restrict__ Qhs, int s0, int cnt,
                                           const double (&xt)[TPL], const double (&yt)[TPL],
                                           const double (&zt)[TPL], const double (&nt)[TPL],
-                                          const typename P::Rt (&wi)[TPL],
-                                          const typename P::Rt (&whi)[TPL], typename P::At (&acc)[TPL],
-                                          typename P::At (&acch)[TPL], typename P::Rt* tile, int lane,
-                                          double* __restrict__ rev_u, double* __restrict__ rev_h, bool first,
-                                          double sc) {
+                                          const typename P::Rt (&wi)[TPL][P::nv],
+                                          const typename P::Rt (&whi)[TPL][P::nv],
+                                          typename P::At (&acc)[TPL][P::nv], typename P::At (&acch)[TPL][P::nv],
+                                          typename P::Rt* tile, int lane, double* __restrict__ rev_u,
+                                          double* __restrict__ rev_h, bool first, double sc) {
     using R = typename P::Rt;
     using A = typename P::At;
+    constexpr int NR = P::nv;   // interleaved columns (a real kernel)
     // The running reverse sums of earlier passes are fetched before the block's
     // arithmetic, so their latency overlaps it.  Every lane loads (its column's
     // slot, clamped into the block) and forms the new sum, and only the store
@@ -605,15 +616,22 @@ __device__ __forceinline__ void sym_block(const Rec4<double>* __restrict__ Xs, c
     const int cs = lane / kSymLanes;
     const int cl = min(s0 + cs, last);
     const bool own = lane % kSymLanes == 0 && cs < cnt;
-    double prev_u = 0.0, prev_h = 0.0;
-    if (!first) {
-        prev_u = rev_u[cl];
-        if constexpr (H) prev_h = rev_h[cl];
-    }
-    R bacc[TPL], bh[TPL];
-    R ru[kSymBlock], rh[kSymBlock];
+    double prev_u[NR], prev_h[NR];
 #pragma unroll
-    for (int p = 0; p < TPL; ++p) { bacc[p] = R(0); bh[p] = R(0); }
+    for (int v = 0; v < NR; ++v) { prev_u[v] = 0.0; prev_h[v] = 0.0; }
+    if (!first) {
+#pragma unroll
+        for (int v = 0; v < NR; ++v) {
+            prev_u[v] = rev_u[cl * NR + v];
+            if constexpr (H) prev_h[v] = rev_h[cl * NR + v];
+        }
+    }
+    R bacc[TPL][NR], bh[TPL][NR];
+    R ru[NR][kSymBlock], rh[NR][kSymBlock];
+#pragma unroll
+    for (int p = 0; p < TPL; ++p)
+#pragma unroll
+        for (int v = 0; v < NR; ++v) { bacc[p][v] = R(0); bh[p][v] = R(0); }
 #pragma unroll
     for (int c = 0; c < kSymBlock; ++c) {
         // Expanded records are padded per box (copies of its last record), so
@@ -622,15 +640,19 @@ __device__ __forceinline__ void sym_block(const Rec4<double>* __restrict__ Xs, c
         // Exact coordinates are read at the clamped index.
         const int si = FAST ? s0 + c : min(s0 + c, last);
         const Rec4<double> sv = Xs[si];
-        const R qs = static_cast<R>(Qs[si]);
-        const R svw = c < cnt ? qs : R(0);
-        R svwh = R(0);
-        if constexpr (H) {
-            const R qh = static_cast<R>(Qhs[si]);
-            svwh = c < cnt ? qh : R(0);
+        R svw[NR], svwh[NR];
+#pragma unroll
+        for (int v = 0; v < NR; ++v) {
+            const R qs = static_cast<R>(Qs[si * NR + v]);
+            svw[v] = c < cnt ? qs : R(0);
+            svwh[v] = R(0);
+            if constexpr (H) {
+                const R qh = static_cast<R>(Qhs[si * NR + v]);
+                svwh[v] = c < cnt ? qh : R(0);
+            }
+            ru[v][c] = R(0);
+            rh[v][c] = R(0);
         }
-        ru[c] = R(0);
-        rh[c] = R(0);
 #pragma unroll
         for (int p = 0; p < TPL; ++p) {
             R g, gi;
@@ -641,47 +663,61 @@ __device__ __forceinline__ void sym_block(const Rec4<double>* __restrict__ Xs, c
             } else {
                 green<P, false, MASK>(xt[p] - sv.x, yt[p] - sv.y, zt[p] - sv.z, R(0), g, gi);
             }
-            bacc[p] = fma(g, svw, bacc[p]);
-            ru[c] = fma(g, wi[p], ru[c]);
-            if constexpr (H) {
-                bh[p] = fma(g, svwh, bh[p]);
-                rh[c] = fma(g, whi[p], rh[c]);
+#pragma unroll
+            for (int v = 0; v < NR; ++v) {
+                bacc[p][v] = fma(g, svw[v], bacc[p][v]);
+                ru[v][c] = fma(g, wi[p][v], ru[v][c]);
+                if constexpr (H) {
+                    bh[p][v] = fma(g, svwh[v], bh[p][v]);
+                    rh[v][c] = fma(g, whi[p][v], rh[v][c]);
+                }
             }
         }
         // compensated leaf sums: the forward partials reach float64 every four sources
         if constexpr (P::comp && sizeof(R) == 4) {
             if (c % 4 == 3 && c != kSymBlock - 1) {
 #pragma unroll
-                for (int p = 0; p < TPL; ++p) {
-                    acc[p] += static_cast<A>(bacc[p]);
-                    bacc[p] = R(0);
-                    if constexpr (H) {
-                        acch[p] += static_cast<A>(bh[p]);
-                        bh[p] = R(0);
+                for (int p = 0; p < TPL; ++p)
+#pragma unroll
+                    for (int v = 0; v < NR; ++v) {
+                        acc[p][v] += static_cast<A>(bacc[p][v]);
+                        bacc[p][v] = R(0);
+                        if constexpr (H) {
+                            acch[p][v] += static_cast<A>(bh[p][v]);
+                            bh[p][v] = R(0);
+                        }
                     }
-                }
             }
         }
     }
 #pragma unroll
-    for (int p = 0; p < TPL; ++p) {
-        acc[p] += static_cast<A>(bacc[p]);
-        if constexpr (H) acch[p] += static_cast<A>(bh[p]);
-    }
-    double nu, nh = 0.0;
-    if constexpr (P::comp && sizeof(R) == 4) nu = prev_u + sc * column_sum_f64<R>(ru, tile, lane);
-    else nu = prev_u + sc * static_cast<double>(column_sum<R>(ru, tile, lane));
-    if constexpr (H) {
-        if constexpr (P::comp && sizeof(R) == 4) nh = prev_h - sc * column_sum_f64<R>(rh, tile, lane);
-        else nh = prev_h - sc * static_cast<double>(column_sum<R>(rh, tile, lane));
+    for (int p = 0; p < TPL; ++p)
+#pragma unroll
+        for (int v = 0; v < NR; ++v) {
+            acc[p][v] += static_cast<A>(bacc[p][v]);
+            if constexpr (H) acch[p][v] += static_cast<A>(bh[p][v]);
+        }
+    double nu[NR], nh[NR];
+#pragma unroll
+    for (int v = 0; v < NR; ++v) {
+        if constexpr (P::comp && sizeof(R) == 4) nu[v] = prev_u[v] + sc * column_sum_f64<R>(ru[v], tile, lane);
+        else nu[v] = prev_u[v] + sc * static_cast<double>(column_sum<R>(ru[v], tile, lane));
+        nh[v] = 0.0;
+        if constexpr (H) {
+            if constexpr (P::comp && sizeof(R) == 4) nh[v] = prev_h[v] - sc * column_sum_f64<R>(rh[v], tile, lane);
+            else nh[v] = prev_h[v] - sc * static_cast<double>(column_sum<R>(rh[v], tile, lane));
+        }
     }
     // the reverse-sum loads have returned long ago; waiting for them here, in
     // every lane, keeps the wait out of the join after the masked store (where
     // it would also wait for that store)
     __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
     if (own) {
-        rev_u[cl] = nu;
-        if constexpr (H) rev_h[cl] = nh;
+#pragma unroll
+        for (int v = 0; v < NR; ++v) {
+            rev_u[cl * NR + v] = nu[v];
+            if constexpr (H) rev_h[cl * NR + v] = nh[v];
+        }
     }
 }
 
@@ -736,9 +772,10 @@ __device__ __forceinline__ void sym_pass(const SymCtx& cx, int tp, const Rec4<do
     const int tile_end = SELF ? min(tp + 64 * TPL, cx.t1) : 0;
     BlockPlan bp;
     bp.init(tile_end, hp ? bj.k : 0, bj.n);
+    constexpr int NR = P::nv;
     double xt[TPL], yt[TPL], zt[TPL], nt[TPL];
-    R wi[TPL], whi[TPL];
-    A acc[TPL], acch[TPL];
+    R wi[TPL][NR], whi[TPL][NR];
+    A acc[TPL][NR], acch[TPL][NR];
     // expanded form: target coordinates relative to the origin of the source
     // box (its first entry), the origin of the source records Xb
     double o[3] = {0.0, 0.0, 0.0};
@@ -754,15 +791,20 @@ __device__ __forceinline__ void sym_pass(const SymCtx& cx, int tp, const Rec4<do
         const Rec4<double> x = X[bi.voff + tc];
         xt[p] = x.x - o[0]; yt[p] = x.y - o[1]; zt[p] = x.z - o[2];
         nt[p] = fma(xt[p], xt[p], fma(yt[p], yt[p], zt[p] * zt[p]));
-        wi[p] = ok ? static_cast<R>(Q[bi.voff + tc]) : R(0);
-        whi[p] = (ok && t < bi.k) ? static_cast<R>(Qh[bi.hoff + t]) : R(0);
-        acc[p] = A(0);
-        acch[p] = A(0);
+#pragma unroll
+        for (int v = 0; v < NR; ++v) {
+            wi[p][v] = ok ? static_cast<R>(Q[(bi.voff + tc) * NR + v]) : R(0);
+            whi[p][v] = (ok && t < bi.k) ? static_cast<R>(Qh[(bi.hoff + t) * NR + v]) : R(0);
+            acc[p][v] = A(0);
+            acch[p][v] = A(0);
+        }
     }
     if constexpr (SELF) {
-        A ad[TPL][1], adh[TPL][1];
+        A ad[TPL][NR], adh[TPL][NR];
 #pragma unroll
-        for (int p = 0; p < TPL; ++p) { ad[p][0] = A(0); adh[p][0] = A(0); }
+        for (int p = 0; p < TPL; ++p)
+#pragma unroll
+            for (int v = 0; v < NR; ++v) { ad[p][v] = A(0); adh[p][v] = A(0); }
         if (hp) {
             near_loop<P, TPL, false, 1, true>(Xs, Qs, Qhs, tp, min(tile_end, bj.k), R(0), xt, yt, zt, ad, adh);
             near_loop<P, TPL, false, 0, true>(Xs, Qs, Qhs, max(tp, bj.k), tile_end, R(0), xt, yt, zt, ad, adh);
@@ -772,7 +814,9 @@ __device__ __forceinline__ void sym_pass(const SymCtx& cx, int tp, const Rec4<do
         // near_loop accumulates the uhat part with its minus sign; the pair
         // blocks below accumulate it positive and the store negates
 #pragma unroll
-        for (int p = 0; p < TPL; ++p) { acc[p] = ad[p][0]; acch[p] = -adh[p][0]; }
+        for (int p = 0; p < TPL; ++p)
+#pragma unroll
+            for (int v = 0; v < NR; ++v) { acc[p][v] = ad[p][v]; acch[p][v] = -adh[p][v]; }
     }
     for (int b = 0; b < bp.nb; ++b) {
         int s0, cnt;
@@ -788,13 +832,16 @@ __device__ __forceinline__ void sym_pass(const SymCtx& cx, int tp, const Rec4<do
     for (int p = 0; p < TPL; ++p) {
         const int t = tp + lane + 64 * p;
         if (t < cx.t1) {
-            cx.fwd_u[t - cx.t0] = cx.sc * static_cast<double>(acc[p]);
-            if (t < bi.k) cx.fwd_h[t - cx.t0] = -cx.sc * static_cast<double>(acch[p]);
-            // a self item's reverse row starts past the first diagonal tile; the
-            // first pass writes zeros before it so the whole row is defined
-            if (SELF && first) {
-                cx.rev_u[t] = 0.0;
-                if (t < bi.k) cx.rev_h[t] = 0.0;
+#pragma unroll
+            for (int v = 0; v < NR; ++v) {
+                cx.fwd_u[(t - cx.t0) * NR + v] = cx.sc * static_cast<double>(acc[p][v]);
+                if (t < bi.k) cx.fwd_h[(t - cx.t0) * NR + v] = -cx.sc * static_cast<double>(acch[p][v]);
+                // a self item's reverse row starts past the first diagonal tile; the
+                // first pass writes zeros before it so the whole row is defined
+                if (SELF && first) {
+                    cx.rev_u[t * NR + v] = 0.0;
+                    if (t < bi.k) cx.rev_h[t * NR + v] = 0.0;
+                }
             }
         }
     }
@@ -858,15 +905,17 @@ __device__ __forceinline__ void sym_item(const SymTask it, const BoxRec* __restr
     cx.bj = box[it.bj];
     cx.t0 = it.t0;
     cx.t1 = it.t1;
-    // uhat rows exist only where an item touches them (offsets < 0 are never used)
-    cx.fwd_u = slots + it.fwd_u;
-    cx.fwd_h = slots + (it.fwd_h >= 0 ? it.fwd_h : 0);
-    cx.rev_u = slots + it.rev_u;
-    cx.rev_h = slots + (it.rev_h >= 0 ? it.rev_h : 0);
+    // uhat rows exist only where an item touches them (offsets < 0 are never
+    // used); offsets count entries of P::nv values
+    constexpr int NR = P::nv;
+    cx.fwd_u = slots + NR * it.fwd_u;
+    cx.fwd_h = slots + NR * (it.fwd_h >= 0 ? it.fwd_h : 0);
+    cx.rev_u = slots + NR * it.rev_u;
+    cx.rev_h = slots + NR * (it.rev_h >= 0 ? it.rev_h : 0);
     cx.sc = scale * P::gscale;
     const Rec4<double>* Xs = X + cx.bj.voff;
-    const V* Qs = Q + cx.bj.voff;
-    const V* Qhs = Qh + cx.bj.hoff;
+    const V* Qs = Q + cx.bj.voff * NR;
+    const V* Qhs = Qh + cx.bj.hoff * NR;
     // the expanded |d|^2 serves the float32 evaluation of items the build marked safe for it
     if (sizeof(typename P::Rt) == 4 && (it.flags & SYM_EXPANDED))
         sym_passes<P, TPL, false, true>(cx, X, Q, Qh, Xs, Xe + cx.bj.roff, Qs, Qhs, tile, lane);
@@ -879,7 +928,7 @@ __device__ __forceinline__ void sym_item(const SymTask it, const BoxRec* __restr
 // Waves per SIMD the pair kernel is compiled for: the float32 evaluation fits
 // four waves' registers with up to two targets per lane, three with three.
 template <class P, int TPL>
-constexpr int sym_waves() { return sizeof(typename P::Rt) == 4 ? (TPL <= 2 ? 6 : (TPL == 3 ? 5 : 4)) : 1; }
+constexpr int sym_waves() { return sizeof(typename P::Rt) == 4 && P::rhs == 1 ? (TPL <= 2 ? 6 : (TPL == 3 ? 5 : 4)) : 1; }
 
 template <class P, int TPL>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sym_waves<P, TPL>(), 8))) k_near_sym(const SymTask* __restrict__ tasks, int ntasks,
@@ -915,21 +964,23 @@ __device__ __forceinline__ double add_rows(double acc, const double* __restrict_
 }
 
 // u and uhat of one box += its slot rows, in row order (deterministic).  A
-// block per receiving box; threads run over the box's entries, so every row is
-// read with coalesced loads.
-template <typename V>
+// block per receiving box; threads run over the box's entries (NV values
+// each: a complex entry or interleaved columns), so every row is read with
+// coalesced loads.
+template <typename V, int NV>
 __global__ void __launch_bounds__(256) k_sym_reduce(const SymRows* __restrict__ rows,
                                                     const BoxRec* __restrict__ box,
                                                     const double* __restrict__ slots, V* __restrict__ U,
                                                     V* __restrict__ Uh) {
     const SymRows r = rows[blockIdx.x];
     const BoxRec rec = box[r.box];
-    for (int e = threadIdx.x; e < rec.n; e += blockDim.x) {
-        U[rec.voff + e] = static_cast<V>(add_rows(static_cast<double>(U[rec.voff + e]), slots + r.base_u + e,
-                                                  r.ru, rec.n));
-        if (e < rec.k && r.rh > 0)
-            Uh[rec.hoff + e] = static_cast<V>(add_rows(static_cast<double>(Uh[rec.hoff + e]),
-                                                       slots + r.base_h + e, r.rh, rec.k));
+    for (int e = threadIdx.x; e < NV * rec.n; e += blockDim.x) {
+        V* u = U + NV * rec.voff + e;
+        *u = static_cast<V>(add_rows(static_cast<double>(*u), slots + NV * r.base_u + e, r.ru, NV * rec.n));
+        if (e < NV * rec.k && r.rh > 0) {
+            V* uh = Uh + NV * rec.hoff + e;
+            *uh = static_cast<V>(add_rows(static_cast<double>(*uh), slots + NV * r.base_h + e, r.rh, NV * rec.k));
+        }
     }
 }
 
@@ -1199,6 +1250,28 @@ __global__ void k_gather_pad(const int32_t* __restrict__ dst_e, const int32_t* _
     const int64_t r = i / Wp, c = i - r * Wp;
     out[static_cast<int64_t>(dst_e[r]) * Wp + c] =
         c < Win ? static_cast<VO>(in[static_cast<int64_t>(src_p[r]) * Win + c]) : VO(0);
+}
+
+// A forward and an adjoint column interleaved per entry (two real vectors
+// through one sweep): in[0] and in[1] gathered to out[2 e], out[2 e + 1].
+template <typename V>
+__global__ void k_gather2(const int32_t* __restrict__ dst_e, const int32_t* __restrict__ src_p, int64_t cnt,
+                          const V* __restrict__ a, const V* __restrict__ b, V* __restrict__ out) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= cnt) return;
+    const int64_t e = dst_e[i], p = src_p[i];
+    out[2 * e] = a[p];
+    out[2 * e + 1] = b[p];
+}
+
+template <typename V>
+__global__ void k_scatter2(const int32_t* __restrict__ src_e, const int32_t* __restrict__ dst_p, int64_t cnt,
+                           const V* __restrict__ in, V* __restrict__ a, V* __restrict__ b) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= cnt) return;
+    const int64_t e = src_e[i], p = dst_p[i];
+    a[p] = in[2 * e];
+    b[p] = in[2 * e + 1];
 }
 
 template <typename VI, typename VO>
@@ -1720,24 +1793,6 @@ __global__ void __launch_bounds__(256) k_near_sym_c(const SymTask* __restrict__ 
     const double sc = scale * P::gscale;
     for (int tp = it.t0; tp < it.t1; tp += 64 * TPL)
         sym_pass_c<P, TPL, CONJ>(it, bi, bj, tp, X, Q, Qh, slots, kappa, sc, tiles[wv], lane);
-}
-
-// u and uhat of one box += its complex slot rows (two doubles per entry), in row order.
-template <typename V>
-__global__ void __launch_bounds__(256) k_sym_reduce_c(const SymRows* __restrict__ rows,
-                                                      const BoxRec* __restrict__ box,
-                                                      const double* __restrict__ slots, V* __restrict__ U,
-                                                      V* __restrict__ Uh) {
-    const SymRows r = rows[blockIdx.x];
-    const BoxRec rec = box[r.box];
-    for (int e = threadIdx.x; e < 2 * rec.n; e += blockDim.x) {
-        V* u = U + 2 * rec.voff + e;
-        *u = static_cast<V>(add_rows(static_cast<double>(*u), slots + 2 * r.base_u + e, r.ru, 2 * rec.n));
-        if (e < 2 * rec.k && r.rh > 0) {
-            V* uh = Uh + 2 * rec.hoff + e;
-            *uh = static_cast<V>(add_rows(static_cast<double>(*uh), slots + 2 * r.base_h + e, r.rh, 2 * rec.k));
-        }
-    }
 }
 
 // Near field for NR right-hand sides per work item (one chunk of Wp): the

@@ -115,6 +115,7 @@ struct DeviceOp {
     std::vector<int> up_nw, down_nw;
     std::vector<int> up_rows, down_rows;          // per level: most output rows of a box (k up, n - k down)
     int tpl = kDefaultTPL;
+    int tpl2 = kDefaultTPL;                       // the same for a forward + adjoint sweep (two columns)
     int xfer = kDefaultXfer;                      // launch shape of the matrix-core transfers
     DevMem tasks[SKELFMM_NTPL];                   // work lists for 1 .. 4 targets per lane
     int ntasks[SKELFMM_NTPL] = {};
@@ -159,6 +160,10 @@ struct IO {
     void* u;
     int64_t g0;     // first index into the gather lists
     int64_t cnt;    // number of points
+    // a forward and an adjoint apply in one sweep (real kernels): the second
+    // input and output, interleaved with q and u inside the sweep
+    const void* q2 = nullptr;
+    void* u2 = nullptr;
 };
 
 // Events bracketing the passes of one sweep (only when timing is on).
@@ -228,14 +233,14 @@ void launch_near_t(const DeviceOp* d, hipStream_t s, void* Q, void* Qh, void* U,
     if (pm) pm->mark(4);
     if constexpr (P::kind == 1) {
         if (sym && d->nred > 0) {
-            hipLaunchKernelGGL((kern::k_sym_reduce_c<V>), dim3(d->nred), dim3(256), 0, s, d->symrows.as<SymRows>(),
+            hipLaunchKernelGGL((kern::k_sym_reduce<V, 2>), dim3(d->nred), dim3(256), 0, s, d->symrows.as<SymRows>(),
                                d->boxrec.as<kern::BoxRec>(), slots, static_cast<V*>(U), static_cast<V*>(Uh));
             SKF_HIP(hipGetLastError());
         }
     }
     if constexpr (P::kind == 0) {
         if (sym && d->nred > 0) {
-            hipLaunchKernelGGL((kern::k_sym_reduce<V>), dim3(d->nred), dim3(256), 0, s, d->symrows.as<SymRows>(),
+            hipLaunchKernelGGL((kern::k_sym_reduce<V, P::nv>), dim3(d->nred), dim3(256), 0, s, d->symrows.as<SymRows>(),
                                d->boxrec.as<kern::BoxRec>(), slots, static_cast<V*>(U),
                                static_cast<V*>(Uh));
             SKF_HIP(hipGetLastError());
@@ -245,9 +250,10 @@ void launch_near_t(const DeviceOp* d, hipStream_t s, void* Q, void* Qh, void* U,
 
 template <class P, bool CONJ>
 void launch_near(const DeviceOp* d, hipStream_t s, const Work& w, PassMarks* pm = nullptr) {
-    if (d->tpl == 1) launch_near_t<P, 1, CONJ>(d, s, w.Q, w.Qh, w.U, w.Uh, w.slots, pm);
-    else if (d->tpl == 3) launch_near_t<P, 3, CONJ>(d, s, w.Q, w.Qh, w.U, w.Uh, w.slots, pm);
-    else if (d->tpl == 4) launch_near_t<P, 4, CONJ>(d, s, w.Q, w.Qh, w.U, w.Uh, w.slots, pm);
+    const int tpl = P::rhs == 2 ? d->tpl2 : d->tpl;
+    if (tpl == 1) launch_near_t<P, 1, CONJ>(d, s, w.Q, w.Qh, w.U, w.Uh, w.slots, pm);
+    else if (tpl == 3) launch_near_t<P, 3, CONJ>(d, s, w.Q, w.Qh, w.U, w.Uh, w.slots, pm);
+    else if (tpl == 4) launch_near_t<P, 4, CONJ>(d, s, w.Q, w.Qh, w.U, w.Uh, w.slots, pm);
     else launch_near_t<P, 2, CONJ>(d, s, w.Q, w.Qh, w.U, w.Uh, w.slots, pm);
 }
 
@@ -346,7 +352,10 @@ void sweep(DeviceOp* d, const std::vector<IO>& io, int64_t nrhs, int dtype, hipS
     const bool multi = nrhs > 1;
     const int Win = static_cast<int>(nrhs * P::nv);
     const bool mfma = use_mfma(d, nrhs, dtype);
-    const int Wp = static_cast<int>(padded_width(nrhs, dtype, mfma));
+    // one RHS: P::nv values per entry (a complex value, or a forward and an
+    // adjoint column of a real kernel), unpadded
+    const int Wp = multi ? static_cast<int>(padded_width(nrhs, dtype, mfma)) : P::nv;
+    static_assert(P::rhs == 1 || P::kind == 0, "interleaved columns are for real kernels");
     V* Q = static_cast<V*>(w.Q);
     V* Qh = static_cast<V*>(w.Qh);
     V* U = static_cast<V*>(w.U);
@@ -361,8 +370,12 @@ void sweep(DeviceOp* d, const std::vector<IO>& io, int64_t nrhs, int dtype, hipS
     pm.mark(0);
     for (const IO& x : io) {
         if (x.cnt <= 0) continue;
-        hipLaunchKernelGGL((kern::k_gather_pad<V, V>), dim3(blocks_for(x.cnt * Wp, 256)), dim3(256), 0, s,
-                           ge + x.g0, gp + x.g0, x.cnt, Win, Wp, static_cast<const V*>(x.q), Q);
+        if constexpr (P::rhs == 2)
+            hipLaunchKernelGGL((kern::k_gather2<V>), dim3(blocks_for(x.cnt, 256)), dim3(256), 0, s, ge + x.g0,
+                               gp + x.g0, x.cnt, static_cast<const V*>(x.q), static_cast<const V*>(x.q2), Q);
+        else
+            hipLaunchKernelGGL((kern::k_gather_pad<V, V>), dim3(blocks_for(x.cnt * Wp, 256)), dim3(256), 0, s,
+                               ge + x.g0, gp + x.g0, x.cnt, Win, Wp, static_cast<const V*>(x.q), Q);
         SKF_HIP(hipGetLastError());
     }
     pm.mark(1);
@@ -442,8 +455,12 @@ void sweep(DeviceOp* d, const std::vector<IO>& io, int64_t nrhs, int dtype, hipS
     pm.mark(6);
     for (const IO& x : io) {
         if (x.cnt <= 0) continue;
-        hipLaunchKernelGGL((kern::k_scatter_pad<V, V>), dim3(blocks_for(x.cnt * Win, 256)), dim3(256), 0, s,
-                           ge + x.g0, gp + x.g0, x.cnt, Win, Wp, U, static_cast<V*>(x.u));
+        if constexpr (P::rhs == 2)
+            hipLaunchKernelGGL((kern::k_scatter2<V>), dim3(blocks_for(x.cnt, 256)), dim3(256), 0, s, ge + x.g0,
+                               gp + x.g0, x.cnt, U, static_cast<V*>(x.u), static_cast<V*>(x.u2));
+        else
+            hipLaunchKernelGGL((kern::k_scatter_pad<V, V>), dim3(blocks_for(x.cnt * Win, 256)), dim3(256), 0, s,
+                               ge + x.g0, gp + x.g0, x.cnt, Win, Wp, U, static_cast<V*>(x.u));
         SKF_HIP(hipGetLastError());
     }
     pm.mark(7);
@@ -466,19 +483,39 @@ void dispatch(DeviceOp* d, const std::vector<IO>& io, int64_t nrhs, int dtype, h
 }
 
 
+// A forward apply (io's q -> u) and an adjoint apply (q2 -> u2) of a real
+// kernel in one float32 sweep: the adjoint of a real symmetric kernel's
+// operator is the operator itself (the skeletons and T serve rows and columns
+// alike), so the two vectors go through the sweep as two interleaved columns
+// and share every kernel value of the near field.
+template <int DIM>
+void dispatch_pair(DeviceOp* d, const std::vector<IO>& io, hipStream_t s, const Work& w) {
+    using P = kern::Pol<float, double, float, DIM, 0, false, 2>;
+    sweep<float, float, P, float>(d, io, 1, SKELFMM_F32, s, false, w, d->T32.as<float>(), d->Tt32.as<float>());
+}
+
 // Time the near-field launches for 1 .. 4 targets per lane on this operator
 // (workspace contents are whatever the last apply left; timing does not depend
-// on values) and keep the fastest.
+// on values) and keep the fastest.  pair: the two-column near field of the
+// forward + adjoint sweep (its own setting, tpl2).
 template <int DIM, int KIND>
-void tune_near(DeviceOp* d, int dtype, hipStream_t s, float* ms_out) {
+void tune_near(DeviceOp* d, int dtype, hipStream_t s, float* ms_out, bool pair = false) {
     const bool single = dtype_is_single(dtype);
+    int& tpl = pair ? d->tpl2 : d->tpl;
     for (int t : {1, 2, 3, 4}) {
-        d->tpl = t;
+        tpl = t;
         hipEvent_t a, b;
         SKF_HIP(hipEventCreate(&a));
         SKF_HIP(hipEventCreate(&b));
         for (int rep = 0; rep < 4; ++rep) {
             if (rep == 1) SKF_HIP(hipEventRecord(a, s));
+            if constexpr (KIND == 0) {
+                if (pair) {
+                    using P = kern::Pol<float, double, float, DIM, 0, false, 2>;
+                    launch_near<P, false>(d, s, d->own_work());
+                    continue;
+                }
+            }
             if (!single) {
                 using P = kern::Pol<double, double, double, DIM, KIND>;
                 launch_near<P, false>(d, s, d->own_work());
@@ -501,7 +538,7 @@ void tune_near(DeviceOp* d, int dtype, hipStream_t s, float* ms_out) {
     int best = 1;
     for (int t : {1, 2, 3, 4})
         if (ms_out[tpl_slot(t)] < ms_out[tpl_slot(best)]) best = t;
-    d->tpl = best;
+    tpl = best;
 }
 
 
@@ -514,8 +551,10 @@ void sweep_helm3(DeviceOp* d, const std::vector<IO>& io, int64_t nrhs, int dtype
                  const Work& w);
 void sweep_helm2(DeviceOp* d, const std::vector<IO>& io, int64_t nrhs, int dtype, hipStream_t s, bool adjoint,
                  const Work& w);
-void tune_lap2(DeviceOp* d, int dtype, hipStream_t s, float* ms_out);
-void tune_lap3(DeviceOp* d, int dtype, hipStream_t s, float* ms_out);
+void tune_lap2(DeviceOp* d, int dtype, hipStream_t s, float* ms_out, bool pair);
+void tune_lap3(DeviceOp* d, int dtype, hipStream_t s, float* ms_out, bool pair);
+void sweep_pair_lap2(DeviceOp* d, const std::vector<IO>& io, hipStream_t s, const Work& w);
+void sweep_pair_lap3(DeviceOp* d, const std::vector<IO>& io, hipStream_t s, const Work& w);
 void tune_helm3(DeviceOp* d, int dtype, hipStream_t s, float* ms_out);
 void tune_helm2(DeviceOp* d, int dtype, hipStream_t s, float* ms_out);
 

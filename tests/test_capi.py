@@ -89,6 +89,13 @@ def test_apply_argument_errors_before_gpu_work():
     assert lib.skelfmm_apply(op.handle, buf, ctypes.c_void_p(0x2000), 1, sk.C128, None) == -1
     assert lib.skelfmm_apply(op.handle, buf, ctypes.c_void_p(0x2000), 1, 9, None) == -1
     assert lib.skelfmm_apply(None, buf, ctypes.c_void_p(0x2000), 1, sk.F64, None) == -1
+    b2, b3, b4 = ctypes.c_void_p(0x2000), ctypes.c_void_p(0x3000), ctypes.c_void_p(0x4000)
+    assert lib.skelfmm_apply_fwd_adj(op.handle, None, b2, b3, b4, sk.F32, None) == -1
+    assert lib.skelfmm_apply_fwd_adj(op.handle, buf, b2, b3, b3, sk.F32, None) == -1
+    assert lib.skelfmm_apply_fwd_adj(op.handle, buf, b2, buf, b4, sk.F32, None) == -1
+    assert lib.skelfmm_apply_fwd_adj(op.handle, buf, b2, b3, b4, sk.C64, None) == -1
+    assert lib.skelfmm_apply_fwd_adj(None, buf, b2, b3, b4, sk.F32, None) == -1
+    assert lib.skelfmm_autotune_fwd_adj(op.handle, None, None, None) == -1
     assert lib.skelfmm_set_targets_per_lane(op.handle, 5) == -1
     assert lib.skelfmm_set_targets_per_lane(op.handle, 0) == -1
     assert lib.skelfmm_set_targets_per_lane(op.handle, 3) == 0

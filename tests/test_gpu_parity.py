@@ -427,3 +427,43 @@ def test_helmholtz_symmetric_pairing(name):
         ec, ewc = relerr(uc, u2r), relerr(wc, w2r)
         record(f"{name} c64 f64-leaf paired tpl{t}", vs_o2=ec, adjoint_vs_o2t=ewc)
         assert ec <= F32_VS_O2 and ewc <= F32_VS_O2
+
+
+@pytest.mark.parametrize("name", ["lap3d_uniform_64k", "lap2d_16k", "lap3d_ellipsoid_60k", "helm3d_uniform_32k"])
+def test_fused_forward_adjoint(name):
+    """skelfmm_apply_fwd_adj: (A q, A^H v) in one call.  Real kernels in float32
+    share one sweep (two interleaved columns) at every targets-per-lane setting;
+    each column matches its own single apply to float32 rounding and O2 to the
+    float32 bar.  Complex kernels run the two sweeps in turn (same results as
+    the separate calls, bit for bit)."""
+    x, op, P = _op(name)
+    kind = CASES[name][1]
+    cplx = kind == "helmholtz"
+    dt = torch.complex64 if cplx else torch.float32
+    q = _charges(name, x.shape[0], 21)
+    v = _charges(name, x.shape[0], 22)
+    qd, vd = dev(q, dt), dev(v, dt)
+    u1, w1 = host(op.apply(qd)), host(op.apply_adjoint(vd))
+    up = np.complex128 if cplx else np.float64
+    qr = q.astype(np.complex64 if cplx else np.float32).astype(q.dtype)
+    vr = v.astype(np.complex64 if cplx else np.float32).astype(v.dtype)
+    u2 = oracle.apply(P, qr)
+    w2 = oracle.apply(P, vr, adjoint=True)
+    if cplx:
+        u, w = op.apply_fwd_adj(qd, vd)
+        assert np.array_equal(host(u), u1) and np.array_equal(host(w), w1)
+        return
+    for tpl in (1, 2, 3, 4, 0):
+        if tpl:
+            op.set_targets_per_lane(tpl)
+            u1, w1 = host(op.apply(qd)), host(op.apply_adjoint(vd))
+        else:
+            tpl = op.autotune_fwd_adj()["targets_per_lane"]
+            assert tpl in (1, 2, 3, 4)
+        u, w = op.apply_fwd_adj(qd, vd)
+        u, w = host(u).astype(up), host(w).astype(up)
+        e_single = max(relerr(u, u1.astype(up)), relerr(w, w1.astype(up)))
+        e_u, e_w = relerr(u, u2), relerr(w, w2)
+        record(f"{name} fwd_adj tpl={tpl}", vs_single=e_single, vs_o2=e_u, adjoint_vs_o2t=e_w)
+        assert e_single <= F32_VS_O2
+        assert e_u <= F32_VS_O2 and e_w <= F32_VS_O2
