@@ -632,22 +632,26 @@ __device__ __forceinline__ void sym_block(const Rec4<double>* __restrict__ Xs, c
     for (int p = 0; p < TPL; ++p)
 #pragma unroll
         for (int v = 0; v < NR; ++v) { bacc[p][v] = R(0); bh[p][v] = R(0); }
+    // the block's first source: constant offsets from here let the loads merge
+    const Rec4<double>* __restrict__ Xb0 = Xs + s0;
+    const typename P::Vt* __restrict__ Qb0 = Qs + static_cast<int64_t>(s0) * NR;
+    const typename P::Vt* __restrict__ Qhb0 = Qhs + static_cast<int64_t>(s0) * NR;
 #pragma unroll
     for (int c = 0; c < kSymBlock; ++c) {
         // Expanded records are padded per box (copies of its last record), so
         // the block reads them unclamped and the loads merge; the charges past
         // cnt are read within the arrays' spare tail and replaced by zero.
         // Exact coordinates are read at the clamped index.
-        const int si = FAST ? s0 + c : min(s0 + c, last);
-        const Rec4<double> sv = Xs[si];
+        const int ci = FAST ? c : min(c, cnt - 1);
+        const Rec4<double> sv = Xb0[ci];
         R svw[NR], svwh[NR];
 #pragma unroll
         for (int v = 0; v < NR; ++v) {
-            const R qs = static_cast<R>(Qs[si * NR + v]);
+            const R qs = static_cast<R>(Qb0[c * NR + v]);
             svw[v] = c < cnt ? qs : R(0);
             svwh[v] = R(0);
             if constexpr (H) {
-                const R qh = static_cast<R>(Qhs[si * NR + v]);
+                const R qh = static_cast<R>(Qhb0[c * NR + v]);
                 svwh[v] = c < cnt ? qh : R(0);
             }
             ru[v][c] = R(0);
