@@ -81,12 +81,17 @@ FLOPS_PER_HELM_SYM_SKEL_PAIR = 16
 # targets-per-lane variant, valid only for the kernel and kernel source they were
 # measured on (first 16 hex digits of the sha256 of the pair kernel's section of
 # kernels.hip, pair_kernel_digest).
-NEAR_TRAFFIC = {"f32": {"kernel": "k_near_sym", "kernels_sha256": "542e57b9110cce95",
-                        "bytes_by_tpl": {
-                          1: 6.4410e+09 + 2.0518e+09,
-                          2: 3.9893e+09 + 1.5460e+09,
-                          3: 2.8289e+09 + 1.0113e+09,
-                          4: 1.9410e+09 + 7.4405e+08}}}
+NEAR_TRAFFIC = {
+    "f32": {"kernel": "k_near_sym", "kernels_sha256": "7a829e1ff051d1e1",
+            "bytes_by_tpl": {1: 1.0775e+10 + 2.0506e+09, 2: 6.0432e+09 + 1.2163e+09,
+                             3: 4.6176e+09 + 9.4874e+08, 4: 3.2830e+09 + 7.4526e+08}},
+    "f32_fused": {"kernel": "k_near_sym", "kernels_sha256": "7a829e1ff051d1e1",
+                  "bytes_by_tpl": {1: 1.4131e+10 + 4.0723e+09, 2: 7.3514e+09 + 2.4062e+09,
+                                   3: 5.5221e+09 + 1.8773e+09, 4: 3.9171e+09 + 1.4802e+09}},
+    "f64": {"kernel": "k_near_sym", "kernels_sha256": "7a829e1ff051d1e1",
+            "bytes_by_tpl": {1: 1.1539e+10 + 2.0484e+09, 2: 6.3879e+09 + 1.2125e+09,
+                             3: 4.8123e+09 + 9.4521e+08, 4: 3.3696e+09 + 7.4386e+08}},
+}
 
 
 PAIR_KERNEL_BEGIN = "// symmetric near field (real kernels, one right-hand side)"

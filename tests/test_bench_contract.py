@@ -29,7 +29,9 @@ def test_traffic_is_reported_only_for_the_measured_kernel_source(monkeypatch):
     monkeypatch.setitem(tr, "kernels_sha256", digest)
     assert bench.near_traffic("f32", "k_near_sym", 3) == tr["bytes_by_tpl"][3]
     assert bench.near_traffic("f32", "k_near", 3) is None
-    assert bench.near_traffic("f64", "k_near_sym", 3) is None
+    assert bench.near_traffic("c128", "k_near_sym", 3) is None   # a path never measured
+    for path in ("f32_fused", "f64"):
+        assert sorted(bench.NEAR_TRAFFIC[path]["bytes_by_tpl"]) == [1, 2, 3, 4]
     monkeypatch.setitem(tr, "kernels_sha256", "0" * 16)
     assert bench.near_traffic("f32", "k_near_sym", 3) is None
 
