@@ -46,16 +46,18 @@ PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
 # Dense float32 matrix-core peak (published), for the many-RHS kernels.
 PEAK_MFMA_F32_TFLOPS = 157.3
 # Issue cycles per wave instruction (64 lanes) used for the instruction-mix bound of
-# the float32 pair kernel: float64 add / multiply-add and the float64 -> float32
-# conversion 4, float32 multiply-add 2, reciprocal square root 16.  The cheapest
-# evaluation of a symmetric pair (expanded |d|^2: one float64 add and three float64
-# multiply-adds; one conversion; one reciprocal square root; two float32
-# multiply-adds) therefore costs 40 cycles per wave of 64 pairs.
+# the float32 pair kernel, measured on MI355X with loop kernels of independent
+# instructions (8 chains per lane, 8 waves per SIMD): float64 add / multiply-add
+# and the float64 -> float32 conversion 4, float32 multiply-add 2, reciprocal
+# square root 8 (it does not overlap the other VALU work of its SIMD).  The
+# cheapest evaluation of a symmetric pair (expanded |d|^2: one float64 add and
+# three float64 multiply-adds; one conversion; one reciprocal square root; two
+# float32 multiply-adds per column) therefore costs 32 cycles per wave of 64 pairs
+# with one column and 36 with the two columns of the fused forward + adjoint sweep.
 CLOCK_GHZ = 2.4
 SIMDS = 1024
-MIX_CYCLES_PER_64_SYM_PAIRS = {"f32": 4 * 4 + 4 + 16 + 2 * 2,
-                               # the fused forward + adjoint sweep: one evaluation, four multiply-adds
-                               "f32_fused": 4 * 4 + 4 + 16 + 4 * 2}
+MIX_CYCLES_PER_64_SYM_PAIRS = {"f32": 4 * 4 + 4 + 8 + 2 * 2,
+                               "f32_fused": 4 * 4 + 4 + 8 + 4 * 2}
 PEAK_HBM_GBS = 8000.0
 # algorithmic flops of one 3D Laplace pair in k_near: 3 subtractions, |d|^2
 # (3 mul + 2 add), one reciprocal square root, one multiply-add into u; a skeleton

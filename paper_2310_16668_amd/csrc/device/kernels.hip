@@ -932,7 +932,11 @@ __device__ __forceinline__ void sym_item(const SymTask it, const BoxRec* __restr
 // Waves per SIMD the pair kernel is compiled for: the float32 evaluation fits
 // four waves' registers with up to two targets per lane, three with three.
 template <class P, int TPL>
-constexpr int sym_waves() { return sizeof(typename P::Rt) == 4 && P::rhs == 1 ? (TPL <= 2 ? 6 : (TPL == 3 ? 5 : 4)) : 1; }
+constexpr int sym_waves() {
+    if (sizeof(typename P::Rt) != 4) return 1;
+    if (P::rhs == 1) return TPL <= 2 ? 6 : (TPL == 3 ? 5 : 4);
+    return TPL == 1 ? 6 : (TPL == 2 ? 5 : (TPL == 3 ? 4 : 1));
+}
 
 template <class P, int TPL>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sym_waves<P, TPL>(), 8))) k_near_sym(const SymTask* __restrict__ tasks, int ntasks,
