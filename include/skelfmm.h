@@ -54,10 +54,16 @@ typedef enum {
     SKELFMM_EINTERNAL = -5
 } skelfmm_status;
 
-typedef enum { SKELFMM_LAPLACE = 0, SKELFMM_HELMHOLTZ = 1 } skelfmm_kind;
+/* The *_ENUM_MAX entries are not values: they give the enum types the range of
+ * int32, so an out-of-range argument from a caller is a value the library can
+ * reject (EINVAL), not undefined behaviour on the C++ side. */
+typedef enum { SKELFMM_LAPLACE = 0, SKELFMM_HELMHOLTZ = 1, SKELFMM_KIND_ENUM_MAX = 0x7fffffff } skelfmm_kind;
 
 /* Arithmetic of an apply.  Laplace takes F64 or F32, Helmholtz C128 or C64. */
-typedef enum { SKELFMM_F64 = 0, SKELFMM_F32 = 1, SKELFMM_C128 = 2, SKELFMM_C64 = 3 } skelfmm_dtype;
+typedef enum {
+    SKELFMM_F64 = 0, SKELFMM_F32 = 1, SKELFMM_C128 = 2, SKELFMM_C64 = 3,
+    SKELFMM_DTYPE_ENUM_MAX = 0x7fffffff
+} skelfmm_dtype;
 
 /* Kernel G (section 2, equations for the Laplace and Helmholtz kernels):
  *   2D Laplace    -log(r) / (2 pi)          (dim = 2)
@@ -91,7 +97,7 @@ typedef struct {
     int32_t compensated_leaf;/* F32 applies with one right-hand side: the symmetric pair kernel keeps
                                 its float32 partial sums to at most four products per target and
                                 forms its per-source column sums in float64 before everything is
-                                accumulated in float64 (default 0: float32 partials over blocks of 16
+                                accumulated in float64 (default 0: float32 partials over blocks of 8
                                 sources and float32 column sums over the 64 x tpl targets of a pass) */
     int32_t gpu_build;       /* 1: skelfmm_build computes the interpolative decompositions (proxy
                                 matrices, pivoted QR, T = R11^{-1} R12) level by level on the current

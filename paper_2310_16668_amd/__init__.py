@@ -14,7 +14,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "libskelfmm.so")
+# SKELFMM_LIB selects another build of the same library (the host-sanitizer build)
+_LIB_PATH = os.environ.get("SKELFMM_LIB") or os.path.join(_HERE, "libskelfmm.so")
 
 if not os.path.exists(_LIB_PATH):
     raise ImportError(f"{_LIB_PATH} is missing; build it with __graft_entry__.build() "
