@@ -104,6 +104,21 @@ static void build_transfer_work(DeviceOp* d) {
         d->upwork[g].upload(up);
         d->downwork[g].upload(down);
     }
+    // levels whose boxes are all uncompressed (k = n, no T) with entries and
+    // skeleton entries laid out alike: the transfers are elementwise there
+    d->flat.assign(L.max_level + 1, FlatLevel{});
+    for (int l = 2; l <= L.max_level; ++l) {
+        const int b0 = L.level_ptr[l], b1 = L.level_ptr[l + 1];
+        if (b1 <= b0) continue;
+        bool ok = true;
+        int64_t e = L.voff[b0], h = L.hoff[b0];
+        for (int b = b0; b < b1 && ok; ++b) {
+            ok = L.kb[b] == L.nb[b] && L.voff[b] == e && L.hoff[b] == h;
+            e += L.nb[b];
+            h += L.kb[b];
+        }
+        if (ok && e > L.voff[b0]) d->flat[l] = FlatLevel{L.voff[b0], L.hoff[b0], e - L.voff[b0]};
+    }
 }
 
 // T (k x m per box) or its transpose (m x k) with columns padded to pad_ld rows,

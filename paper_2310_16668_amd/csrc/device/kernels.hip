@@ -270,6 +270,36 @@ __global__ void __launch_bounds__(1024) k_up_gemv(const int2* __restrict__ work,
     }
 }
 
+// The same two passes on a level of uncompressed boxes (k = n, no T), whose
+// entries e0 + j and skeleton entries h0 + j correspond one to one: one
+// thread per value instead of a block per box (the leaf level of a uniform
+// cube holds 32,768 such boxes of ~32 points).  The arithmetic is that of
+// k_up_gemv / k_down_gemv for such a box.
+template <typename V, int NV>
+__global__ void __launch_bounds__(256) k_up_flat(int64_t e0, int64_t h0, int64_t cnt,
+                                                 const int32_t* __restrict__ pmap, const V* __restrict__ Qin,
+                                                 V* __restrict__ Qout, V* __restrict__ Qh) {
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= cnt * NV) return;
+    const int64_t j = t / NV, v = t - j * NV;
+    const V val = Qin[(e0 + j) * NV + v];
+    Qh[(h0 + j) * NV + v] = val;
+    Qout[static_cast<int64_t>(pmap[h0 + j]) * NV + v] = val;
+}
+
+template <typename V, int NV>
+__global__ void __launch_bounds__(256) k_down_flat(int64_t e0, int64_t h0, int64_t cnt,
+                                                   const int32_t* __restrict__ pmap, const V* __restrict__ Uh,
+                                                   const V* __restrict__ Upar, V* __restrict__ Uown) {
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= cnt * NV) return;
+    const int64_t j = t / NV, v = t - j * NV;
+    const double uh = static_cast<double>(Uh[(h0 + j) * NV + v]) +
+                      static_cast<double>(Upar[static_cast<int64_t>(pmap[h0 + j]) * NV + v]);
+    V* u = Uown + (e0 + j) * NV + v;
+    *u = static_cast<V>(static_cast<double>(*u) + uh);
+}
+
 // downward: uhat = Uh + U_parent[pmap]; u[0:k] += uhat; u[k:n] += T^T uhat,
 // with Tt = T^T stored column-major (m x k, columns padded) so rows of the
 // result are contiguous; toff here holds the offsets of the transposes.

@@ -96,6 +96,12 @@ struct Work {
     bool marks;     // per-pass events when the operator's timing is on
 };
 
+// A level of uncompressed boxes whose entries [e0, e0 + cnt) and skeleton
+// entries [h0, h0 + cnt) correspond one to one (cnt = 0: not such a level).
+struct FlatLevel {
+    int64_t e0 = 0, h0 = 0, cnt = 0;
+};
+
 struct DeviceOp {
     Layout L;
     bool f64_leaf = false;
@@ -114,6 +120,7 @@ struct DeviceOp {
     std::vector<int64_t> up_ptr[4], down_ptr[4];
     std::vector<int> up_nw, down_nw;
     std::vector<int> up_rows, down_rows;          // per level: most output rows of a box (k up, n - k down)
+    std::vector<FlatLevel> flat;                  // per level: elementwise transfers (all boxes uncompressed)
     int tpl = kDefaultTPL;
     int tpl2 = kDefaultTPL;                       // the same for a forward + adjoint sweep (two columns)
     int xfer = kDefaultXfer;                      // launch shape of the matrix-core transfers
@@ -393,6 +400,9 @@ void sweep(DeviceOp* d, const std::vector<IO>& io, int64_t nrhs, int dtype, hipS
             const int gy = std::max(1, (d->up_rows[l] + 4 * kern::kRB - 1) / (4 * kern::kRB));
             hipLaunchKernelGGL((kern::k_upward_mr<V, TT>), dim3(nbx, gy), dim3(256), 0, s, br, toff, pmap, b0, Wp,
                                T, Q, Qh);
+        } else if (const FlatLevel& fl = d->flat[l]; fl.cnt > 0) {
+            hipLaunchKernelGGL((kern::k_up_flat<V, P::nv>), dim3(blocks_for(fl.cnt * P::nv, 256)), dim3(256), 0, s,
+                               fl.e0, fl.h0, fl.cnt, pmap, Q, Q, Qh);
         } else {
             const int wg = sizeof(TT) == 4 ? 1 : 0;
             const int64_t w0 = d->up_ptr[wg][l], nwk = d->up_ptr[wg][l + 1] - w0;
@@ -437,6 +447,9 @@ void sweep(DeviceOp* d, const std::vector<IO>& io, int64_t nrhs, int dtype, hipS
             const int gy = std::max(1, (d->down_rows[l] + 4 * kern::kRB - 1) / (4 * kern::kRB));
             hipLaunchKernelGGL((kern::k_downward_mr<V, TT>), dim3(nbx, gy), dim3(256), 0, s, br, ttoff, pmap, b0, Wp,
                                Tt, Uh, U);
+        } else if (const FlatLevel& fl = d->flat[l]; fl.cnt > 0) {
+            hipLaunchKernelGGL((kern::k_down_flat<V, P::nv>), dim3(blocks_for(fl.cnt * P::nv, 256)), dim3(256), 0,
+                               s, fl.e0, fl.h0, fl.cnt, pmap, Uh, U, U);
         } else {
             const int wg = sizeof(TT) == 4 ? 1 : 0;
             const int64_t w0 = d->down_ptr[wg][l], nwk = d->down_ptr[wg][l + 1] - w0;
