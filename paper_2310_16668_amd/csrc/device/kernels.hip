@@ -1280,12 +1280,27 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(H ? 2 
 // the n_entries x Wp workspace (Wp = Win for one RHS; for several, Wp is a
 // multiple of the RHS chunk, the gather zero-fills the padding and the scatter
 // writes only the caller's columns).
+// i = r w + c (0 <= c < w) for an index below total: 32-bit division (about a
+// quarter of the instructions of a 64-bit one) whenever total fits it.
+__device__ __forceinline__ void split_index(int64_t i, int64_t total, int w, int64_t& r, int64_t& c) {
+    if (total <= 0xffffffffLL) {
+        const uint32_t u = static_cast<uint32_t>(i), uw = static_cast<uint32_t>(w);
+        const uint32_t q = u / uw;
+        r = q;
+        c = u - q * uw;
+    } else {
+        r = i / w;
+        c = i - r * w;
+    }
+}
+
 template <typename VI, typename VO>
 __global__ void k_gather_pad(const int32_t* __restrict__ dst_e, const int32_t* __restrict__ src_p, int64_t cnt,
                              int Win, int Wp, const VI* __restrict__ in, VO* __restrict__ out) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= cnt * Wp) return;
-    const int64_t r = i / Wp, c = i - r * Wp;
+    int64_t r, c;
+    split_index(i, cnt * Wp, Wp, r, c);
     out[static_cast<int64_t>(dst_e[r]) * Wp + c] =
         c < Win ? static_cast<VO>(in[static_cast<int64_t>(src_p[r]) * Win + c]) : VO(0);
 }
@@ -1317,7 +1332,8 @@ __global__ void k_scatter_pad(const int32_t* __restrict__ src_e, const int32_t* 
                               int Win, int Wp, const VI* __restrict__ in, VO* __restrict__ out) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= cnt * Win) return;
-    const int64_t r = i / Win, c = i - r * Win;
+    int64_t r, c;
+    split_index(i, cnt * Win, Win, r, c);
     out[static_cast<int64_t>(dst_p[r]) * Win + c] = static_cast<VO>(in[static_cast<int64_t>(src_e[r]) * Wp + c]);
 }
 
@@ -1596,12 +1612,15 @@ template <typename V>
 __global__ void __launch_bounds__(256) k_down_prep(const BoxRec* __restrict__ box, const int32_t* __restrict__ pmap,
                                                   int b0, int Wp, const V* __restrict__ U, V* __restrict__ Uh) {
     const BoxRec tb = box[b0 + blockIdx.x];
-    const int64_t cnt = static_cast<int64_t>(tb.k) * Wp;
     V* __restrict__ x = Uh + tb.hoff * Wp;
     const int32_t* __restrict__ pm = pmap + tb.hoff;
-    for (int64_t e = threadIdx.x; e < cnt; e += blockDim.x) {
-        const int64_t i = e / Wp, c = e - i * Wp;
-        x[e] = x[e] + U[static_cast<int64_t>(pm[i]) * Wp + c];
+    // groups of 32 threads walk the rows, each thread a column of 32 (Wp is a
+    // multiple of 32 here)
+    const int g = threadIdx.x >> 5, ng = blockDim.x >> 5, lc = threadIdx.x & 31;
+    for (int i = g; i < tb.k; i += ng) {
+        const V* __restrict__ up = U + static_cast<int64_t>(pm[i]) * Wp;
+        V* __restrict__ xr = x + static_cast<int64_t>(i) * Wp;
+        for (int c = lc; c < Wp; c += 32) xr[c] = xr[c] + up[c];
     }
 }
 
