@@ -1042,10 +1042,11 @@ constexpr int kMfmaTile = 32;   // columns of one accumulator tile
 // near_loop_mr: 0 u += G q; 1 u += G q, uh -= G qh; 2 u += G q, uh -= G q;
 // 3 u += G (q - qh).  Steps run in groups of GS: the group's loads are issued
 // together, then its kernel values and MFMAs, so one memory latency covers GS
-// steps; steps past s1 repeat the last source with a zero kernel value.  With
-// NT = 2, `two` is false when the second tile lies past the padded width (an
-// odd tile count): its loads are skipped and its MFMAs accumulate zeros that
-// are never stored.
+// steps.  The last group's steps past s1 are skipped (a wave-uniform branch;
+// their loads repeat the last source), and a step's second source past s1 gets
+// a zero kernel value, which adds exact zeros.  With NT = 2, `two` is false
+// when the second tile lies past the padded width (an odd tile count): its
+// loads are skipped and its MFMAs accumulate zeros that are never stored.
 template <class P, bool MASK, int MODE, int NT, int GS>
 __device__ __forceinline__ void mfma_steps(const Rec4<double>* __restrict__ Xs, const float* __restrict__ Qs,
                                            const float* __restrict__ Qhs, int Wp, int s0, int s1, double xt,
@@ -1077,6 +1078,7 @@ __device__ __forceinline__ void mfma_steps(const Rec4<double>* __restrict__ Xs, 
         }
 #pragma unroll
         for (int u = 0; u < GS; ++u) {
+            if (u > 0 && sg + 2 * u >= s1) break;
             float g, gi;
             green<P, false, MASK>(xt - sx[u], yt - sy[u], zt - sz[u], 0.0f, g, gi);
             g = ok[u] ? g : 0.0f;
@@ -1214,7 +1216,7 @@ __device__ __forceinline__ void mfma_segment2(int mode, const Rec4<double>* __re
 // targets lie in the box's skeleton (uhat rows); tasks are launched in two
 // lists, with and without.
 template <class P, bool H>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(H ? 2 : 1, 8))) k_near_mfma2(const Task* __restrict__ tasks, int ntasks, int npairs, int Wp,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(H ? 2 : 3, 8))) k_near_mfma2(const Task* __restrict__ tasks, int ntasks, int npairs, int Wp,
                                                     const int32_t* __restrict__ seg_ptr,
                                                     const int2* __restrict__ segs, const BoxRec* __restrict__ box,
                                                     const Rec4<double>* __restrict__ X, const float* __restrict__ Q,
@@ -1606,21 +1608,37 @@ __global__ void __launch_bounds__(256) k_upward_mfma(const int2* __restrict__ wo
 }
 
 // downward, first step of a level: x = uhat + the parent's u at the box's slots,
-// formed in place in uhat (one block per box of the level), so the level's
-// GEMMs read contiguous rows.  uhat is not read again in the sweep.
-template <typename V>
+// formed in place in uhat, so the level's GEMMs read contiguous rows.  uhat is
+// not read again in the sweep.  Block (box, y) takes float4 elements
+// [1024 y, 1024 (y + 1)) of the box's k x Wp values (Wp a multiple of 32), four
+// per thread with all loads issued before the stores; gridDim.y covers the
+// level's largest k, blocks past a smaller box's end return at once.
+constexpr int kPrepUnroll = 4;
+template <int UNROLL>
 __global__ void __launch_bounds__(256) k_down_prep(const BoxRec* __restrict__ box, const int32_t* __restrict__ pmap,
-                                                  int b0, int Wp, const V* __restrict__ U, V* __restrict__ Uh) {
+                                                  int b0, int Wp, const float* __restrict__ U,
+                                                  float* __restrict__ Uh) {
     const BoxRec tb = box[b0 + blockIdx.x];
-    V* __restrict__ x = Uh + tb.hoff * Wp;
+    const int w4 = Wp >> 2;
+    const int total = tb.k * w4;
+    float4* __restrict__ x = reinterpret_cast<float4*>(Uh + tb.hoff * Wp);
     const int32_t* __restrict__ pm = pmap + tb.hoff;
-    // groups of 32 threads walk the rows, each thread a column of 32 (Wp is a
-    // multiple of 32 here)
-    const int g = threadIdx.x >> 5, ng = blockDim.x >> 5, lc = threadIdx.x & 31;
-    for (int i = g; i < tb.k; i += ng) {
-        const V* __restrict__ up = U + static_cast<int64_t>(pm[i]) * Wp;
-        V* __restrict__ xr = x + static_cast<int64_t>(i) * Wp;
-        for (int c = lc; c < Wp; c += 32) xr[c] = xr[c] + up[c];
+    for (int e0 = blockIdx.y * (256 * UNROLL) + threadIdx.x; e0 < total; e0 += gridDim.y * (256 * UNROLL)) {
+        float4 a[UNROLL], b[UNROLL];
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+            const int e = e0 + 256 * u;
+            if (e < total) {
+                const int i = e / w4;
+                a[u] = x[e];
+                b[u] = reinterpret_cast<const float4*>(U + static_cast<int64_t>(pm[i]) * Wp)[e - i * w4];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+            const int e = e0 + 256 * u;
+            if (e < total) x[e] = make_float4(a[u].x + b[u].x, a[u].y + b[u].y, a[u].z + b[u].z, a[u].w + b[u].w);
+        }
     }
 }
 

@@ -331,7 +331,9 @@ void xfer_level_t(const DeviceOp* d, hipStream_t s, bool up, int l, int Wp, cons
                            d->pmap.as<int32_t>(), Wp, Tt, Q, Qh);
     else {
         const int b0 = d->L.level_ptr[l], nbx = d->L.level_ptr[l + 1] - b0;
-        hipLaunchKernelGGL(kern::k_down_prep<float>, dim3(nbx), dim3(256), 0, s, d->boxrec.as<kern::BoxRec>(),
+        const int64_t per_y = 256 * kern::kPrepUnroll, vals = int64_t(d->up_rows[l]) * (Wp / 4);
+        const unsigned ny = static_cast<unsigned>(std::min<int64_t>(65535, std::max<int64_t>(1, (vals + per_y - 1) / per_y)));
+        hipLaunchKernelGGL(kern::k_down_prep<kern::kPrepUnroll>, dim3(nbx, ny), dim3(256), 0, s, d->boxrec.as<kern::BoxRec>(),
                            d->pmap.as<int32_t>(), b0, Wp, U, Uh);
         SKF_HIP(hipGetLastError());
         hipLaunchKernelGGL((kern::k_downward_mfma<WPB, NT>), dim3(nb), dim3(64 * WPB), 0, s,
