@@ -337,6 +337,38 @@ def cpu_baseline(P, q, v, budget_s: float, nrhs: int = 1):
 # ---------------------------------------------------------------------------
 # legs
 # ---------------------------------------------------------------------------
+def f32_differences_leg(op, w, x, q_h, v_h, steps, warmup, fused_ms, build_s):
+    """skelfmm_apply_fwd_adj on an operator built with f32_differences: step time,
+    pair-kernel time, errors against the dense sum, items on the float32 form."""
+    import torch
+
+    import oracle
+    dev = torch.device("cuda:0")
+    op.prepare(1, torch.float32)
+    tuned = op.autotune_fwd_adj()
+    q = torch.from_numpy(q_h).to(dev, torch.float32)
+    v = torch.from_numpy(v_h).to(dev, torch.float32)
+    holder = {}
+
+    def step():
+        holder["u"], holder["w"] = op.apply_fwd_adj(q, v)
+
+    ms = timed_steps(step, steps, warmup)
+    pm = pass_times(op, step, steps)
+    tg = w.targets()
+    qr = q_h.astype(np.float32).astype(np.float64)
+    vr = v_h.astype(np.float32).astype(np.float64)
+    e = errors(holder["u"].double().cpu().numpy()[tg], oracle.direct(x, qr, targets=tg))
+    ea = errors(holder["w"].double().cpu().numpy()[tg], oracle.direct(x, vr, targets=tg))
+    st = op.stats()
+    return {"value": w.n / (ms * 1e-3), "unit": "points/s", "ms_per_step": ms, "ratio_to_headline_fused_ms": ms / fused_ms,
+            "autotune": tuned, "near_pairs_ms": pm["near_pairs"], "passes_ms_per_sweep": pm,
+            "relerr_vs_direct": e["rel_l2"], "maxrel_vs_direct": e["max_rel"],
+            "relerr_adjoint_vs_direct": ea["rel_l2"], "maxrel_adjoint_vs_direct": ea["max_rel"],
+            "sym_items": st["n_sym_tasks"], "f32diff_items": st["n_sym_f32diff"],
+            "expanded_items": st["n_sym_expanded"], "build_s": build_s}
+
+
 def many_rhs_same_operator(op, w, x, steps, warmup, f64_rate):
     """64 float32 right-hand sides on the 1M cube's operator (matrix-core near field
     and transfers): forward + adjoint points x RHS/s against the float64 single-RHS
@@ -654,6 +686,18 @@ def main():
         log("[bench] 64 float32 RHS on the same operator")
         out["many_rhs_same_operator"] = many_rhs_same_operator(op, w, x, args.steps, args.warmup, f64_rate)
         log(f"[bench] many RHS: {out['many_rhs_same_operator']}")
+    if legs and "f32_fused" in results:
+        # the same cube built with f32_differences: the pair items whose reach is at
+        # most 1024 x their smallest spacing form |d|^2 from float32 differences (an
+        # option with a looser bound per kernel value, so not a headline candidate)
+        log("[bench] fused float32 step with f32_differences")
+        t0 = time.perf_counter()
+        opf = sk.build(x, "laplace", tol=w.tol, leaf_size=w.leaf_size, f32_differences=True)
+        tb = time.perf_counter() - t0
+        out["f32_differences_fused"] = f32_differences_leg(opf, w, x, q_h, v_h, args.steps, args.warmup,
+                                                           results["f32_fused"]["ms_per_step"], tb)
+        log(f"[bench] f32 differences: {out['f32_differences_fused']}")
+        del opf
     if legs:
         we = workloads.LAPLACE3D_ELLIPSOID_4M
         log(f"[bench] building {we.name}")

@@ -103,7 +103,15 @@ typedef struct {
                                 matrices, pivoted QR, T = R11^{-1} R12) level by level on the current
                                 HIP device; the tree and neighbor lists stay on the host (default 0:
                                 all on the host).  ENOTSUP when no HIP device is present */
-    int32_t reserved[4];
+    int32_t f32_differences; /* F32 applies with one right-hand side: symmetric pair items whose reach R
+                                from the source box's first entry is at most 1024 times their
+                                smallest point spacing d form |d|^2 from float32 coordinate
+                                differences about that entry (one kernel value's relative error is
+                                then at most about (R / |t - s| + 1) 2^-24: up to 6e-5 for the
+                                closest pair an item may hold, a few float32 units for most pairs;
+                                see skelfmm_stats.n_sym_f32diff).  Default 0: float64 differences
+                                or the float64 expanded form */
+    int32_t reserved[3];
 } skelfmm_options;
 
 /* Build-time and layout statistics (section 5 / table "Notation for reported results"). */
@@ -126,7 +134,7 @@ typedef struct {
     int64_t pairs_tile_skel;         /* skeleton pairs inside them */
     int32_t n_sym_expanded;          /* pair items whose float32 evaluation expands |d|^2 about an
                                         origin (the build's distance bound allows it) */
-    int32_t reserved[1];
+    int32_t n_sym_f32diff;           /* pair items evaluated from float32 differences (f32_differences) */
     double t_skel_qr;                /* seconds of t_skel spent in the interpolative decompositions
                                         themselves (proxy matrices, pivoted QR, T; on the device with
                                         gpu_build, copies included) */

@@ -49,7 +49,7 @@ class Options(ctypes.Structure):
                 ("num_threads", ctypes.c_int32), ("keep_transparent", ctypes.c_int32),
                 ("f64_leaf", ctypes.c_int32), ("nonsymmetric", ctypes.c_int32), ("no_expansion", ctypes.c_int32),
                 ("compensated_leaf", ctypes.c_int32), ("gpu_build", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("f32_differences", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class Stats(ctypes.Structure):
@@ -61,7 +61,7 @@ class Stats(ctypes.Structure):
                 ("tile_targets", ctypes.c_int32), ("n_sym_tasks", ctypes.c_int32), ("pairs_sym", ctypes.c_int64),
                 ("pairs_sym_skel", ctypes.c_int64), ("pairs_tile", ctypes.c_int64),
                 ("pairs_tile_skel", ctypes.c_int64), ("n_sym_expanded", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 1), ("t_skel_qr", ctypes.c_double), ("t_layout", ctypes.c_double)]
+                ("n_sym_f32diff", ctypes.c_int32), ("t_skel_qr", ctypes.c_double), ("t_layout", ctypes.c_double)]
 
 
 _P = ctypes.POINTER
@@ -324,7 +324,7 @@ def build(points, kind: str = "laplace", tol: float = 1e-6, leaf_size: int = 64,
           proxy_shape: int = 0, proxy_points: int = 0, proxy_scale: float = 0.0, no_compression: bool = False,
           num_threads: int = 0, keep_transparent: bool = False, f64_leaf: bool = False,
           symmetric: bool = True, expansion: bool = True, compensated_leaf: bool = False,
-          gpu_build: bool = False) -> Operator:
+          gpu_build: bool = False, f32_differences: bool = False) -> Operator:
     """Build the skeleton operator for ``points`` (n x dim, host, float64).
 
     ``symmetric=False`` evaluates both orders of every colleague pair separately
@@ -332,7 +332,10 @@ def build(points, kind: str = "laplace", tol: float = 1e-6, leaf_size: int = 64,
     ``expansion=False`` keeps the float32 pair kernel on coordinate differences;
     ``compensated_leaf=True`` keeps its float32 partial sums to four products and
     forms its column sums in float64; ``gpu_build=True`` computes the
-    interpolative decompositions on the current HIP device."""
+    interpolative decompositions on the current HIP device;
+    ``f32_differences=True`` lets the float32 pair kernel form |d|^2 from float32
+    coordinate differences in items whose reach is at most 1024 times their
+    smallest point spacing."""
     pts = np.ascontiguousarray(points, dtype=np.float64)
     if pts.ndim != 2:
         raise ValueError("points must be n x dim")
@@ -346,6 +349,7 @@ def build(points, kind: str = "laplace", tol: float = 1e-6, leaf_size: int = 64,
     o.no_expansion = int(not expansion)
     o.compensated_leaf = int(compensated_leaf)
     o.gpu_build = int(gpu_build)
+    o.f32_differences = int(f32_differences)
     h = _vp()
     _check(_lib.skelfmm_build(pts.ctypes.data_as(_P(ctypes.c_double)), n, k, tol, leaf_size,
                               ctypes.byref(o), ctypes.byref(h)))

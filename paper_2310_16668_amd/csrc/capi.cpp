@@ -118,7 +118,7 @@ skelfmm_status skelfmm_build(const double* points, int64_t n, skelfmm_kernel ker
             const auto tl0 = std::chrono::steady_clock::now();
             op->dev = skelfmm::device_create(p, op->opt.keep_transparent != 0, op->opt.f64_leaf != 0,
                                              op->opt.nonsymmetric == 0, op->opt.no_expansion == 0,
-                                             op->opt.compensated_leaf != 0);
+                                             op->opt.f32_differences != 0, op->opt.compensated_leaf != 0);
             p.t_layout = std::chrono::duration<double>(std::chrono::steady_clock::now() - tl0).count();
         } catch (...) {
             delete op;

@@ -37,12 +37,15 @@ struct Task {
 struct SymTask {
     int32_t bi, bj;   // target-side box (lanes) and source-side box (wave-uniform)
     int32_t t0, t1;   // target entries [t0, t1) of bi
-    int32_t flags;    // SYM_EXPANDED: |d|^2 may be expanded about the source box's origin
+    int32_t flags;    // SymFlags: how the float32 evaluation may form |d|^2
     int32_t pad;
     int64_t fwd_u, fwd_h, rev_u, rev_h;
 };
-enum SymFlags : int32_t { SYM_EXPANDED = 1 };
-// The pair kernel's expanded source records: box b's records start at
+// SYM_EXPANDED: |d|^2 may be expanded about the source box's origin (float64
+// terms); SYM_F32DIFF: |d|^2 may come from float32 differences about it.
+enum SymFlags : int32_t { SYM_EXPANDED = 1, SYM_F32DIFF = 2 };
+// The pair kernel's expanded source records (and its float32 relative
+// coordinates, laid out alike): box b's records start at
 // voff[b] + kSymRecordPad * b and are followed by kSymRecordPad copies of its
 // last record, so a block of up to kSymRecordPad + 1 sources is read without
 // clamping its indices (the copies take zero charges).
@@ -93,6 +96,7 @@ struct Layout {
     // removed from the *_ns segment lists, which serve the one-RHS near field
     bool sym = false;
     bool allow_expanded = true;     // pair items may use the expanded |d|^2 where the bound allows
+    bool allow_f32diff = false;     // pair items may use float32 differences where the bound allows
     std::vector<int32_t> seg_ptr_ns, seg_src_ns, seg_mode_ns;
     std::vector<SymTask> sym_tasks;
     std::vector<SymRows> sym_rows;               // boxes receiving slot rows
@@ -124,7 +128,7 @@ Layout merge_layouts(const std::vector<const Layout*>& ls, std::vector<int64_t>&
 struct DeviceOp;
 struct DeviceBatch;
 
-DeviceOp* device_create(const Plan& p, bool keep_transparent, bool f64_leaf, bool symmetric, bool expanded,
+DeviceOp* device_create(const Plan& p, bool keep_transparent, bool f64_leaf, bool symmetric, bool expanded, bool f32diff,
                         bool compensated);
 void device_prepare(DeviceOp* d, int64_t nrhs_max, int dtype);
 void device_apply(DeviceOp* d, const void* q, void* u, int64_t nrhs, int dtype, void* stream, bool adjoint);

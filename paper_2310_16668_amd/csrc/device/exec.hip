@@ -43,11 +43,12 @@ static void check_ranks(const Layout& L) {
 // for every tpl in 1 .. 4).
 constexpr int kSymGroup = 768;
 
-DeviceOp* device_create(const Plan& p, bool keep_transparent, bool f64_leaf, bool symmetric, bool expanded,
+DeviceOp* device_create(const Plan& p, bool keep_transparent, bool f64_leaf, bool symmetric, bool expanded, bool f32diff,
                         bool compensated) {
     auto d = std::make_unique<DeviceOp>();
     d->L = make_layout(p, keep_transparent, 64 * kDefaultTPL);
     d->L.allow_expanded = expanded;
+    d->L.allow_f32diff = f32diff;
     // the pairing needs G(x, y) = G(y, x): the real Laplace kernels, and the
     // complex-symmetric Helmholtz kernels (distinct boxes only)
     if (symmetric) make_symmetric(d->L, kSymGroup, p.kind == 0);
@@ -183,6 +184,24 @@ static std::vector<double> expanded_records(const Layout& L, const std::vector<i
     return E;
 }
 
+// The float32 coordinates of every entry relative to its box's first entry
+// (laid out and padded like the expanded records).
+static std::vector<float> relative_records(const Layout& L, const std::vector<int64_t>& roff) {
+    const size_t total = static_cast<size_t>(L.n_entries) + static_cast<size_t>(kSymRecordPad) * L.n_boxes;
+    std::vector<float> F(total * 4, 0.0f);
+    for (int b = 0; b < L.n_boxes; ++b) {
+        if (L.nb[b] == 0) continue;
+        const double* o = &L.X[static_cast<size_t>(L.voff[b]) * 4];
+        for (int64_t e = 0; e < L.nb[b] + kSymRecordPad; ++e) {
+            const int64_t src = std::min<int64_t>(e, L.nb[b] - 1);
+            const double* x = &L.X[static_cast<size_t>(L.voff[b] + src) * 4];
+            float* r = &F[static_cast<size_t>(roff[b] + e) * 4];
+            for (int c = 0; c < 3; ++c) r[c] = static_cast<float>(x[c] - o[c]);
+        }
+    }
+    return F;
+}
+
 static void upload(DeviceOp* d, int dtype) {
     const Layout& L = d->L;
     if (!d->uploaded) {
@@ -236,6 +255,7 @@ static void upload(DeviceOp* d, int dtype) {
         d->boxrec.upload(br);
         d->X64.upload(L.X);   // coordinates are float64 in every precision policy
         d->XE64.upload(expanded_records(L, roff));
+        if (L.allow_f32diff) d->XF32.upload(relative_records(L, roff));
         build_transfer_work(d);
         d->uploaded = true;
     }
@@ -485,7 +505,11 @@ void device_fill_stats(const DeviceOp* d, skelfmm_stats* out) {
     out->pairs_tile = pc[2];
     out->pairs_tile_skel = pc[3];
     out->n_sym_expanded = 0;
-    for (const SymTask& st : d->L.sym_tasks) out->n_sym_expanded += (st.flags & SYM_EXPANDED) ? 1 : 0;
+    out->n_sym_f32diff = 0;
+    for (const SymTask& st : d->L.sym_tasks) {
+        out->n_sym_expanded += (st.flags & SYM_EXPANDED) ? 1 : 0;
+        out->n_sym_f32diff += (st.flags & SYM_F32DIFF) ? 1 : 0;
+    }
 }
 
 void device_destroy(DeviceOp* d) { delete d; }
@@ -527,9 +551,11 @@ DeviceBatch* batch_create(const std::vector<DeviceOp*>& ops) {
     b->merged = std::make_unique<DeviceOp>();
     b->merged->L = merge_layouts(ls, ebase);
     for (auto* o : ops)
-        if (o->L.sym != ops[0]->L.sym || o->L.allow_expanded != ops[0]->L.allow_expanded)
+        if (o->L.sym != ops[0]->L.sym || o->L.allow_expanded != ops[0]->L.allow_expanded ||
+            o->L.allow_f32diff != ops[0]->L.allow_f32diff)
             throw std::invalid_argument("batched operators must share the pairing options");
     b->merged->L.allow_expanded = ops[0]->L.allow_expanded;
+    b->merged->L.allow_f32diff = ops[0]->L.allow_f32diff;
     if (ops[0]->L.sym) make_symmetric(b->merged->L, kSymGroup, b->merged->L.kind == 0);
     b->merged->f64_leaf = ops[0]->f64_leaf;
     for (auto* o : ops)

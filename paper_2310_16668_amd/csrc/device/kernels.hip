@@ -32,6 +32,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "../hankel.h"
 #include "device.h"
@@ -614,7 +615,13 @@ __device__ __forceinline__ double column_sum_f64(const B (&r)[kSymBlock], B* til
 // an SGPR operand, so a pair costs no LDS traffic and no staging barrier.
 // Exact form: the record is the source's coordinates.  Expanded form (see
 // sym_pass): the record is (-2 (x_s - o), |x_s - o|^2) for the origin o of the
-// source box, precomputed once per operator.
+// source box, precomputed once per operator.  Float32 differences: the record
+// is x_s - o in float32, and the targets hold t - o in float32.
+// FM (form of |d|^2): 0 float64 differences, 1 expanded, 2 float32 differences.
+template <int FM>
+using SrcRec = typename std::conditional<FM == 2, Rec4<float>, Rec4<double>>::type;
+template <int FM>
+using CoordT = typename std::conditional<FM == 2, float, double>::type;
 
 // One block of up to kSymBlock sources s0 .. s0 + cnt - 1 of box j (records
 // Xs, charges Qs and Qhs, indexed from the box's first entry).  H: the pass
@@ -624,11 +631,11 @@ __device__ __forceinline__ double column_sum_f64(const B (&r)[kSymBlock], B* til
 // reverse sums are not stored), so the block is branch-free.  Reverse sums go
 // to rev_u[s] (and rev_h[s]), stored on the item's first pass and accumulated
 // on later ones.
-template <class P, int TPL, bool H, bool MASK, bool FAST>
-__device__ __forceinline__ void sym_block(const Rec4<double>* __restrict__ Xs, const typename P::Vt* __restrict__ Qs,
+template <class P, int TPL, bool H, bool MASK, int FM>
+__device__ __forceinline__ void sym_block(const SrcRec<FM>* __restrict__ Xs, const typename P::Vt* __restrict__ Qs,
                                           const typename P::Vt* __restrict__ Qhs, int s0, int cnt,
-                                          const double (&xt)[TPL], const double (&yt)[TPL],
-                                          const double (&zt)[TPL], const double (&nt)[TPL],
+                                          const CoordT<FM> (&xt)[TPL], const CoordT<FM> (&yt)[TPL],
+                                          const CoordT<FM> (&zt)[TPL], const double (&nt)[TPL],
                                           const typename P::Rt (&wi)[TPL][P::nv],
                                           const typename P::Rt (&whi)[TPL][P::nv],
                                           typename P::At (&acc)[TPL][P::nv], typename P::At (&acch)[TPL][P::nv],
@@ -663,17 +670,17 @@ __device__ __forceinline__ void sym_block(const Rec4<double>* __restrict__ Xs, c
 #pragma unroll
         for (int v = 0; v < NR; ++v) { bacc[p][v] = R(0); bh[p][v] = R(0); }
     // the block's first source: constant offsets from here let the loads merge
-    const Rec4<double>* __restrict__ Xb0 = Xs + s0;
+    const SrcRec<FM>* __restrict__ Xb0 = Xs + s0;
     const typename P::Vt* __restrict__ Qb0 = Qs + static_cast<int64_t>(s0) * NR;
     const typename P::Vt* __restrict__ Qhb0 = Qhs + static_cast<int64_t>(s0) * NR;
 #pragma unroll
     for (int c = 0; c < kSymBlock; ++c) {
-        // Expanded records are padded per box (copies of its last record), so
-        // the block reads them unclamped and the loads merge; the charges past
-        // cnt are read within the arrays' spare tail and replaced by zero.
-        // Exact coordinates are read at the clamped index.
-        const int ci = FAST ? c : min(c, cnt - 1);
-        const Rec4<double> sv = Xb0[ci];
+        // Expanded and float32 records are padded per box (copies of its last
+        // record), so the block reads them unclamped and the loads merge; the
+        // charges past cnt are read within the arrays' spare tail and replaced
+        // by zero.  Exact coordinates are read at the clamped index.
+        const int ci = FM != 0 ? c : min(c, cnt - 1);
+        const SrcRec<FM> sv = Xb0[ci];
         R svw[NR], svwh[NR];
 #pragma unroll
         for (int v = 0; v < NR; ++v) {
@@ -690,10 +697,14 @@ __device__ __forceinline__ void sym_block(const Rec4<double>* __restrict__ Xs, c
 #pragma unroll
         for (int p = 0; p < TPL; ++p) {
             R g, gi;
-            if constexpr (FAST) {
+            if constexpr (FM == 1) {
                 // |t - s|^2 = |t'|^2 + |s'|^2 - 2 t'.s' relative to the source box's origin
                 const double r2 = fma(xt[p], sv.x, fma(yt[p], sv.y, fma(zt[p], sv.z, nt[p] + sv.w)));
                 green_r2<P, false, MASK>(r2, R(0), g, gi);
+            } else if constexpr (FM == 2) {
+                // t' - s' in float32, both relative to the source box's origin
+                const float dx = xt[p] - sv.x, dy = yt[p] - sv.y, dz = zt[p] - sv.z;
+                green_r2<P, false, MASK>(fmaf(dx, dx, fmaf(dy, dy, dz * dz)), R(0), g, gi);
             } else {
                 green<P, false, MASK>(xt[p] - sv.x, yt[p] - sv.y, zt[p] - sv.z, R(0), g, gi);
             }
@@ -786,11 +797,11 @@ struct SymCtx {
 
 // One pass: targets tp .. tp + 64 TPL - 1 of box i (those below t1) against all
 // sources of box j.
-template <class P, int TPL, bool SELF, bool FAST>
+template <class P, int TPL, bool SELF, int FM>
 __device__ __forceinline__ void sym_pass(const SymCtx& cx, int tp, const Rec4<double>* __restrict__ X,
                                          const typename P::Vt* __restrict__ Q,
                                          const typename P::Vt* __restrict__ Qh,
-                                         const Rec4<double>* __restrict__ Xs, const Rec4<double>* __restrict__ Xb,
+                                         const Rec4<double>* __restrict__ Xs, const SrcRec<FM>* __restrict__ Xb,
                                          const typename P::Vt* __restrict__ Qs,
                                          const typename P::Vt* __restrict__ Qhs, typename P::Rt* tile, int lane) {
     using R = typename P::Rt;
@@ -807,13 +818,15 @@ __device__ __forceinline__ void sym_pass(const SymCtx& cx, int tp, const Rec4<do
     BlockPlan bp;
     bp.init(tile_end, hp ? bj.k : 0, bj.n);
     constexpr int NR = P::nv;
-    double xt[TPL], yt[TPL], zt[TPL], nt[TPL];
+    CoordT<FM> xt[TPL], yt[TPL], zt[TPL];
+    double nt[TPL];
     R wi[TPL][NR], whi[TPL][NR];
     A acc[TPL][NR], acch[TPL][NR];
-    // expanded form: target coordinates relative to the origin of the source
-    // box (its first entry), the origin of the source records Xb
+    // expanded form and float32 differences: target coordinates relative to
+    // the origin of the source box (its first entry), the origin of the source
+    // records Xb
     double o[3] = {0.0, 0.0, 0.0};
-    if constexpr (FAST) {
+    if constexpr (FM != 0) {
         const Rec4<double> x0 = Xs[0];
         o[0] = x0.x; o[1] = x0.y; o[2] = x0.z;
     }
@@ -823,8 +836,11 @@ __device__ __forceinline__ void sym_pass(const SymCtx& cx, int tp, const Rec4<do
         const bool ok = t < cx.t1;
         const int tc = ok ? t : cx.t1 - 1;
         const Rec4<double> x = X[bi.voff + tc];
-        xt[p] = x.x - o[0]; yt[p] = x.y - o[1]; zt[p] = x.z - o[2];
-        nt[p] = fma(xt[p], xt[p], fma(yt[p], yt[p], zt[p] * zt[p]));
+        const double dx = x.x - o[0], dy = x.y - o[1], dz = x.z - o[2];
+        xt[p] = static_cast<CoordT<FM>>(dx);
+        yt[p] = static_cast<CoordT<FM>>(dy);
+        zt[p] = static_cast<CoordT<FM>>(dz);
+        nt[p] = FM == 1 ? fma(dx, dx, fma(dy, dy, dz * dz)) : 0.0;
 #pragma unroll
         for (int v = 0; v < NR; ++v) {
             wi[p][v] = ok ? static_cast<R>(Q[(bi.voff + tc) * NR + v]) : R(0);
@@ -856,10 +872,10 @@ __device__ __forceinline__ void sym_pass(const SymCtx& cx, int tp, const Rec4<do
         int s0, cnt;
         bp.range(b, s0, cnt);
         if (b < bp.nbH)
-            sym_block<P, TPL, true, SELF, FAST>(Xb, Qs, Qhs, s0, cnt, xt, yt, zt, nt, wi, whi, acc, acch, tile, lane,
+            sym_block<P, TPL, true, SELF, FM>(Xb, Qs, Qhs, s0, cnt, xt, yt, zt, nt, wi, whi, acc, acch, tile, lane,
                                                 cx.rev_u, cx.rev_h, first, cx.sc);
         else
-            sym_block<P, TPL, false, SELF, FAST>(Xb, Qs, Qhs, s0, cnt, xt, yt, zt, nt, wi, whi, acc, acch, tile, lane,
+            sym_block<P, TPL, false, SELF, FM>(Xb, Qs, Qhs, s0, cnt, xt, yt, zt, nt, wi, whi, acc, acch, tile, lane,
                                                  cx.rev_u, cx.rev_h, first, cx.sc);
     }
 #pragma unroll
@@ -886,38 +902,38 @@ __device__ __forceinline__ void sym_pass(const SymCtx& cx, int tp, const Rec4<do
 // one wave's lanes.  The pass boundaries (and with them the diagonal tiles of a
 // self item) are those of TPL-wide passes.  Every pass width is inlined at one
 // call site (two copies of a wide pass cost the float32 variants spills).
-template <class P, int TPL, bool SELF, bool FAST>
+template <class P, int TPL, bool SELF, int FM>
 __device__ __forceinline__ void sym_tail(const SymCtx& cx, int tp, const Rec4<double>* __restrict__ X,
                                          const typename P::Vt* __restrict__ Q, const typename P::Vt* __restrict__ Qh,
-                                         const Rec4<double>* __restrict__ Xs, const Rec4<double>* __restrict__ Xb,
+                                         const Rec4<double>* __restrict__ Xs, const SrcRec<FM>* __restrict__ Xb,
                                          const typename P::Vt* __restrict__ Qs,
                                          const typename P::Vt* __restrict__ Qhs, typename P::Rt* tile, int lane) {
     if constexpr (TPL == 1) {
-        sym_pass<P, 1, SELF, FAST>(cx, tp, X, Q, Qh, Xs, Xb, Qs, Qhs, tile, lane);
+        sym_pass<P, 1, SELF, FM>(cx, tp, X, Q, Qh, Xs, Xb, Qs, Qhs, tile, lane);
     } else {
         if (cx.t1 - tp > 64 * (TPL - 1))
-            sym_pass<P, TPL, SELF, FAST>(cx, tp, X, Q, Qh, Xs, Xb, Qs, Qhs, tile, lane);
+            sym_pass<P, TPL, SELF, FM>(cx, tp, X, Q, Qh, Xs, Xb, Qs, Qhs, tile, lane);
         else
-            sym_tail<P, TPL - 1, SELF, FAST>(cx, tp, X, Q, Qh, Xs, Xb, Qs, Qhs, tile, lane);
+            sym_tail<P, TPL - 1, SELF, FM>(cx, tp, X, Q, Qh, Xs, Xb, Qs, Qhs, tile, lane);
     }
 }
 
 // All passes of an item: TPL-wide while more than 64 (TPL - 1) targets are
 // left (the last of them may be ragged), else the narrower tail.
-template <class P, int TPL, bool SELF, bool FAST>
+template <class P, int TPL, bool SELF, int FM>
 __device__ __forceinline__ void sym_passes(const SymCtx& cx, const Rec4<double>* __restrict__ X,
                                            const typename P::Vt* __restrict__ Q,
                                            const typename P::Vt* __restrict__ Qh,
                                            const Rec4<double>* __restrict__ Xs,
-                                           const Rec4<double>* __restrict__ Xb,
+                                           const SrcRec<FM>* __restrict__ Xb,
                                            const typename P::Vt* __restrict__ Qs,
                                            const typename P::Vt* __restrict__ Qhs, typename P::Rt* tile, int lane) {
     for (int tp = cx.t0; tp < cx.t1;) {
         if (cx.t1 - tp > 64 * (TPL - 1)) {
-            sym_pass<P, TPL, SELF, FAST>(cx, tp, X, Q, Qh, Xs, Xb, Qs, Qhs, tile, lane);
+            sym_pass<P, TPL, SELF, FM>(cx, tp, X, Q, Qh, Xs, Xb, Qs, Qhs, tile, lane);
             tp += 64 * TPL;
         } else {
-            if constexpr (TPL > 1) sym_tail<P, TPL - 1, SELF, FAST>(cx, tp, X, Q, Qh, Xs, Xb, Qs, Qhs, tile, lane);
+            if constexpr (TPL > 1) sym_tail<P, TPL - 1, SELF, FM>(cx, tp, X, Q, Qh, Xs, Xb, Qs, Qhs, tile, lane);
             break;
         }
     }
@@ -930,7 +946,7 @@ __device__ __forceinline__ void sym_passes(const SymCtx& cx, const Rec4<double>*
 template <class P, int TPL>
 __device__ __forceinline__ void sym_item(const SymTask it, const BoxRec* __restrict__ box,
                                          const Rec4<double>* __restrict__ X, const Rec4<double>* __restrict__ Xe,
-                                         const typename P::Vt* __restrict__ Q,
+                                         const Rec4<float>* __restrict__ Xf, const typename P::Vt* __restrict__ Q,
                                          const typename P::Vt* __restrict__ Qh, double* __restrict__ slots,
                                          double scale, typename P::Rt* tile, int lane) {
     using V = typename P::Vt;
@@ -950,13 +966,22 @@ __device__ __forceinline__ void sym_item(const SymTask it, const BoxRec* __restr
     const Rec4<double>* Xs = X + cx.bj.voff;
     const V* Qs = Q + cx.bj.voff * NR;
     const V* Qhs = Qh + cx.bj.hoff * NR;
-    // the expanded |d|^2 serves the float32 evaluation of items the build marked safe for it
-    if (sizeof(typename P::Rt) == 4 && (it.flags & SYM_EXPANDED))
-        sym_passes<P, TPL, false, true>(cx, X, Q, Qh, Xs, Xe + cx.bj.roff, Qs, Qhs, tile, lane);
-    else if (it.bi != it.bj)
-        sym_passes<P, TPL, false, false>(cx, X, Q, Qh, Xs, Xs, Qs, Qhs, tile, lane);
+    // float32 differences or the expanded |d|^2 serve the float32 evaluation of
+    // items the build marked safe for them
+    if constexpr (sizeof(typename P::Rt) == 4) {
+        if (it.flags & SYM_F32DIFF) {
+            sym_passes<P, TPL, false, 2>(cx, X, Q, Qh, Xs, Xf + cx.bj.roff, Qs, Qhs, tile, lane);
+            return;
+        }
+        if (it.flags & SYM_EXPANDED) {
+            sym_passes<P, TPL, false, 1>(cx, X, Q, Qh, Xs, Xe + cx.bj.roff, Qs, Qhs, tile, lane);
+            return;
+        }
+    }
+    if (it.bi != it.bj)
+        sym_passes<P, TPL, false, 0>(cx, X, Q, Qh, Xs, Xs, Qs, Qhs, tile, lane);
     else
-        sym_passes<P, TPL, true, false>(cx, X, Q, Qh, Xs, Xs, Qs, Qhs, tile, lane);
+        sym_passes<P, TPL, true, 0>(cx, X, Q, Qh, Xs, Xs, Qs, Qhs, tile, lane);
 }
 
 // Waves per SIMD the pair kernel is compiled for: the float32 evaluation fits
@@ -973,6 +998,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sym_wa
                                                   const BoxRec* __restrict__ box,
                                                   const Rec4<double>* __restrict__ X,
                                                   const Rec4<double>* __restrict__ Xe,
+                                                  const Rec4<float>* __restrict__ Xf,
                                                   const typename P::Vt* __restrict__ Q,
                                                   const typename P::Vt* __restrict__ Qh,
                                                   double* __restrict__ slots, double scale) {
@@ -982,7 +1008,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sym_wa
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int tid = blockIdx.x * 4 + wv;
     if (tid >= ntasks) return;
-    sym_item<P, TPL>(tasks[tid], box, X, Xe, Q, Qh, slots, scale, tiles[wv], lane);
+    sym_item<P, TPL>(tasks[tid], box, X, Xe, Xf, Q, Qh, slots, scale, tiles[wv], lane);
 }
 
 // acc + p[0] + p[ld] + ... + p[(rows - 1) ld], added in row order; the loads of

@@ -103,13 +103,13 @@ static void box_geometry(const Plan& p, Layout& L) {
     }
 }
 
-// An item of boxes i != j may use the expanded |d|^2 (origin: the first entry
-// of the source box j).  Its terms reach about R^2 for the reach R of the two
-// boxes from the origin, so its rounding error relative to |d|^2 >= d^2 (d
-// their smallest spacing) is a few units of 2^-53 (R/d)^2: with R <= 4096 d
-// at most about 2^-26, a quarter of the float32 rounding of the kernel value.
-static bool expanded_ok(const Layout& L, int bi, int bj) {
-    if (L.nb[bj] == 0 || L.dmin.empty()) return false;
+// R / d for an item of boxes i != j: R the reach of the two boxes from the
+// origin (the first entry of the source box j), d their smallest point spacing.
+// The expanded |d|^2 has terms of about R^2, so its rounding error relative to
+// |d|^2 >= d^2 is a few units of 2^-53 (R/d)^2: with R <= 4096 d at most about
+// 2^-26, a quarter of the float32 rounding of the kernel value.
+static double reach_ratio(const Layout& L, int bi, int bj) {
+    if (L.nb[bj] == 0 || L.dmin.empty()) return std::numeric_limits<double>::infinity();
     // the expanded records of box j are relative to its first entry
     const double* o = &L.X[static_cast<size_t>(L.voff[bj]) * 4];
     auto reach = [&](int b) {
@@ -122,7 +122,20 @@ static bool expanded_ok(const Layout& L, int bi, int bj) {
     };
     const double R = std::max(reach(bi), reach(bj));
     const double d = std::min(L.dmin[bi], L.dmin[bj]);
-    return d > 0.0 && R <= 4096.0 * d;
+    return d > 0.0 ? R / d : std::numeric_limits<double>::infinity();
+}
+
+// The float32 evaluation of an item of boxes i != j: float32 differences of
+// coordinates relative to the source box's first entry where R <= 1024 d (each
+// coordinate rounded once, so |d| is off by at most about R 2^-24 and a kernel
+// value by (R / |d| + 1) 2^-24 relative), else the expanded form where
+// R <= 4096 d, else float64 differences.
+static int32_t sym_flags(const Layout& L, int bi, int bj) {
+    if (!L.allow_expanded && !L.allow_f32diff) return 0;
+    const double q = reach_ratio(L, bi, bj);
+    if (L.allow_f32diff && q <= 1024.0) return SYM_F32DIFF;
+    if (L.allow_expanded && q <= 4096.0) return SYM_EXPANDED;
+    return 0;
 }
 
 Layout make_layout(const Plan& p, bool keep_transparent, int tile) {
@@ -370,7 +383,7 @@ void make_symmetric(Layout& L, int group, bool self_items) {
         const int64_t row_h = ki > 0 ? base_h[bi] + int64_t(nh[bi]++) * ki : -1;
         for (int t0 = 0; t0 < ni; t0 += group) {
             const int t1 = std::min(ni, t0 + group);
-            SymTask st{bi, bj, t0, t1, (L.allow_expanded && expanded_ok(L, bi, bj)) ? SYM_EXPANDED : 0, 0, row_u + t0, -1,
+            SymTask st{bi, bj, t0, t1, sym_flags(L, bi, bj), 0, row_u + t0, -1,
                        base_u[bj] + int64_t(nu[bj]++) * nj, -1};
             if (t0 < ki) st.fwd_h = row_h + t0;
             if (t0 < ki && kj > 0) st.rev_h = base_h[bj] + int64_t(nh[bj]++) * kj;

@@ -112,6 +112,7 @@ struct DeviceOp {
     DevMem voff, hoff, toff, ttoff, nb, kb, pmap, gather_e, gather_p;
     DevMem X64, T64, T32, Tt64, Tt32;             // T and its per-box transposes, columns padded
     DevMem XE64;                                  // expanded source records of the pair kernel
+    DevMem XF32;                                  // float32 relative coordinates (f32_differences)
     DevMem seg_ptr, segs, boxrec;
     // one-RHS transfer work: (box, first row) items per level, and waves per item
     // [0]: float64 T row groups, [1]: float32, [2] / [3]: 64- / 128-row blocks of
@@ -219,11 +220,13 @@ void launch_near_t(const DeviceOp* d, hipStream_t s, void* Q, void* Qh, void* U,
                 hipLaunchKernelGGL((kern::k_near_sym<kern::WithComp<P>, TPL>), dim3(blocks_for(d->nsym, 4)),
                                    dim3(256), 0, s, d->symtasks.as<SymTask>(), d->nsym, d->boxrec.as<kern::BoxRec>(),
                                    d->X64.as<kern::Rec4<double>>(), d->XE64.as<kern::Rec4<double>>(),
+                                   d->XF32.as<kern::Rec4<float>>(),
                                    static_cast<const V*>(Q), static_cast<const V*>(Qh), slots, kern::kscale<P>());
             else
                 hipLaunchKernelGGL((kern::k_near_sym<P, TPL>), dim3(blocks_for(d->nsym, 4)), dim3(256), 0, s,
                                    d->symtasks.as<SymTask>(), d->nsym, d->boxrec.as<kern::BoxRec>(),
                                    d->X64.as<kern::Rec4<double>>(), d->XE64.as<kern::Rec4<double>>(),
+                                   d->XF32.as<kern::Rec4<float>>(),
                                    static_cast<const V*>(Q), static_cast<const V*>(Qh), slots, kern::kscale<P>());
             SKF_HIP(hipGetLastError());
         }

@@ -128,3 +128,23 @@ def test_batch_rejects_mixed_kernels():
     with pytest.raises(sk.SkelfmmError) as e:
         sk.Batch([a, b])
     assert e.value.status == -1
+
+
+def test_f32_differences_gate_is_the_tighter_reach_bound():
+    """An item takes float32 differences only where its reach is at most 1024 x its
+    smallest spacing, a subset of the items whose reach allows the expanded form
+    (4096 x): with the option, expanded + float32-difference items equal the
+    expanded items without it.  Batches must agree on the option."""
+    x = np.random.default_rng(5).random((20000, 3))
+    a = sk.build(x, "laplace", tol=1e-7, leaf_size=64)
+    b = sk.build(x, "laplace", tol=1e-7, leaf_size=64, f32_differences=True)
+    sa, sb = a.stats(), b.stats()
+    assert sa["n_sym_f32diff"] == 0
+    assert 0 < sb["n_sym_f32diff"] <= sa["n_sym_expanded"]
+    assert sb["n_sym_f32diff"] + sb["n_sym_expanded"] == sa["n_sym_expanded"]
+    assert sb["n_sym_tasks"] == sa["n_sym_tasks"]
+    c = sk.build(x, "laplace", tol=1e-7, leaf_size=64, expansion=False, f32_differences=True)
+    assert c.stats()["n_sym_expanded"] == 0 and c.stats()["n_sym_f32diff"] == sb["n_sym_f32diff"]
+    with pytest.raises(sk.SkelfmmError) as e:
+        sk.Batch([a, b])
+    assert e.value.status == -1 and b"pairing options" in sk._lib.skelfmm_last_error()

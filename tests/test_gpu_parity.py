@@ -468,3 +468,42 @@ def test_fused_forward_adjoint(name):
         # each column runs the separate apply's arithmetic in the same order
         assert np.array_equal(u, u1.astype(up)) and np.array_equal(w, w1.astype(up))
         assert e_u <= F32_VS_O2 and e_w <= F32_VS_O2
+
+
+@pytest.mark.parametrize("name", ["lap3d_uniform_64k", "lap2d_16k", "lap3d_ellipsoid_60k"])
+def test_f32_differences(name):
+    """f32_differences: pair items whose reach is at most 1024 x their smallest
+    spacing form |d|^2 from float32 coordinate differences about the source box's
+    first entry.  Every targets-per-lane variant, forward and adjoint, against O2
+    on the rounded charges (F32_VS_O2) and O1 (10 tol + F32_VS_O2); the fused
+    forward + adjoint equals the separate applies bit for bit."""
+    _say("case", name)
+    x, op, P = _op(name, f32_differences=True)
+    _, op_e, _ = _op(name)
+    st = op.stats()
+    record(f"{name} f32 differences layout", items=st["n_sym_tasks"], f32diff_items=st["n_sym_f32diff"],
+           expanded_items=st["n_sym_expanded"])
+    assert st["n_sym_f32diff"] > 0
+    assert op_e.stats()["n_sym_f32diff"] == 0
+    tol = CASES[name][3]
+    q = _charges(name, x.shape[0], 31)
+    v = _charges(name, x.shape[0], 32)
+    qr = q.astype(np.float32).astype(np.float64)
+    vr = v.astype(np.float32).astype(np.float64)
+    u2, w2 = oracle.apply(P, qr), oracle.apply(P, vr, adjoint=True)
+    tg = np.random.default_rng(33).choice(x.shape[0], size=512, replace=False)
+    u1 = oracle.direct(x, qr, targets=tg)
+    qd, vd = dev(q, torch.float32), dev(v, torch.float32)
+    for t in (1, 2, 3, 4):
+        op.set_targets_per_lane(t)
+        op_e.set_targets_per_lane(t)
+        u = host(op.apply(qd)).astype(np.float64)
+        w = host(op.apply_adjoint(vd)).astype(np.float64)
+        ue = host(op_e.apply(qd)).astype(np.float64)
+        e2, ew, e1 = relerr(u, u2), relerr(w, w2), relerr(u[tg], u1)
+        record(f"{name} f32 differences tpl{t}", vs_o2=e2, adjoint_vs_o2t=ew, vs_o1=e1,
+               default_vs_o2=relerr(ue, u2), default_vs_o1=relerr(ue[tg], u1))
+        assert e2 <= F32_VS_O2 and ew <= F32_VS_O2
+        assert e1 <= 10 * tol + F32_VS_O2
+        uf, wf = op.apply_fwd_adj(qd, vd)
+        assert np.array_equal(host(uf).astype(np.float64), u) and np.array_equal(host(wf).astype(np.float64), w)
