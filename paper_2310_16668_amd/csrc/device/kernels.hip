@@ -942,8 +942,10 @@ __device__ __forceinline__ void sym_passes(const SymCtx& cx, const Rec4<double>*
 // A pair item: its passes (sym_passes).
 // A box paired with itself (bi == bj, one item over all its targets) evaluates
 // each unordered pair of distinct entries once, except inside the diagonal
-// tiles, which run in one direction with the zero distances masked.
-template <class P, int TPL>
+// tiles, which run in one direction with the zero distances masked.  F32D:
+// the operator was built with f32_differences (a kernel of its own, so the
+// default kernel carries no registers for the float32-difference form).
+template <class P, int TPL, bool F32D>
 __device__ __forceinline__ void sym_item(const SymTask it, const BoxRec* __restrict__ box,
                                          const Rec4<double>* __restrict__ X, const Rec4<double>* __restrict__ Xe,
                                          const Rec4<float>* __restrict__ Xf, const typename P::Vt* __restrict__ Q,
@@ -969,7 +971,7 @@ __device__ __forceinline__ void sym_item(const SymTask it, const BoxRec* __restr
     // float32 differences or the expanded |d|^2 serve the float32 evaluation of
     // items the build marked safe for them
     if constexpr (sizeof(typename P::Rt) == 4) {
-        if (it.flags & SYM_F32DIFF) {
+        if (F32D && (it.flags & SYM_F32DIFF)) {
             sym_passes<P, TPL, false, 2>(cx, X, Q, Qh, Xs, Xf + cx.bj.roff, Qs, Qhs, tile, lane);
             return;
         }
@@ -993,7 +995,7 @@ constexpr int sym_waves() {
     return TPL == 1 ? 6 : (TPL == 2 ? 5 : (TPL == 3 ? 4 : 1));
 }
 
-template <class P, int TPL>
+template <class P, int TPL, bool F32D = false>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sym_waves<P, TPL>(), 8))) k_near_sym(const SymTask* __restrict__ tasks, int ntasks,
                                                   const BoxRec* __restrict__ box,
                                                   const Rec4<double>* __restrict__ X,
@@ -1008,7 +1010,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sym_wa
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int tid = blockIdx.x * 4 + wv;
     if (tid >= ntasks) return;
-    sym_item<P, TPL>(tasks[tid], box, X, Xe, Xf, Q, Qh, slots, scale, tiles[wv], lane);
+    sym_item<P, TPL, F32D>(tasks[tid], box, X, Xe, Xf, Q, Qh, slots, scale, tiles[wv], lane);
 }
 
 // acc + p[0] + p[ld] + ... + p[(rows - 1) ld], added in row order; the loads of

@@ -215,19 +215,26 @@ void launch_near_t(const DeviceOp* d, hipStream_t s, void* Q, void* Qh, void* U,
     if (pm) pm->mark(3);
     if constexpr (P::kind == 0) {
         if (sym && d->nsym > 0) {
-            // the compensated leaf sums only change the float32 evaluation
-            if (sizeof(R) == 4 && d->compensated)
-                hipLaunchKernelGGL((kern::k_near_sym<kern::WithComp<P>, TPL>), dim3(blocks_for(d->nsym, 4)),
-                                   dim3(256), 0, s, d->symtasks.as<SymTask>(), d->nsym, d->boxrec.as<kern::BoxRec>(),
-                                   d->X64.as<kern::Rec4<double>>(), d->XE64.as<kern::Rec4<double>>(),
-                                   d->XF32.as<kern::Rec4<float>>(),
+            const auto launch = [&](auto kern_fn) {
+                hipLaunchKernelGGL(kern_fn, dim3(blocks_for(d->nsym, 4)), dim3(256), 0, s, d->symtasks.as<SymTask>(),
+                                   d->nsym, d->boxrec.as<kern::BoxRec>(), d->X64.as<kern::Rec4<double>>(),
+                                   d->XE64.as<kern::Rec4<double>>(), d->XF32.as<kern::Rec4<float>>(),
                                    static_cast<const V*>(Q), static_cast<const V*>(Qh), slots, kern::kscale<P>());
-            else
-                hipLaunchKernelGGL((kern::k_near_sym<P, TPL>), dim3(blocks_for(d->nsym, 4)), dim3(256), 0, s,
-                                   d->symtasks.as<SymTask>(), d->nsym, d->boxrec.as<kern::BoxRec>(),
-                                   d->X64.as<kern::Rec4<double>>(), d->XE64.as<kern::Rec4<double>>(),
-                                   d->XF32.as<kern::Rec4<float>>(),
-                                   static_cast<const V*>(Q), static_cast<const V*>(Qh), slots, kern::kscale<P>());
+            };
+            // the compensated leaf sums and the float32 differences only change the
+            // float32 evaluation
+            if constexpr (sizeof(R) == 4) {
+                const bool f32d = d->L.allow_f32diff;
+                if (d->compensated) {
+                    if (f32d) launch(kern::k_near_sym<kern::WithComp<P>, TPL, true>);
+                    else launch(kern::k_near_sym<kern::WithComp<P>, TPL, false>);
+                } else {
+                    if (f32d) launch(kern::k_near_sym<P, TPL, true>);
+                    else launch(kern::k_near_sym<P, TPL, false>);
+                }
+            } else {
+                launch(kern::k_near_sym<P, TPL, false>);
+            }
             SKF_HIP(hipGetLastError());
         }
     }
