@@ -7,7 +7,8 @@
 //      equivalent to the concatenation [M; conj M] of equation (5), so T is real),
 //   2. runs column-pivoted Householder QR on each of them, one block per box
 //      and one thread per column, so every step streams the trailing rows with
-//      coalesced loads; it stops at the first pivot with |R_jj| <= tol |R_11|
+//      coalesced loads, in panels whose reflectors reach the trailing columns
+//      once per panel; it stops at the first pivot with |R_jj| <= tol |R_11|
 //      (pivot: largest remaining column norm, lowest index on ties; norms
 //      downdated and recomputed when cancellation looms, as the host build does),
 //   3. solves T = R11^{-1} R12 by back substitution, one thread per column,
@@ -19,11 +20,13 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <numeric>
 #include <string>
 #include <vector>
 
 #include "../hankel.h"
+#include "../host/parallel.h"
 #include "../host/skel.h"
 #include "device.h"
 
@@ -85,28 +88,75 @@ __global__ void __launch_bounds__(256) k_proxy_matrix(const double* __restrict__
     }
 }
 
+// Sums over the block of cnt <= B per-thread values p[0 .. cnt): every
+// thread receives them in out[0 .. cnt) (LDS).  wpart holds B x 16 doubles.
+template <int B>
+__device__ __forceinline__ void block_sums(const double (&p)[B], int cnt, double* wpart, double* out) {
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+    for (int l = 0; l < B; ++l) {
+        if (l >= cnt) break;
+        double v = p[l];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        if (lane == 0) wpart[l * 16 + wv] = v;
+    }
+    __syncthreads();
+    if (tid < cnt) {
+        double v = 0.0;
+        for (int w = 0; w < nw; ++w) v += wpart[tid * 16 + w];
+        out[tid] = v;
+    }
+    __syncthreads();
+}
+
 // Column-pivoted Householder QR of box blockIdx.x's m x n matrix A (row-major,
-// in place), truncated at |R_jj| <= tol |R_11|.  Thread t owns columns t,
-// t + blockDim, ... (blockDim a power of two, for the tree reductions); perm
-// receives the pivot order, kout k; nrm holds 2 n doubles of scratch per box
-// (running and reference column norms).
+// in place), truncated at |R_jj| <= tol |R_11|, in panels of B pivots.  Within
+// a panel the trailing columns are not updated: after reflectors 0 .. i - 1 of
+// the panel the current matrix is A - sum_l v_l z_l^T, where z_l[c] = beta_l
+// v_l^T (current column c) is kept per column (scratch), so pivot i needs one
+// read of the trailing rows for z_i (corrected by the panel's Gram matrix
+// v_i^T v_l) and the row j entries for the norm downdates; the panel's
+// reflectors are applied to the trailing columns once, at its end.  Per pivot
+// that reads the trailing matrix about (B + 2) / B times instead of three
+// times; the pivots, the norm downdates and the stopping rule are those of the
+// plain algorithm (in exact arithmetic the same factorization).  Thread t owns
+// columns t, t + blockDim, ... (blockDim a power of two); perm receives the
+// pivot order, kout k; scratch holds (2 + B) n doubles per box (running and
+// reference column norms, z of the panel); V (dynamic LDS) B m doubles.
+// rows per batch of a thread's column loops: their loads are issued together
+constexpr int kRowBatch = 8;
+
+template <int B>
 __global__ void __launch_bounds__(1024) k_cpqr(double* __restrict__ M, const int64_t* __restrict__ moff,
                                                const int32_t* __restrict__ nn, int m, double tol,
                                                int32_t* __restrict__ kout, int32_t* __restrict__ perm,
-                                               const int64_t* __restrict__ poff, double* __restrict__ nrmbuf) {
-    extern __shared__ double v[];   // the Householder vector, m entries
-    __shared__ double red_v[1024];
-    __shared__ int red_i[1024];
+                                               const int64_t* __restrict__ poff, double* __restrict__ scratch) {
+    extern __shared__ double V[];   // the panel's Householder vectors, V[l m + r]
+    __shared__ double wbest[16];
+    __shared__ int wbi[16];
+    __shared__ int piv_sh;
+    __shared__ double wpart[B * 16];
+    __shared__ double gsum[B];
     const int b = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
     double* __restrict__ A = M + moff[b];
     const int n = nn[b];
     int32_t* __restrict__ pm = perm + poff[b];
-    double* __restrict__ nrm = nrmbuf + 2 * poff[b];
+    double* __restrict__ nrm = scratch + (2 + B) * poff[b];
     double* __restrict__ ref = nrm + n;
+    double* __restrict__ Z = ref + n;   // Z[l n + c]
     for (int c = tid; c < n; c += nt) {
         double s = 0.0;
-        for (int i = 0; i < m; ++i) {
-            const double x = A[static_cast<int64_t>(i) * n + c];
+        const double* __restrict__ col = A + c;
+        int i = 0;
+        for (; i + kRowBatch <= m; i += kRowBatch) {
+            double a[kRowBatch];
+#pragma unroll
+            for (int u = 0; u < kRowBatch; ++u) a[u] = col[static_cast<int64_t>(i + u) * n];
+#pragma unroll
+            for (int u = 0; u < kRowBatch; ++u) s += a[u] * a[u];
+        }
+        for (; i < m; ++i) {
+            const double x = col[static_cast<int64_t>(i) * n];
             s += x * x;
         }
         nrm[c] = s;
@@ -117,97 +167,194 @@ __global__ void __launch_bounds__(1024) k_cpqr(double* __restrict__ M, const int
     const double tol_norm2 = 1.4901161193847656e-08;   // sqrt(2^-52): recompute a norm below this fraction
     const int kmax = min(m, n);
     double r11 = 0.0;
-    int k = 0;
-    for (int j = 0; j < kmax; ++j) {
-        // pivot: the largest remaining norm, the lowest index on ties
-        double best = -1.0;
-        int bi = n;
-        for (int c = j + tid; c < n; c += nt) {
-            const double x = nrm[c];
-            if (x > best) { best = x; bi = c; }
-        }
-        red_v[tid] = best;
-        red_i[tid] = bi;
-        __syncthreads();
-        for (int o = nt / 2; o > 0; o >>= 1) {
-            if (tid < o) {
-                const double x = red_v[tid + o];
-                const int xi = red_i[tid + o];
-                if (x > red_v[tid] || (x == red_v[tid] && xi < red_i[tid])) {
-                    red_v[tid] = x;
-                    red_i[tid] = xi;
+    int j = 0;
+    bool stop = false;
+    while (j < kmax && !stop) {
+        const int j0 = j;
+        const int jend = min(j0 + B, kmax);
+        for (; j < jend; ++j) {
+            const int i = j - j0;
+            // pivot: the largest remaining norm, the lowest index on ties (a
+            // total order on (norm, index): per thread, then across the wave
+            // with shuffles, then across the waves)
+            double best = -1.0;
+            int bi = n;
+            for (int c = j + tid; c < n; c += nt) {
+                const double x = nrm[c];
+                if (x > best) { best = x; bi = c; }
+            }
+            for (int o = 32; o > 0; o >>= 1) {
+                const double x = __shfl_xor(best, o);
+                const int xi = __shfl_xor(bi, o);
+                if (x > best || (x == best && xi < bi)) { best = x; bi = xi; }
+            }
+            if ((tid & 63) == 0) { wbest[tid >> 6] = best; wbi[tid >> 6] = bi; }
+            __syncthreads();
+            if (tid == 0) {
+                for (int w = 1; w < (nt >> 6); ++w)
+                    if (wbest[w] > best || (wbest[w] == best && wbi[w] < bi)) { best = wbest[w]; bi = wbi[w]; }
+                piv_sh = bi;
+            }
+            __syncthreads();
+            const int piv = piv_sh;
+            if (piv != j) {
+                for (int r = tid; r < m; r += nt) {
+                    double* row = A + static_cast<int64_t>(r) * n;
+                    const double t = row[j];
+                    row[j] = row[piv];
+                    row[piv] = t;
+                }
+                if (tid < i) {
+                    const double t = Z[tid * n + j];
+                    Z[tid * n + j] = Z[tid * n + piv];
+                    Z[tid * n + piv] = t;
+                }
+                if (tid == 0) {
+                    double t = nrm[j]; nrm[j] = nrm[piv]; nrm[piv] = t;
+                    t = ref[j]; ref[j] = ref[piv]; ref[piv] = t;
+                    const int32_t pt = pm[j]; pm[j] = pm[piv]; pm[piv] = pt;
                 }
             }
             __syncthreads();
-        }
-        const int piv = red_i[0];
-        __syncthreads();
-        if (piv != j) {
-            for (int i = tid; i < m; i += nt) {
-                double* row = A + static_cast<int64_t>(i) * n;
-                const double t = row[j];
-                row[j] = row[piv];
-                row[piv] = t;
+            // the current column j, rows j .. m - 1: the vector to reflect (into V
+            // row i); its rows j0 .. j - 1 become R entries once the pivot is taken
+            double zj[B];
+#pragma unroll
+            for (int l = 0; l < B; ++l) zj[l] = l < i ? Z[l * n + j] : 0.0;
+            double sq[B];
+#pragma unroll
+            for (int l = 0; l < B; ++l) sq[l] = 0.0;
+            for (int r = j + tid; r < m; r += nt) {
+                double x = A[static_cast<int64_t>(r) * n + j];
+#pragma unroll
+                for (int l = 0; l < B; ++l)
+                    if (l < i) x -= V[l * m + r] * zj[l];
+                V[i * m + r] = x;
+                sq[0] += x * x;
             }
-            if (tid == 0) {
-                double t = nrm[j]; nrm[j] = nrm[piv]; nrm[piv] = t;
-                t = ref[j]; ref[j] = ref[piv]; ref[piv] = t;
-                const int32_t pt = pm[j]; pm[j] = pm[piv]; pm[piv] = pt;
+            block_sums<B>(sq, 1, wpart, gsum);
+            const double alpha = sqrt(gsum[0]);
+            if (j == 0) r11 = alpha;
+            if (!(alpha > tol * r11) || alpha == 0.0) {
+                stop = true;
+                break;
             }
-        }
-        __syncthreads();
-        // alpha = |A[j:, j]|: the column's rows, one per thread, then a tree sum
-        double s = 0.0;
-        for (int i = j + tid; i < m; i += nt) {
-            const double x = A[static_cast<int64_t>(i) * n + j];
-            v[i] = x;
-            s += x * x;
-        }
-        red_v[tid] = s;
-        __syncthreads();
-        for (int o = nt / 2; o > 0; o >>= 1) {
-            if (tid < o) red_v[tid] += red_v[tid + o];
+            // Householder reflector H = I - beta v v^T with H x = rjj e1, v_j = 1
+            const double x0 = V[i * m + j];
+            const double rjj = x0 >= 0 ? -alpha : alpha;
+            const double v0 = x0 - rjj;
+            const double beta = -v0 / rjj;
+            __syncthreads();
+            for (int r = j0 + tid; r < m; r += nt) {
+                if (r < j) {
+                    // R entry: the column after the panel's reflectors so far (a stop
+                    // leaves the column to the panel's end, which applies them)
+                    double x = A[static_cast<int64_t>(r) * n + j];
+#pragma unroll
+                    for (int l = 0; l < B; ++l)
+                        if (l < i) x -= V[l * m + r] * zj[l];
+                    A[static_cast<int64_t>(r) * n + j] = x;
+                    V[i * m + r] = 0.0;
+                } else {
+                    V[i * m + r] = r == j ? 1.0 : V[i * m + r] / v0;
+                    A[static_cast<int64_t>(r) * n + j] = r == j ? rjj : 0.0;
+                }
+            }
+            __syncthreads();
+            // the panel's Gram row: g[l] = v_i^T v_l (rows >= j), l < i
+#pragma unroll
+            for (int l = 0; l < B; ++l) sq[l] = 0.0;
+            for (int r = j + tid; r < m; r += nt) {
+                const double vi = V[i * m + r];
+#pragma unroll
+                for (int l = 0; l < B; ++l)
+                    if (l < i) sq[l] += vi * V[l * m + r];
+            }
+            block_sums<B>(sq, i, wpart, gsum);
+            double g[B], vj[B];
+#pragma unroll
+            for (int l = 0; l < B; ++l) {
+                g[l] = l < i ? gsum[l] : 0.0;
+                vj[l] = l < i ? V[l * m + j] : 0.0;
+            }
+            // trailing columns: z_i[c] = beta v_i^T (A - sum_l v_l z_l^T)[:, c]
+            // and the norm downdates with the updated row j
+            for (int c = j + 1 + tid; c < n; c += nt) {
+                const double* __restrict__ col = A + c;
+                const double* __restrict__ vi = V + i * m;
+                // four partial sums (rows r = 4 q + p go to partial p), added in order
+                double dp[4] = {0.0, 0.0, 0.0, 0.0};
+                int r = j;
+                for (; r + kRowBatch <= m; r += kRowBatch) {
+                    double a[kRowBatch];
+#pragma unroll
+                    for (int u = 0; u < kRowBatch; ++u) a[u] = col[static_cast<int64_t>(r + u) * n];
+#pragma unroll
+                    for (int u = 0; u < kRowBatch; ++u) dp[u & 3] += vi[r + u] * a[u];
+                }
+                for (; r < m; ++r) dp[(r - j) & 3] += vi[r] * col[static_cast<int64_t>(r) * n];
+                double d = (dp[0] + dp[1]) + (dp[2] + dp[3]);
+                double zc[B];
+#pragma unroll
+                for (int l = 0; l < B; ++l) zc[l] = l < i ? Z[l * n + c] : 0.0;
+#pragma unroll
+                for (int l = 0; l < B; ++l) d -= g[l] * zc[l];
+                const double z = beta * d;
+                Z[i * n + c] = z;
+                double ajc = col[static_cast<int64_t>(j) * n] - z;
+#pragma unroll
+                for (int l = 0; l < B; ++l) ajc -= vj[l] * zc[l];
+                double t = nrm[c] - ajc * ajc;
+                if (t <= tol_norm2 * ref[c]) {
+                    double s2 = 0.0;
+                    for (int r = j + 1; r < m; ++r) {
+                        double x = col[static_cast<int64_t>(r) * n] - V[i * m + r] * z;
+#pragma unroll
+                        for (int l = 0; l < B; ++l)
+                            if (l < i) x -= V[l * m + r] * zc[l];
+                        s2 += x * x;
+                    }
+                    t = s2;
+                    ref[c] = t;
+                }
+                nrm[c] = t > 0.0 ? t : 0.0;
+            }
             __syncthreads();
         }
-        const double alpha = sqrt(red_v[0]);
-        __syncthreads();
-        if (j == 0) r11 = alpha;
-        if (!(alpha > tol * r11) || alpha == 0.0) break;
-        // Householder reflector H = I - beta v v^T with H x = rjj e1, v_j = 1
-        const double x0 = v[j];
-        const double rjj = x0 >= 0 ? -alpha : alpha;
-        const double v0 = x0 - rjj;
-        const double beta = -v0 / rjj;
-        __syncthreads();
-        for (int i = j + tid; i < m; i += nt) {
-            v[i] = i == j ? 1.0 : v[i] / v0;
-            A[static_cast<int64_t>(i) * n + j] = i == j ? rjj : 0.0;
+        // the panel's reflectors on the trailing columns (from j: after a stop the
+        // rejected column is trailing too), rows j0 .. m - 1
+        const int nv = j - j0;
+        if (nv > 0) {
+            for (int c = j + tid; c < n; c += nt) {
+                double zc[B];
+#pragma unroll
+                for (int l = 0; l < B; ++l) zc[l] = l < nv ? Z[l * n + c] : 0.0;
+                double* __restrict__ col = A + c;
+                int r = j0;
+                for (; r + kRowBatch <= m; r += kRowBatch) {
+                    double a[kRowBatch];
+#pragma unroll
+                    for (int u = 0; u < kRowBatch; ++u) a[u] = col[static_cast<int64_t>(r + u) * n];
+#pragma unroll
+                    for (int u = 0; u < kRowBatch; ++u) {
+#pragma unroll
+                        for (int l = 0; l < B; ++l)
+                            if (l < nv) a[u] -= V[l * m + r + u] * zc[l];
+                        col[static_cast<int64_t>(r + u) * n] = a[u];
+                    }
+                }
+                for (; r < m; ++r) {
+                    double x = col[static_cast<int64_t>(r) * n];
+#pragma unroll
+                    for (int l = 0; l < B; ++l)
+                        if (l < nv) x -= V[l * m + r] * zc[l];
+                    col[static_cast<int64_t>(r) * n] = x;
+                }
+            }
         }
         __syncthreads();
-        // the trailing columns, one per thread: w = beta v^T A[j:, c]; A[j:, c] -= w v
-        for (int c = j + 1 + tid; c < n; c += nt) {
-            double* col = A + c;
-            double w = 0.0;
-            for (int i = j; i < m; ++i) w += v[i] * col[static_cast<int64_t>(i) * n];
-            w *= beta;
-            double s2 = 0.0, cjn = 0.0;
-            for (int i = j; i < m; ++i) {
-                const double x = col[static_cast<int64_t>(i) * n] - w * v[i];
-                col[static_cast<int64_t>(i) * n] = x;
-                if (i > j) s2 += x * x;
-                else cjn = x;
-            }
-            double t = nrm[c] - cjn * cjn;
-            if (t <= tol_norm2 * ref[c]) {
-                t = s2;
-                ref[c] = t;
-            }
-            nrm[c] = t > 0.0 ? t : 0.0;
-        }
-        __syncthreads();
-        k = j + 1;
     }
-    if (tid == 0) kout[b] = k;
+    if (tid == 0) kout[b] = j;
 }
 
 // T = R11^{-1} R12 of box blockIdx.y by back substitution, one thread per column
@@ -223,7 +370,15 @@ __global__ void __launch_bounds__(256) k_tsolve(const double* __restrict__ M, co
         for (int i = k - 1; i >= 0; --i) {
             const double* row = A + static_cast<int64_t>(i) * n;
             double s = row[k + c];
-            for (int l = i + 1; l < k; ++l) s -= row[l] * Tb[static_cast<int64_t>(l) * w + c];
+            int l = i + 1;
+            for (; l + kRowBatch <= k; l += kRowBatch) {
+                double t[kRowBatch];
+#pragma unroll
+                for (int u = 0; u < kRowBatch; ++u) t[u] = Tb[static_cast<int64_t>(l + u) * w + c];
+#pragma unroll
+                for (int u = 0; u < kRowBatch; ++u) s -= row[l + u] * t[u];
+            }
+            for (; l < k; ++l) s -= row[l] * Tb[static_cast<int64_t>(l) * w + c];
             Tb[static_cast<int64_t>(i) * w + c] = s / row[i];
         }
     }
@@ -334,7 +489,13 @@ private:
         poff_.put(poff);
         double* M = M_.need(static_cast<size_t>(mo));
         int32_t* perm = perm_.need(static_cast<size_t>(po));
-        double* nrm = nrm_.need(2 * static_cast<size_t>(po));
+        // panels of up to 8 pivots: the panel's Householder vectors (panel x m
+        // doubles) stay within 40 KiB of LDS; blocks of one wave (boxes of at most
+        // 64 entries) take panels of 4 so that more of them share a CU
+        int panel = m_ <= 640 ? 8 : (m_ <= 1280 ? 4 : (m_ <= 2560 ? 2 : 1));
+        if (nmax <= 64) panel = std::min(panel, 4);
+        if (m_ > 5120) throw NotSupported("gpu_build supports proxy matrices of at most 5120 rows");
+        double* nrm = nrm_.need(static_cast<size_t>(2 + panel) * static_cast<size_t>(po));
         int32_t* kd = k_.need(nbx);
         const int gx = static_cast<int>(std::min<int64_t>(64, (static_cast<int64_t>(np_) * nmax + 255) / 256));
         hipLaunchKernelGGL(k_proxy_matrix, dim3(gx, nbx), dim3(256), 0, 0, pts_.p, p.dim, p.kind, p.kappa, idx_.p,
@@ -343,8 +504,14 @@ private:
         // one thread per column up to 1024; a power of two for the tree reductions
         int qt = 64;
         while (qt < nmax && qt < 1024) qt *= 2;
-        hipLaunchKernelGGL(k_cpqr, dim3(nbx), dim3(qt), m_ * sizeof(double), 0, M, moff_.p, nn_.p, m_, p.tol, kd,
-                           perm, poff_.p, nrm);
+        const auto qr = [&](auto kern_fn) {
+            hipLaunchKernelGGL(kern_fn, dim3(nbx), dim3(qt), static_cast<size_t>(panel) * m_ * sizeof(double), 0, M,
+                               moff_.p, nn_.p, m_, p.tol, kd, perm, poff_.p, nrm);
+        };
+        if (panel == 8) qr(k_cpqr<8>);
+        else if (panel == 4) qr(k_cpqr<4>);
+        else if (panel == 2) qr(k_cpqr<2>);
+        else qr(k_cpqr<1>);
         SKF_BHIP(hipGetLastError());
         std::vector<int32_t> kk;
         k_.get(kk, nbx);
@@ -364,10 +531,11 @@ private:
             SKF_BHIP(hipGetLastError());
         }
         std::vector<int32_t> ph;
-        std::vector<double> Th;
         perm_.get(ph, static_cast<size_t>(po));
-        T_.get(Th, static_cast<size_t>(to));
-        for (int i = 0; i < nbx; ++i) {
+        // T comes back into uninitialised host memory (every entry is written)
+        std::unique_ptr<double[]> Th(new double[static_cast<size_t>(std::max<int64_t>(to, 1))]);
+        if (to > 0) SKF_BHIP(hipMemcpy(Th.get(), T, static_cast<size_t>(to) * sizeof(double), hipMemcpyDeviceToHost));
+        parallel_for(nbx, host_threads(p.opt.num_threads), [&](int64_t i) {
             BoxSkel& s = S[boxes[i]];
             const int n = nn[i];
             s.k = kk[i];
@@ -375,10 +543,10 @@ private:
             // row-major k x (n - k) on the device, column-major in the plan
             const int64_t w = n - s.k;
             s.T.resize(static_cast<size_t>(s.k) * w);
-            const double* src = Th.data() + toff[i];
+            const double* src = Th.get() + toff[i];
             for (int64_t r = 0; r < s.k; ++r)
                 for (int64_t c = 0; c < w; ++c) s.T[r + c * s.k] = src[r * w + c];
-        }
+        }, 16);
     }
 
     int np_ = 0, m_ = 0;

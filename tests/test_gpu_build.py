@@ -130,3 +130,28 @@ def test_gpu_build_1m_cube():
     record(f"{w.name} gpu_build", build_s=t_gpu, t_tree=st["t_tree"], t_skel=st["t_skel"],
            t_skel_qr=st["t_skel_qr"], t_layout=st["t_layout"], k_max=st["k_max"], vs_o1=e1)
     assert e1 <= 1e-6
+
+
+@pytest.mark.parametrize("proxy_points", [16, 24])
+def test_gpu_build_many_proxy_rows(proxy_points):
+    """Proxy boxes of 16 and 24 points per side (1,536 and 3,456 rows): the
+    pivoted QR runs in narrower panels (2 and 1 pivots) there.  Ranks close to
+    the host build with the same proxies, accuracy against the dense sum, and the
+    GPU apply against O2 on this plan."""
+    x = workloads.uniform_points(12000, 3, 808)
+    tol = 1e-6
+    op = sk.build(x, "laplace", tol=tol, leaf_size=64, proxy_points=proxy_points, gpu_build=True)
+    op_h = sk.build(x, "laplace", tol=tol, leaf_size=64, proxy_points=proxy_points)
+    P, Ph = op.export(), op_h.export()
+    assert op.stats()["proxy_count"] == 6 * proxy_points ** 2
+    kg = np.maximum(P["rank"], 0).sum()
+    kh = np.maximum(Ph["rank"], 0).sum()
+    q = workloads.charges(x.shape[0], 1, 809)
+    u = op.apply(torch.from_numpy(q).to("cuda:0", torch.float64)).cpu().numpy()
+    tg = workloads.target_subset(x.shape[0], 1024, 810)
+    e1 = relerr(u[tg], oracle.direct(x, q, targets=tg))
+    e2 = relerr(u, oracle.apply(P, q))
+    record(f"gpu_build proxy {proxy_points}/side", ranks=kg, ranks_host=kh, vs_o1=e1, vs_o2=e2)
+    assert abs(kg - kh) <= 0.02 * kh + 8, (kg, kh)
+    assert e1 <= 10 * tol
+    assert e2 <= 1e-12
