@@ -80,7 +80,11 @@ struct Layout {
     std::vector<int32_t> pmap;      // skeleton entry -> entry in the parent's vector
     std::vector<int32_t> gather_e, gather_p;     // leaf entries and their user indices
     std::vector<int32_t> topleaf_e, topleaf_p;   // entries of top-level leaves
-    std::vector<double> T;          // interpolation matrices, column-major per box (at toff)
+    // interpolation matrices, column-major per box (at toff): the plan's own
+    // array (Tref, which outlives the layout) or, for a merged batch layout, T
+    std::vector<double> T;
+    const std::vector<double>* Tref = nullptr;
+    const std::vector<double>& Tvec() const { return Tref ? *Tref : T; }
     // device copies of T (k x m per box) and of its transpose (m x k) have their
     // columns padded to kTPad entries, so no 128-byte line is shared by two row
     // groups of a transfer; tpad / ttpad are the padded per-box offsets

@@ -130,7 +130,7 @@ static std::vector<TT> padded_t(const Layout& L, bool transpose) {
     for (int b = 0; b < L.n_boxes; ++b) {
         const int64_t k = L.kb[b], m = L.nb[b] - L.kb[b];
         if (k <= 0 || m <= 0) continue;
-        const double* src = L.T.data() + L.toff[b];
+        const double* src = L.Tvec().data() + L.toff[b];
         if (!transpose) {
             const int64_t ld = pad_ld(k);
             TT* dst = out.data() + L.tpad[b];

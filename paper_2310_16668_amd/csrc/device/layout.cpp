@@ -34,13 +34,9 @@
 
 namespace skelfmm {
 
-// Geometry for the expanded |d|^2 of the pair kernel.  With coordinates taken
-// relative to an origin o, |t - s|^2 = |t'|^2 + |s'|^2 - 2 t'.s' evaluated in
-// float64 has an absolute error below 20 u R^2 (u = 2^-53, R bounding |t'| and
-// |s'|), i.e. a relative error below 20 u (R / d)^2 for a pair at distance
-// >= d.  For R <= 1024 d that is below 2.4e-9, far under the float32 rounding
-// that follows; the build marks an item expanded only then, with d a lower
-// bound of the distance between any two distinct entries of its boxes.
+// Geometry for the float32 evaluation of the pair kernel (sym_flags below): a
+// lower bound d of the distance between any two distinct entries of a box, and
+// the box's centre and radius (the reach R of an item from its origin).
 //
 // Lower bound of the nearest-neighbor distance of every point: a leaf's points
 // are compared with the points of the leaf itself, its colleague leaves, its
@@ -70,12 +66,31 @@ static void box_geometry(const Plan& p, Layout& L) {
             if (p.is_leaf[p.coll_idx[x]]) cand.push_back(p.coll_idx[x]);
         for (int x = p.coarse_ptr[b]; x < p.coarse_ptr[b + 1]; ++x) cand.push_back(p.coarse_idx[x]);
         for (int x = p.fine_ptr[b]; x < p.fine_ptr[b + 1]; ++x) cand.push_back(p.fine_idx[x]);
+        // the candidates' boxes: a box farther from the point than the best
+        // distance so far cannot hold a nearer point
+        std::vector<double> lo(cand.size() * 3), hi(cand.size() * 3);
+        for (size_t q = 0; q < cand.size(); ++q) {
+            const double side = std::ldexp(p.root_side, -p.level[cand[q]]);
+            for (int d = 0; d < dim; ++d) {
+                lo[3 * q + d] = p.root_lo[d] + p.coord[3 * cand[q] + d] * side;
+                hi[3 * q + d] = lo[3 * q + d] + side;
+            }
+        }
         for (int64_t i = p.idx_ptr[b]; i < p.idx_ptr[b + 1]; ++i) {
             const int64_t a = p.idx[i];
             double m = half * half;
-            for (int c : cand)
+            for (size_t q = 0; q < cand.size(); ++q) {
+                double g2 = 0.0;
+                for (int d = 0; d < dim; ++d) {
+                    const double x = p.pts[a * dim + d];
+                    const double t = x < lo[3 * q + d] ? lo[3 * q + d] - x : (x > hi[3 * q + d] ? x - hi[3 * q + d] : 0.0);
+                    g2 += t * t;
+                }
+                if (g2 >= m) continue;
+                const int c = cand[q];
                 for (int64_t j = p.idx_ptr[c]; j < p.idx_ptr[c + 1]; ++j)
                     if (p.idx[j] != a) m = std::min(m, dist2(a, p.idx[j]));
+            }
             nn[a] = std::sqrt(m);
         }
     }, 16);
@@ -105,9 +120,10 @@ static void box_geometry(const Plan& p, Layout& L) {
 
 // R / d for an item of boxes i != j: R the reach of the two boxes from the
 // origin (the first entry of the source box j), d their smallest point spacing.
-// The expanded |d|^2 has terms of about R^2, so its rounding error relative to
-// |d|^2 >= d^2 is a few units of 2^-53 (R/d)^2: with R <= 4096 d at most about
-// 2^-26, a quarter of the float32 rounding of the kernel value.
+// The expanded |d|^2 = |t'|^2 + |s'|^2 - 2 t'.s' in float64 has terms of about
+// R^2, so its absolute error is below 20 u R^2 (u = 2^-53) and its error
+// relative to |d|^2 >= d^2 below 20 u (R/d)^2: with R <= 4096 d about 3.7e-8,
+// 1.9e-8 on the kernel value, a third of the float32 rounding that follows.
 static double reach_ratio(const Layout& L, int bi, int bj) {
     if (L.nb[bj] == 0 || L.dmin.empty()) return std::numeric_limits<double>::infinity();
     // the expanded records of box j are relative to its first entry
@@ -221,7 +237,7 @@ Layout make_layout(const Plan& p, bool keep_transparent, int tile) {
         for (int i = 0; i < L.kb[b]; ++i)
             L.pmap[L.hoff[b] + i] = static_cast<int32_t>(L.voff[par] + inv[off + i]);
     }
-    L.T = p.T;
+    L.Tref = &p.T;
 
     // near-field segments per target box
     auto transparent = [&](int b) { return L.kb[b] == L.nb[b]; };
@@ -466,7 +482,7 @@ Layout merge_layouts(const std::vector<const Layout*>& ls, std::vector<int64_t>&
         box_base[i + 1] = box_base[i] + L.n_boxes;
         entry_base[i + 1] = entry_base[i] + L.n_entries;
         hbase[i + 1] = hbase[i] + L.n_hentries;
-        tbase[i + 1] = tbase[i] + static_cast<int64_t>(L.T.size());
+        tbase[i + 1] = tbase[i] + static_cast<int64_t>(L.Tvec().size());
         M.n_points += L.n_points;
         M.max_level = std::max(M.max_level, L.max_level);
         M.top = std::min(M.top, L.top);
@@ -532,7 +548,7 @@ Layout merge_layouts(const std::vector<const Layout*>& ls, std::vector<int64_t>&
         M.X.insert(M.X.end(), L.X.begin(), L.X.end());
         M.perm.insert(M.perm.end(), L.perm.begin(), L.perm.end());
         for (int32_t v : L.pmap) M.pmap.push_back(static_cast<int32_t>(v + entry_base[i]));
-        M.T.insert(M.T.end(), L.T.begin(), L.T.end());
+        M.T.insert(M.T.end(), L.Tvec().begin(), L.Tvec().end());
         for (size_t j = 0; j < L.gather_e.size(); ++j) {
             M.gather_e.push_back(static_cast<int32_t>(L.gather_e[j] + entry_base[i]));
             M.gather_p.push_back(L.gather_p[j]);
