@@ -458,8 +458,11 @@ def test_fused_forward_adjoint(name):
             op.set_targets_per_lane(tpl)
             u1, w1 = host(op.apply(qd)), host(op.apply_adjoint(vd))
         else:
+            # the autotuned two-column shape, against separate applies at that shape
             tpl = op.autotune_fwd_adj()["targets_per_lane"]
             assert tpl in (1, 2, 3, 4)
+            op.set_targets_per_lane(tpl)
+            u1, w1 = host(op.apply(qd)), host(op.apply_adjoint(vd))
         u, w = op.apply_fwd_adj(qd, vd)
         u, w = host(u).astype(up), host(w).astype(up)
         e_single = max(relerr(u, u1.astype(up)), relerr(w, w1.astype(up)))
