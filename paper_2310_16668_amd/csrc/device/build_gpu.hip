@@ -532,22 +532,64 @@ private:
         }
         std::vector<int32_t> ph;
         perm_.get(ph, static_cast<size_t>(po));
-        // T comes back into uninitialised host memory (every entry is written)
-        std::unique_ptr<double[]> Th(new double[static_cast<size_t>(std::max<int64_t>(to, 1))]);
-        if (to > 0) SKF_BHIP(hipMemcpy(Th.get(), T, static_cast<size_t>(to) * sizeof(double), hipMemcpyDeviceToHost));
-        parallel_for(nbx, host_threads(p.opt.num_threads), [&](int64_t i) {
-            BoxSkel& s = S[boxes[i]];
-            const int n = nn[i];
-            s.k = kk[i];
-            s.pos.assign(ph.begin() + poff[i], ph.begin() + poff[i] + n);
-            // row-major k x (n - k) on the device, column-major in the plan
-            const int64_t w = n - s.k;
-            s.T.resize(static_cast<size_t>(s.k) * w);
-            const double* src = Th.get() + toff[i];
-            for (int64_t r = 0; r < s.k; ++r)
-                for (int64_t c = 0; c < w; ++c) s.T[r + c * s.k] = src[r * w + c];
-        }, 16);
+        // T comes back through a pinned staging buffer, a run of whole boxes at a
+        // time (a pageable copy of the level's T ran at a fraction of the link)
+        const int threads = host_threads(p.opt.num_threads);
+        const auto end_of = [&](int i) { return i + 1 < nbx ? toff[i + 1] : to; };   // end of box i's T
+        for (int i0 = 0; i0 < nbx;) {
+            // boxes i0 .. i1 - 1: as many as fit the staging buffer (at least one)
+            int i1 = i0 + 1;
+            while (i1 < nbx && end_of(i1) - toff[i0] <= static_cast<int64_t>(kStageDoubles)) ++i1;
+            const int64_t t0 = toff[i0], t1 = end_of(i1 - 1);
+            const double* src0 = nullptr;
+            std::unique_ptr<double[]> big;
+            if (t1 - t0 <= static_cast<int64_t>(kStageDoubles)) {
+                double* st = stage();
+                if (t1 > t0)
+                    SKF_BHIP(hipMemcpy(st, T + t0, static_cast<size_t>(t1 - t0) * sizeof(double),
+                                       hipMemcpyDeviceToHost));
+                src0 = st;
+            } else {   // one box larger than the staging buffer
+                big.reset(new double[static_cast<size_t>(t1 - t0)]);
+                SKF_BHIP(hipMemcpy(big.get(), T + t0, static_cast<size_t>(t1 - t0) * sizeof(double),
+                                   hipMemcpyDeviceToHost));
+                src0 = big.get();
+            }
+            parallel_for(i1 - i0, threads, [&](int64_t q) {
+                const int i = i0 + static_cast<int>(q);
+                BoxSkel& s = S[boxes[i]];
+                const int n = nn[i];
+                s.k = kk[i];
+                s.pos.assign(ph.begin() + poff[i], ph.begin() + poff[i] + n);
+                // row-major k x (n - k) on the device, column-major in the plan
+                const int64_t w = n - s.k;
+                s.T.resize(static_cast<size_t>(s.k) * w);
+                const double* src = src0 + (toff[i] - t0);
+                for (int64_t r = 0; r < s.k; ++r)
+                    for (int64_t c = 0; c < w; ++c) s.T[r + c * s.k] = src[r * w + c];
+            }, 16);
+            i0 = i1;
+        }
     }
+
+    // the pinned staging buffer, allocated on first use and kept for the build
+    static constexpr size_t kStageDoubles = size_t(1) << 25;   // 256 MiB
+    double* stage() {
+        if (!stage_) {
+            void* h = nullptr;
+            SKF_BHIP(hipHostMalloc(&h, kStageDoubles * sizeof(double), hipHostMallocDefault));
+            stage_ = static_cast<double*>(h);
+        }
+        return stage_;
+    }
+    double* stage_ = nullptr;
+
+public:
+    ~DeviceSkeletonizer() override {
+        if (stage_) (void)hipHostFree(stage_);
+    }
+
+private:
 
     int np_ = 0, m_ = 0;
     double half_ = 0.0;
