@@ -535,6 +535,9 @@ private:
         // T comes back through a pinned staging buffer, a run of whole boxes at a
         // time (a pageable copy of the level's T ran at a fraction of the link)
         const int threads = host_threads(p.opt.num_threads);
+        // the batch's T, column-major per box, stays here until the plan copies it
+        blocks_.emplace_back(new double[static_cast<size_t>(std::max<int64_t>(to, 1))]);
+        double* const blk = blocks_.back().get();
         const auto end_of = [&](int i) { return i + 1 < nbx ? toff[i + 1] : to; };   // end of box i's T
         for (int i0 = 0; i0 < nbx;) {
             // boxes i0 .. i1 - 1: as many as fit the staging buffer (at least one)
@@ -563,10 +566,13 @@ private:
                 s.pos.assign(ph.begin() + poff[i], ph.begin() + poff[i] + n);
                 // row-major k x (n - k) on the device, column-major in the plan
                 const int64_t w = n - s.k;
-                s.T.resize(static_cast<size_t>(s.k) * w);
                 const double* src = src0 + (toff[i] - t0);
+                double* dst = blk + toff[i];
                 for (int64_t r = 0; r < s.k; ++r)
-                    for (int64_t c = 0; c < w; ++c) s.T[r + c * s.k] = src[r * w + c];
+                    for (int64_t c = 0; c < w; ++c) dst[r + c * s.k] = src[r * w + c];
+                s.T.clear();
+                s.Tsrc = dst;
+                s.Tn = s.k * w;
             }, 16);
             i0 = i1;
         }
@@ -583,6 +589,7 @@ private:
         return stage_;
     }
     double* stage_ = nullptr;
+    std::vector<std::unique_ptr<double[]>> blocks_;
 
 public:
     ~DeviceSkeletonizer() override {

@@ -82,9 +82,9 @@ struct Layout {
     std::vector<int32_t> topleaf_e, topleaf_p;   // entries of top-level leaves
     // interpolation matrices, column-major per box (at toff): the plan's own
     // array (Tref, which outlives the layout) or, for a merged batch layout, T
-    std::vector<double> T;
-    const std::vector<double>* Tref = nullptr;
-    const std::vector<double>& Tvec() const { return Tref ? *Tref : T; }
+    DoubleArray T;
+    const DoubleArray* Tref = nullptr;
+    const DoubleArray& Tvec() const { return Tref ? *Tref : T; }
     // device copies of T (k x m per box) and of its transpose (m x k) have their
     // columns padded to kTPad entries, so no 128-byte line is shared by two row
     // groups of a transfer; tpad / ttpad are the padded per-box offsets

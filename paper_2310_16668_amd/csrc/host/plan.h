@@ -5,10 +5,35 @@
 #pragma once
 
 #include <cstdint>
+#include <memory>
 #include <string>
+#include <utility>
 #include <vector>
 
 namespace skelfmm {
+
+// An allocator whose value-less construct leaves doubles uninitialised, so a
+// large array that is written in full right after resize() is not zero-filled
+// first.
+template <class T>
+struct DefaultInitAlloc : std::allocator<T> {
+    template <class U>
+    struct rebind {
+        using other = DefaultInitAlloc<U>;
+    };
+    DefaultInitAlloc() = default;
+    template <class U>
+    DefaultInitAlloc(const DefaultInitAlloc<U>&) noexcept {}
+    template <class U>
+    void construct(U* p) noexcept {
+        ::new (static_cast<void*>(p)) U;
+    }
+    template <class U, class... Args>
+    void construct(U* p, Args&&... args) {
+        ::new (static_cast<void*>(p)) U(std::forward<Args>(args)...);
+    }
+};
+using DoubleArray = std::vector<double, DefaultInitAlloc<double>>;
 
 struct BuildOptions {
     int proxy_shape = 0;       // 0 default (2D circle, 3D Chebyshev box), 1 box, 2 circle (2D)
@@ -49,7 +74,7 @@ struct Plan {
     std::vector<int32_t> rank;                 // k per box, -1 for boxes at or above the top level
     std::vector<int64_t> pos;                  // per box [sk positions | rd positions] in natural order
     std::vector<int64_t> T_ptr;                // offsets into T (n_boxes + 1)
-    std::vector<double> T;                     // column-major k x (n - k) per box
+    DoubleArray T;                             // column-major k x (n - k) per box
 
     // statistics
     double t_tree = 0.0, t_skel = 0.0;

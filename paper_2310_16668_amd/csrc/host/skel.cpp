@@ -256,7 +256,7 @@ void skeletonize(Plan& p, const std::vector<int64_t>& order, const std::vector<i
     p.k_max = 0;
     for (int b = 0; b < nb; ++b) {
         p.idx_ptr[b + 1] = p.idx_ptr[b] + static_cast<int64_t>(S[b].idx.size());
-        p.T_ptr[b + 1] = p.T_ptr[b] + static_cast<int64_t>(S[b].T.size());
+        p.T_ptr[b + 1] = p.T_ptr[b] + S[b].t_size();
         if (p.level[b] > top) { p.rank[b] = S[b].k; p.k_max = std::max(p.k_max, S[b].k); }
     }
     p.idx.resize(p.idx_ptr[nb]);
@@ -265,7 +265,8 @@ void skeletonize(Plan& p, const std::vector<int64_t>& order, const std::vector<i
     parallel_for(nb, threads, [&](int64_t b) {
         std::copy(S[b].idx.begin(), S[b].idx.end(), p.idx.begin() + p.idx_ptr[b]);
         std::copy(S[b].pos.begin(), S[b].pos.end(), p.pos.begin() + p.idx_ptr[b]);
-        std::copy(S[b].T.begin(), S[b].T.end(), p.T.begin() + p.T_ptr[b]);
+        if (S[b].Tsrc) std::copy(S[b].Tsrc, S[b].Tsrc + S[b].Tn, p.T.begin() + p.T_ptr[b]);
+        else std::copy(S[b].T.begin(), S[b].T.end(), p.T.begin() + p.T_ptr[b]);
     }, 64);
     {
         std::vector<double> Y;

@@ -16,6 +16,11 @@ struct BoxSkel {
     int k = 0;                    // skeleton size
     std::vector<int64_t> pos;     // [skeleton | redundant] positions within idx
     std::vector<double> T;        // k x (n - k), column-major
+    // or, from the device build, the same k x (n - k) values held by the level
+    // skeletonizer (valid while it lives): Tn entries at Tsrc
+    const double* Tsrc = nullptr;
+    int64_t Tn = 0;
+    int64_t t_size() const { return Tsrc ? Tn : static_cast<int64_t>(T.size()); }
 };
 
 // The proxy surface of a box of side a centred at c is c + h U_r with
