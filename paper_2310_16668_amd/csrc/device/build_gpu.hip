@@ -429,15 +429,17 @@ public:
     }
 
     void level(const Plan& p, int b0, int b1, std::vector<BoxSkel>& S) override {
-        // boxes in batches whose proxy matrices fit the budget
-        const size_t budget = size_t(1) << 29;   // doubles (4 GiB)
+        // boxes in batches whose proxy matrices fit the budget, at most 65,535 per
+        // batch (the grid's y extent of the per-box launches)
+        const size_t budget = size_t(1) << 30;   // doubles (8 GiB): a level of the 1M cube in one launch
+        const int max_boxes = 65535;
         int a = b0;
         while (a < b1) {
             size_t need = 0;
             int e = a;
             while (e < b1) {
                 const size_t add = static_cast<size_t>(m_) * S[e].idx.size();
-                if (e > a && need + add > budget) break;
+                if (e > a && (need + add > budget || e - a >= max_boxes)) break;
                 need += add;
                 ++e;
             }

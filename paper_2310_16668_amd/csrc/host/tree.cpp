@@ -17,6 +17,7 @@
 #include <stdexcept>
 #include <unordered_map>
 
+#include "parallel.h"
 #include "plan.h"
 
 namespace skelfmm {
@@ -133,15 +134,28 @@ struct Builder {
         const double scale = std::ldexp(1.0, D) / side;
         const int32_t cmax = (1 << D) - 1;
         std::vector<std::pair<uint64_t, int64_t>> kv(n);
-        for (int64_t i = 0; i < n; ++i) {
+        const int threads = host_threads(p.opt.num_threads);
+        parallel_for(n, threads, [&](int64_t i) {
             int32_t c[3] = {0, 0, 0};
             for (int d = 0; d < dim; ++d) {
                 double f = std::floor((p.pts[i * dim + d] - p.root_lo[d]) * scale);
                 c[d] = static_cast<int32_t>(std::min<double>(std::max<double>(f, 0.0), cmax));
             }
             kv[i] = {morton(dim, c), i};
+        }, 4096);
+        // sorted runs in parallel, then merged pairwise (the order is total: the
+        // user index breaks ties, so the result is that of one sort)
+        const int64_t runs = std::max<int64_t>(1, std::min<int64_t>(threads, n / 65536));
+        std::vector<int64_t> bnd(runs + 1);
+        for (int64_t r = 0; r <= runs; ++r) bnd[r] = n * r / runs;
+        parallel_for(runs, threads, [&](int64_t r) { std::sort(kv.begin() + bnd[r], kv.begin() + bnd[r + 1]); });
+        for (int64_t width = 1; width < runs; width *= 2) {
+            const int64_t pairs = (runs + 2 * width - 1) / (2 * width);
+            parallel_for(pairs, threads, [&](int64_t q) {
+                const int64_t a = 2 * width * q, m = std::min(a + width, runs), e = std::min(a + 2 * width, runs);
+                if (m < e) std::inplace_merge(kv.begin() + bnd[a], kv.begin() + bnd[m], kv.begin() + bnd[e]);
+            });
         }
-        std::sort(kv.begin(), kv.end());
         pkey.resize(n);
         order.resize(n);
         for (int64_t i = 0; i < n; ++i) { pkey[i] = kv[i].first; order[i] = kv[i].second; }
