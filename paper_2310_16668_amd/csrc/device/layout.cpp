@@ -195,7 +195,18 @@ Layout make_layout(const Plan& p, bool keep_transparent, int tile) {
     // entry coordinates (root-centred) and leaf permutation
     L.X.assign(static_cast<size_t>(e) * 4, 0.0);
     L.perm.assign(e, -1);
+    // leaf entries in box order: each box's first slot in the gather lists
+    std::vector<int64_t> goff(nb + 1, 0), tgoff(nb + 1, 0);
     for (int b = 0; b < nb; ++b) {
+        goff[b + 1] = goff[b] + (p.is_leaf[b] ? L.nb[b] : 0);
+        tgoff[b + 1] = tgoff[b] + (p.is_leaf[b] && p.level[b] == p.top_level ? L.nb[b] : 0);
+    }
+    L.gather_e.resize(goff[nb]);
+    L.gather_p.resize(goff[nb]);
+    L.topleaf_e.resize(tgoff[nb]);
+    L.topleaf_p.resize(tgoff[nb]);
+    parallel_for(nb, host_threads(p.opt.num_threads), [&](int64_t bb) {
+        const int b = static_cast<int>(bb);
         const int64_t n = L.nb[b];
         const int64_t* ix = &p.idx[p.idx_ptr[b]];
         const int64_t* ps = &p.pos[p.idx_ptr[b]];
@@ -203,19 +214,17 @@ Layout make_layout(const Plan& p, bool keep_transparent, int tile) {
             const int64_t pt = ix[ps[i]];
             double* x = &L.X[static_cast<size_t>(L.voff[b] + i) * 4];
             for (int d = 0; d < p.dim; ++d) x[d] = p.pts[pt * p.dim + d] - L.center[d];
-            if (p.is_leaf[b]) L.perm[L.voff[b] + i] = static_cast<int32_t>(pt);
-        }
-        if (p.is_leaf[b]) {
-            for (int64_t i = 0; i < n; ++i) {
-                L.gather_e.push_back(static_cast<int32_t>(L.voff[b] + i));
-                L.gather_p.push_back(static_cast<int32_t>(ix[ps[i]]));
+            if (p.is_leaf[b]) {
+                L.perm[L.voff[b] + i] = static_cast<int32_t>(pt);
+                L.gather_e[goff[b] + i] = static_cast<int32_t>(L.voff[b] + i);
+                L.gather_p[goff[b] + i] = static_cast<int32_t>(pt);
                 if (p.level[b] == p.top_level) {
-                    L.topleaf_e.push_back(static_cast<int32_t>(L.voff[b] + i));
-                    L.topleaf_p.push_back(static_cast<int32_t>(ix[ps[i]]));
+                    L.topleaf_e[tgoff[b] + i] = static_cast<int32_t>(L.voff[b] + i);
+                    L.topleaf_p[tgoff[b] + i] = static_cast<int32_t>(pt);
                 }
             }
         }
-    }
+    }, 64);
     if (static_cast<int64_t>(L.gather_e.size()) != p.n) throw std::runtime_error("leaves do not partition the points");
 
     // parent slots of skeleton entries
