@@ -57,7 +57,6 @@ __global__ void __launch_bounds__(256) k_proxy_matrix(const double* __restrict__
                                                       const int64_t* __restrict__ moff, double* __restrict__ M) {
     const int b = blockIdx.y;
     const int n = nn[b];
-    const int m = kind == 1 ? 2 * np : np;
     const double* ch = ctrh + 4 * b;
     const int64_t total = static_cast<int64_t>(np) * n;
     for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < total;

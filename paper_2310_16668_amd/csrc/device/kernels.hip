@@ -1954,7 +1954,6 @@ __global__ void __launch_bounds__(256) k_near_mr(const Task* __restrict__ tasks,
                                                  const typename P::Vt* __restrict__ Qh,
                                                  typename P::Vt* __restrict__ U, typename P::Vt* __restrict__ Uh,
                                                  typename P::Rt kappa, double scale) {
-    using R = typename P::Rt;
     using V = typename P::Vt;
     constexpr int nv = P::nv;
     constexpr int NW = NR * nv;
