@@ -84,12 +84,12 @@ FLOPS_PER_HELM_SYM_SKEL_PAIR = 16
 # measured on (first 16 hex digits of the sha256 of the pair kernel's section of
 # kernels.hip, pair_kernel_digest).
 NEAR_TRAFFIC = {
-    "f32": {"kernel": "k_near_sym", "kernels_sha256": "12d8a2c0cb8f5b31",
-            "bytes_by_tpl": {1: 1.0776e+10 + 2.0506e+09, 2: 6.0447e+09 + 1.2162e+09, 3: 4.6175e+09 + 9.4872e+08, 4: 3.2833e+09 + 7.4526e+08}},
-    "f32_fused": {"kernel": "k_near_sym", "kernels_sha256": "12d8a2c0cb8f5b31",
-                  "bytes_by_tpl": {1: 1.4171e+10 + 4.0734e+09, 2: 7.5270e+09 + 2.4532e+09, 3: 5.6405e+09 + 1.9096e+09, 4: 3.9165e+09 + 1.4802e+09}},
-    "f64": {"kernel": "k_near_sym", "kernels_sha256": "12d8a2c0cb8f5b31",
-            "bytes_by_tpl": {1: 1.1544e+10 + 2.0484e+09, 2: 6.3888e+09 + 1.2125e+09, 3: 4.8139e+09 + 9.4521e+08, 4: 3.3717e+09 + 7.4386e+08}},
+    "f32": {"kernel": "k_near_sym", "kernels_sha256": "3c712fe22d9617b0",
+            "bytes_by_tpl": {1: 1.0774e+10 + 2.0505e+09, 2: 6.0437e+09 + 1.2162e+09, 3: 4.6171e+09 + 9.4871e+08, 4: 3.2840e+09 + 7.4526e+08}},
+    "f32_fused": {"kernel": "k_near_sym", "kernels_sha256": "3c712fe22d9617b0",
+                  "bytes_by_tpl": {1: 1.4166e+10 + 4.0731e+09, 2: 7.5355e+09 + 2.4531e+09, 3: 5.6397e+09 + 1.9096e+09, 4: 3.9151e+09 + 1.4802e+09}},
+    "f64": {"kernel": "k_near_sym", "kernels_sha256": "3c712fe22d9617b0",
+            "bytes_by_tpl": {1: 1.1541e+10 + 2.0484e+09, 2: 6.3858e+09 + 1.2125e+09, 3: 4.8105e+09 + 9.4521e+08, 4: 3.3710e+09 + 7.4385e+08}},
 }
 
 

@@ -1016,14 +1016,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sym_wa
 // acc + p[0] + p[ld] + ... + p[(rows - 1) ld], added in row order; the loads of
 // four rows are issued together.
 __device__ __forceinline__ double add_rows(double acc, const double* __restrict__ p, int rows, int ld) {
+    constexpr int kRows = 8;
     int i = 0;
-    for (; i + 4 <= rows; i += 4) {
-        const double a0 = p[static_cast<int64_t>(i) * ld], a1 = p[static_cast<int64_t>(i + 1) * ld];
-        const double a2 = p[static_cast<int64_t>(i + 2) * ld], a3 = p[static_cast<int64_t>(i + 3) * ld];
-        acc += a0;
-        acc += a1;
-        acc += a2;
-        acc += a3;
+    for (; i + kRows <= rows; i += kRows) {
+        double a[kRows];
+#pragma unroll
+        for (int u = 0; u < kRows; ++u) a[u] = p[static_cast<int64_t>(i + u) * ld];
+#pragma unroll
+        for (int u = 0; u < kRows; ++u) acc += a[u];
     }
     for (; i < rows; ++i) acc += p[static_cast<int64_t>(i) * ld];
     return acc;
